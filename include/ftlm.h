@@ -1,0 +1,237 @@
+/*
+ * ftlm.h -- C ABI of the MI355X symmetry-adapted finite-temperature Lanczos
+ * library (spin-s Heisenberg clusters with site-permutation symmetry).
+ *
+ * The operations follow the paper "GPU-accelerated finite-temperature Lanczos
+ * method for Heisenberg spin systems with non-Abelian permutation symmetries":
+ *   - H of Eq. (1) with the spin-flip coefficients of Eq. (3); states are the
+ *     integer labels n = sum_k (m_k + s) d^k of Eq. (2), d = 2s + 1.
+ *   - One (M, Gamma, row) block of the symmetry-adapted basis of Eq. (12):
+ *     orbit representatives (smallest label of each orbit, Section 2.3),
+ *     stabilizers (Eq. 8), n_Gamma and V_r (Eqs. 10-11), D = sum n_Gamma (Eq. 13).
+ *   - Matrix-free H action through the matrix element of Eq. (15) in gather
+ *     form, diagonal of Eq. (16).
+ *   - Batched Lanczos chains with start vectors per chain (Section 2.2, 3),
+ *     host FP64 tridiagonal Ritz data, thermal sums of Eqs. (4)-(7), (14).
+ *
+ * Conventions shared by every call
+ *   status: 0 = FTLM_OK, negative = error; ftlm_last_error() returns a
+ *           thread-local description of the last error on the calling thread.
+ *   group elements: the closure of the generators sorted lexicographically by
+ *           permutation image array (identity = element 0).  A permutation
+ *           array p means: the spin on site k moves to site p[k]; products
+ *           compose as (gh)[k] = g[h[k]].
+ *   irreps: ordered by dimension, then by the character vector (classes in
+ *           the order element order, class size, smallest member) descending.
+ *   block rows: representatives in ascending label order, then k = 0..n-1.
+ *   vectors: row-major D x ld arrays on the device, column v = chain / vector
+ *           (the fastest index), v < nvec <= ld.
+ *   streams: hipStream_t passed as void*; NULL = the null stream.
+ *   ownership: the library owns groups, sectors and blocks (device tables
+ *           included) until the matching *_free; the caller owns every
+ *           pointer it passes in.  Objects are not thread-safe; a built block
+ *           may be read concurrently by apply calls on several streams.
+ */
+#ifndef FTLM_H
+#define FTLM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum ftlm_status {
+  FTLM_OK = 0,
+  FTLM_ERR_INVALID_ARG = -1,
+  FTLM_ERR_NOT_A_PERMUTATION = -2,
+  FTLM_ERR_GROUP_TOO_LARGE = -3,
+  FTLM_ERR_BONDS_NOT_INVARIANT = -4,
+  FTLM_ERR_IRREP_OUT_OF_RANGE = -5,
+  FTLM_ERR_ROW_OUT_OF_RANGE = -6,
+  FTLM_ERR_DIM_GT_12 = -7,
+  FTLM_ERR_COMPLEX_IRREP_UNSUPPORTED = -8,
+  FTLM_ERR_OUT_OF_MEMORY = -9,
+  FTLM_ERR_HIP = -10,
+  FTLM_ERR_BAD_RHO = -11,
+  FTLM_ERR_UNSUPPORTED = -12,
+  FTLM_ERR_IRREPS_FAILED = -13,
+  FTLM_ERR_CANCELLED = -14,
+  FTLM_ERR_QUEUE_FULL = -15
+};
+
+enum ftlm_dtype { FTLM_F64 = 0, FTLM_F32 = 1 };
+enum ftlm_dist { FTLM_RADEMACHER = 0, FTLM_GAUSSIAN = 1 };
+enum ftlm_hv_mode { FTLM_HV_AUTO = 0, FTLM_HV_ENTRIES = 1, FTLM_HV_ONTHEFLY = 2 };
+
+/* Cluster graph of Eq. (1): N sites of spin s = two_s/2, nbonds bonds
+ * (bonds[2b], bonds[2b+1]) with couplings J[b] (J == NULL: all 1). */
+typedef struct ftlm_cluster {
+  int32_t N;
+  int32_t two_s;
+  int32_t nbonds;
+  const int32_t* bonds;
+  const double* J;
+} ftlm_cluster;
+
+/* Build options (every field 0 / NULL = default). */
+typedef struct ftlm_opts {
+  int32_t hv_mode;          /* enum ftlm_hv_mode; AUTO keeps an entry table when it fits */
+  int32_t reserved0;
+  const double* user_rho;   /* optional irrep matrices, |G| x d x d row-major, element
+                               order as above; replaces the library's own irrep */
+  int32_t user_rho_dim;     /* d of user_rho (0 = none) */
+  int32_t reserved1;
+  int64_t hbm_limit_bytes;  /* 0 = no limit; builds that would exceed it fail with
+                               FTLM_ERR_OUT_OF_MEMORY before allocating */
+  int64_t reserved[6];
+} ftlm_opts;
+
+typedef struct ftlm_group ftlm_group;
+typedef struct ftlm_sector ftlm_sector;
+typedef struct ftlm_block ftlm_block;
+
+/* ---------------------------------------------------------------- group ---
+ * Closure of ngens site permutations (ngens x N int32, row-major) into the
+ * full group (Section 3: closure, irreps from the regular representation,
+ * real orthogonal form for Frobenius-Schur indicator +1, verification of
+ * unitarity, character orthogonality and sum d^2 = |G|).  Host only.
+ * Errors: NOT_A_PERMUTATION, GROUP_TOO_LARGE (|G| > 65535), IRREPS_FAILED.
+ * Irreps are computed for |G| <= 1024; a group with irreps that are not of
+ * real type builds, but its irreps report COMPLEX_IRREP_UNSUPPORTED. */
+int ftlm_group_create(int32_t N, const int32_t* gens, int32_t ngens, ftlm_group** out);
+/* |G|, number of irreps, number of conjugacy classes, number of sites. */
+int ftlm_group_info(const ftlm_group* g, int32_t* order, int32_t* n_irreps, int32_t* n_classes,
+                    int32_t* N);
+/* Permutation table, |G| x N int32 (host array owned by the caller). */
+int ftlm_group_elements(const ftlm_group* g, int32_t* perms);
+/* Per irrep: dimension, Frobenius-Schur indicator, characters by class
+ * (n_irreps x n_classes, row-major) and the class of every element (|G|).
+ * Any pointer may be NULL.  Also the largest verification residual. */
+int ftlm_group_irreps(const ftlm_group* g, int32_t* dims, int32_t* indicators, double* chars,
+                      int32_t* class_of, double* max_residual);
+/* Irrep matrices rho(g), |G| x d x d row-major. */
+int ftlm_group_rho(const ftlm_group* g, int32_t irrep, double* rho);
+void ftlm_group_free(ftlm_group* g);
+
+/* --------------------------------------------------------------- sector ---
+ * Irreducible-representation-independent part of one magnetization sector
+ * (Section 3, "performed only once per magnetization sector"): all orbit
+ * representatives of the M = two_M/2 sector (ascending), their stabilizers,
+ * the rank lookup (sector rank of Ref. [36] + a bitmap over ranks), the
+ * diagonal energies of Eq. (16) and, in entry mode, the table of one entry
+ * per admissible (representative, bond, sign) flip: target representative,
+ * connecting element h with U(h) a = min O(a) (smallest index among
+ * minimisers) and the flip.  Built on the device with the GPU kernels.
+ * Errors: INVALID_ARG (N*bits > 64, bad bonds/spin), BONDS_NOT_INVARIANT,
+ * OUT_OF_MEMORY, HIP.  A sector with no states is legal (n_reps = 0). */
+int ftlm_sector_create(const ftlm_cluster* cl, const ftlm_group* g, int32_t two_M,
+                       const ftlm_opts* opts, ftlm_sector** out);
+
+typedef struct ftlm_sector_info {
+  uint64_t D_M;          /* sector dimension */
+  uint64_t n_reps;       /* number of orbits */
+  uint64_t n_entries;    /* entry-table length (0 when not kept) */
+  int32_t n_stab;        /* number of distinct stabilizers */
+  int32_t label_bits;    /* packed bits per site */
+  int64_t device_bytes;  /* device memory held by the sector */
+} ftlm_sector_info;
+int ftlm_sector_info_get(const ftlm_sector* s, ftlm_sector_info* info);
+/* Host copies: representative labels of Eq. (2) (n_reps), stabilizer id per
+ * representative (ids in order of first appearance), and per stabilizer its
+ * size.  Any pointer may be NULL. */
+int ftlm_sector_export(const ftlm_sector* s, uint64_t* reps, uint16_t* stab_id, int32_t* stab_size);
+/* Device-side orbit search and lookup for n labels of Eq. (2) (device arrays):
+ * rep = min O(a), h = smallest element index with U(h) a = rep, index = the
+ * representative's position (-1 if a is not in the sector).  Enqueued on
+ * stream. */
+int ftlm_sector_canonicalize(const ftlm_sector* s, const uint64_t* labels, int64_t n, uint64_t* rep,
+                             int32_t* h, int64_t* index, void* stream);
+void ftlm_sector_free(ftlm_sector* s);
+
+/* ---------------------------------------------------------------- block ---
+ * One (M, Gamma, row) block on top of a sector (Section 2.3): n_Gamma and
+ * V_S per stabilizer (V_S by modified Gram-Schmidt over the columns of
+ * (1/|S|) sum_{h in S} rho(h), columns with residual < 1e-8 dropped), row
+ * offsets, and device copies of rho and V_S.  The row never changes H (the
+ * per-row blocks are identical, Section 2.3); it is recorded and checked.
+ * The sector must outlive the block.  Errors: IRREP_OUT_OF_RANGE,
+ * ROW_OUT_OF_RANGE, DIM_GT_12, COMPLEX_IRREP_UNSUPPORTED, BAD_RHO (user_rho
+ * not a unitary homomorphism), OUT_OF_MEMORY, HIP.  D = 0 is legal. */
+int ftlm_block_create(ftlm_sector* s, int32_t irrep, int32_t row, const ftlm_opts* opts,
+                      ftlm_block** out);
+/* One call: group + sector + block (the block owns the private group and
+ * sector).  gens: ngens x N int32. */
+int ftlm_build_block(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, int32_t two_M,
+                     int32_t irrep, int32_t row, const ftlm_opts* opts, ftlm_block** out);
+
+typedef struct ftlm_block_info {
+  uint64_t D_M;          /* sector dimension */
+  uint64_t n_reps;       /* orbits in the sector */
+  uint64_t n_active;     /* representatives with n_Gamma > 0 */
+  uint64_t D;            /* block dimension, Eq. (13) */
+  int32_t d_gamma;       /* irrep dimension */
+  int32_t group_order;
+  int32_t two_M;
+  int32_t irrep;
+  int32_t row;
+  int32_t hv_mode;       /* mode actually used by apply */
+  int64_t device_bytes;  /* device memory of block + sector */
+} ftlm_block_info;
+int ftlm_block_info_get(const ftlm_block* b, ftlm_block_info* info);
+/* Host copies (n_reps each, any may be NULL): labels of Eq. (2), stabilizer
+ * ids, n_Gamma, orbit lengths L_r (as double), row offsets. */
+int ftlm_block_export(const ftlm_block* b, uint64_t* reps, uint16_t* stab_id, uint8_t* n_gamma,
+                      double* norms, uint64_t* offsets);
+
+/* Y = H X for nvec columns of D x ld device arrays of dtype (F64 or F32;
+ * F32 multiplies in FP32).  X and Y must not overlap.  Enqueued on stream
+ * (asynchronous).  Errors: INVALID_ARG, HIP. */
+int ftlm_apply_H(ftlm_block* b, const void* X, void* Y, int32_t nvec, int64_t ld, int32_t dtype,
+                 void* stream);
+
+/* R independent Lanczos chains batched into one H.V launch per step
+ * (Sections 2.2, 3).  Chain r starts from a SplitMix64 vector keyed by
+ * (seed, two_M, irrep, row, r), Rademacher or Gaussian, normalised in FP64,
+ * stored in `storage` precision; the recurrence w = H v_j - beta_j v_{j-1},
+ * alpha_j = <v_j, w>, w -= alpha_j v_j, beta_{j+1} = |w| runs with
+ * FP64 reductions, n = min(steps, D) products, early stop per chain when
+ * beta_{j+1} <= 1e-10 max_{i<=j}(|alpha_i| + beta_i + beta_{i+1}).
+ * Host outputs: alpha, beta (R x steps, row-major; beta[r][j] = beta_{j+1}),
+ * nsteps (R).  Synchronous.  Device scratch is allocated per call. */
+int ftlm_run(ftlm_block* b, int32_t R, int32_t steps, uint64_t seed, int32_t storage, int32_t dist,
+             double* alpha, double* beta, int32_t* nsteps, void* stream);
+
+/* Host FP64: eigenvalues theta (ascending) and weights w_k = (first
+ * eigenvector component)^2 of the n x n tridiagonal with diagonal alpha and
+ * off-diagonal beta[0..n-2] (Section 2.2).  n <= 4096. */
+int ftlm_tridiag_ritz(const double* alpha, const double* beta, int32_t n, double* theta,
+                      double* weight);
+
+/* Ritz data of one block for the thermal sums. */
+typedef struct ftlm_ritz {
+  int32_t two_M;
+  int32_t d_gamma;
+  uint64_t D;
+  int32_t R;
+  int32_t ld;              /* stride of theta/weight rows (>= max nsteps) */
+  const int32_t* nsteps;   /* R */
+  const double* theta;     /* R x ld */
+  const double* weight;    /* R x ld */
+} ftlm_ritz;
+
+/* Host FP64 thermal sums (Eqs. 4-7, 14): E, C (per cluster, k_B = 1) and the
+ * zero-field susceptibility chi = g^2 beta <(S^z)^2> on nT temperatures,
+ * Boltzmann factors shifted by the lowest Ritz value over all blocks;
+ * logZ = ln Z_FTLM.  Output pointers may be NULL.  Errors: INVALID_ARG. */
+int ftlm_observables(const ftlm_ritz* blocks, int32_t nblocks, const double* T, int32_t nT, double g,
+                     double* E, double* C, double* chi, double* logZ);
+
+void ftlm_block_free(ftlm_block* b);
+const char* ftlm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FTLM_H */

@@ -1,0 +1,11 @@
+"""MI355X symmetry-adapted finite-temperature Lanczos (FTLM) hot path.
+
+The work runs in ``libftlm.so`` (hand-written HIP for gfx950 + C++ host code)
+behind the C ABI of ``include/ftlm.h``; this package only marshals arguments.
+"""
+from .api import (F32, F64, GAUSSIAN, HV_AUTO, HV_ENTRIES, HV_ONTHEFLY, RADEMACHER, Block, FtlmError, Group,
+                  Sector, observables, ritz_from_run, tridiag_ritz)
+from ._lib import lib
+
+__all__ = ["Group", "Sector", "Block", "observables", "ritz_from_run", "tridiag_ritz", "FtlmError", "lib",
+           "F32", "F64", "RADEMACHER", "GAUSSIAN", "HV_AUTO", "HV_ENTRIES", "HV_ONTHEFLY"]

@@ -1,0 +1,153 @@
+"""ctypes binding of ``libftlm.so`` (the C ABI in ``include/ftlm.h``).
+
+Argument marshalling only: every step of the path runs inside the library.
+Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libftlm.so")
+
+F64, F32 = 0, 1
+RADEMACHER, GAUSSIAN = 0, 1
+HV_AUTO, HV_ENTRIES, HV_ONTHEFLY = 0, 1, 2
+
+STATUS = {
+    0: "OK", -1: "INVALID_ARG", -2: "NOT_A_PERMUTATION", -3: "GROUP_TOO_LARGE",
+    -4: "BONDS_NOT_INVARIANT", -5: "IRREP_OUT_OF_RANGE", -6: "ROW_OUT_OF_RANGE",
+    -7: "DIM_GT_12", -8: "COMPLEX_IRREP_UNSUPPORTED", -9: "OUT_OF_MEMORY", -10: "HIP",
+    -11: "BAD_RHO", -12: "UNSUPPORTED", -13: "IRREPS_FAILED", -14: "CANCELLED",
+    -15: "QUEUE_FULL",
+}
+
+
+class FtlmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+class Cluster(C.Structure):
+    _fields_ = [("N", C.c_int32), ("two_s", C.c_int32), ("nbonds", C.c_int32),
+                ("bonds", C.POINTER(C.c_int32)), ("J", C.POINTER(C.c_double))]
+
+
+class Opts(C.Structure):
+    _fields_ = [("hv_mode", C.c_int32), ("reserved0", C.c_int32),
+                ("user_rho", C.POINTER(C.c_double)), ("user_rho_dim", C.c_int32),
+                ("reserved1", C.c_int32), ("hbm_limit_bytes", C.c_int64),
+                ("reserved", C.c_int64 * 6)]
+
+
+class SectorInfo(C.Structure):
+    _fields_ = [("D_M", C.c_uint64), ("n_reps", C.c_uint64), ("n_entries", C.c_uint64),
+                ("n_stab", C.c_int32), ("label_bits", C.c_int32), ("device_bytes", C.c_int64)]
+
+
+class BlockInfo(C.Structure):
+    _fields_ = [("D_M", C.c_uint64), ("n_reps", C.c_uint64), ("n_active", C.c_uint64),
+                ("D", C.c_uint64), ("d_gamma", C.c_int32), ("group_order", C.c_int32),
+                ("two_M", C.c_int32), ("irrep", C.c_int32), ("row", C.c_int32),
+                ("hv_mode", C.c_int32), ("device_bytes", C.c_int64)]
+
+
+class Ritz(C.Structure):
+    _fields_ = [("two_M", C.c_int32), ("d_gamma", C.c_int32), ("D", C.c_uint64), ("R", C.c_int32),
+                ("ld", C.c_int32), ("nsteps", C.POINTER(C.c_int32)),
+                ("theta", C.POINTER(C.c_double)), ("weight", C.POINTER(C.c_double))]
+
+
+VP = C.c_void_p
+I32P = C.POINTER(C.c_int32)
+F64P = C.POINTER(C.c_double)
+
+# name -> (restype, argtypes); every symbol declared in include/ftlm.h
+SIGNATURES = {
+    "ftlm_last_error": (C.c_char_p, []),
+    "ftlm_group_create": (C.c_int, [C.c_int32, I32P, C.c_int32, C.POINTER(VP)]),
+    "ftlm_group_info": (C.c_int, [VP, I32P, I32P, I32P, I32P]),
+    "ftlm_group_elements": (C.c_int, [VP, I32P]),
+    "ftlm_group_irreps": (C.c_int, [VP, I32P, I32P, F64P, I32P, F64P]),
+    "ftlm_group_rho": (C.c_int, [VP, C.c_int32, F64P]),
+    "ftlm_group_free": (None, [VP]),
+    "ftlm_sector_create": (C.c_int, [C.POINTER(Cluster), VP, C.c_int32, C.POINTER(Opts), C.POINTER(VP)]),
+    "ftlm_sector_info_get": (C.c_int, [VP, C.POINTER(SectorInfo)]),
+    "ftlm_sector_export": (C.c_int, [VP, C.POINTER(C.c_uint64), C.POINTER(C.c_uint16), I32P]),
+    "ftlm_sector_canonicalize": (C.c_int, [VP, VP, C.c_int64, VP, VP, VP, VP]),
+    "ftlm_sector_free": (None, [VP]),
+    "ftlm_block_create": (C.c_int, [VP, C.c_int32, C.c_int32, C.POINTER(Opts), C.POINTER(VP)]),
+    "ftlm_build_block": (C.c_int, [C.POINTER(Cluster), I32P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                   C.POINTER(Opts), C.POINTER(VP)]),
+    "ftlm_block_info_get": (C.c_int, [VP, C.POINTER(BlockInfo)]),
+    "ftlm_block_export": (C.c_int, [VP, C.POINTER(C.c_uint64), C.POINTER(C.c_uint16), C.POINTER(C.c_uint8),
+                                    F64P, C.POINTER(C.c_uint64)]),
+    "ftlm_apply_H": (C.c_int, [VP, VP, VP, C.c_int32, C.c_int64, C.c_int32, VP]),
+    "ftlm_run": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, F64P, F64P, I32P, VP]),
+    "ftlm_tridiag_ritz": (C.c_int, [F64P, F64P, C.c_int32, F64P, F64P]),
+    "ftlm_observables": (C.c_int, [C.POINTER(Ritz), C.c_int32, F64P, C.c_int32, C.c_double, F64P, F64P, F64P, F64P]),
+    "ftlm_block_free": (None, [VP]),
+}
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(code):
+    if code != 0:
+        msg = lib().ftlm_last_error()
+        raise FtlmError(code, msg.decode() if msg else "")
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def make_cluster(N, two_s, bonds, J=None):
+    bonds = np.ascontiguousarray(np.asarray(bonds, dtype=np.int32).reshape(-1))
+    keep = [bonds]
+    Jp = None
+    if J is not None:
+        J = np.ascontiguousarray(np.asarray(J, dtype=np.float64))
+        keep.append(J)
+        Jp = _ptr(J, C.c_double)
+    cl = Cluster(int(N), int(two_s), len(bonds) // 2, _ptr(bonds, C.c_int32), Jp)
+    cl._keep = keep
+    return cl
+
+
+def make_opts(hv_mode=HV_AUTO, user_rho=None, hbm_limit=0):
+    o = Opts()
+    o.hv_mode = hv_mode
+    o.hbm_limit_bytes = int(hbm_limit)
+    if user_rho is not None:
+        rho = np.ascontiguousarray(np.asarray(user_rho, dtype=np.float64))
+        o.user_rho = _ptr(rho, C.c_double)
+        o.user_rho_dim = rho.shape[-1]
+        o._keep = rho
+    return o
+
+
+def stream_handle(stream=None):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)

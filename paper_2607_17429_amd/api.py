@@ -1,0 +1,225 @@
+"""Python face of the C ABI: the same calls, with numpy / torch arguments.
+
+Device arrays are torch CUDA tensors (PyTorch supplies device memory and the
+stream); every computation happens in ``libftlm.so``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib as L
+from ._lib import F32, F64, GAUSSIAN, HV_AUTO, HV_ENTRIES, HV_ONTHEFLY, RADEMACHER, FtlmError, check, lib
+
+
+class Group:
+    """Closure of site-permutation generators and its real irreps."""
+
+    def __init__(self, N, gens):
+        gens = np.ascontiguousarray(np.asarray(gens, dtype=np.int32).reshape(-1, N))
+        h = C.c_void_p()
+        check(lib().ftlm_group_create(int(N), gens.ctypes.data_as(L.I32P), len(gens), C.byref(h)))
+        self._h = h
+        o, ni, nc, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+        check(lib().ftlm_group_info(h, C.byref(o), C.byref(ni), C.byref(nc), C.byref(n)))
+        self.order, self.n_irreps, self.n_classes, self.N = o.value, ni.value, nc.value, n.value
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().ftlm_group_free(self._h)
+            self._h = None
+
+    def elements(self):
+        out = np.empty((self.order, self.N), dtype=np.int32)
+        check(lib().ftlm_group_elements(self._h, out.ctypes.data_as(L.I32P)))
+        return out
+
+    def irreps(self):
+        n = self.n_irreps
+        dims = np.empty(n, np.int32)
+        ind = np.empty(n, np.int32)
+        chars = np.empty((n, self.n_classes))
+        cls = np.empty(self.order, np.int32)
+        res = C.c_double()
+        check(lib().ftlm_group_irreps(self._h, dims.ctypes.data_as(L.I32P), ind.ctypes.data_as(L.I32P),
+                                      chars.ctypes.data_as(L.F64P), cls.ctypes.data_as(L.I32P), C.byref(res)))
+        return dict(dims=dims, indicators=ind, chars=chars, class_of=cls, residual=res.value)
+
+    def rho(self, irrep):
+        d = int(self.irreps()["dims"][irrep])
+        out = np.empty((self.order, d, d))
+        check(lib().ftlm_group_rho(self._h, int(irrep), out.ctypes.data_as(L.F64P)))
+        return out
+
+
+class Sector:
+    """Irrep-independent tables of one M sector (built on the GPU)."""
+
+    def __init__(self, cluster, group: Group, two_M, hv_mode=HV_AUTO, hbm_limit=0, two_s=None):
+        cl = L.make_cluster(cluster.N, two_s if two_s is not None else cluster.two_s, cluster.bonds, cluster.J) \
+            if not isinstance(cluster, L.Cluster) else cluster
+        self._cl = cl
+        self.group = group
+        opts = L.make_opts(hv_mode=hv_mode, hbm_limit=hbm_limit)
+        h = C.c_void_p()
+        check(lib().ftlm_sector_create(C.byref(cl), group._h, int(two_M), C.byref(opts), C.byref(h)))
+        self._h = h
+        self.two_M = int(two_M)
+        info = L.SectorInfo()
+        check(lib().ftlm_sector_info_get(h, C.byref(info)))
+        self.D_M, self.n_reps, self.n_entries = info.D_M, info.n_reps, info.n_entries
+        self.n_stab, self.label_bits, self.device_bytes = info.n_stab, info.label_bits, info.device_bytes
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().ftlm_sector_free(self._h)
+            self._h = None
+
+    def export(self):
+        reps = np.empty(self.n_reps, np.uint64)
+        sid = np.empty(self.n_reps, np.uint16)
+        ssz = np.empty(max(self.n_stab, 1), np.int32)
+        check(lib().ftlm_sector_export(self._h, reps.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                       sid.ctypes.data_as(C.POINTER(C.c_uint16)), ssz.ctypes.data_as(L.I32P)))
+        return reps, sid, ssz[: self.n_stab]
+
+    def canonicalize(self, labels, stream=None):
+        """labels: torch uint64/int64 CUDA tensor -> (rep, h, index) CUDA tensors."""
+        import torch
+        labels = labels.contiguous()
+        n = labels.numel()
+        rep = torch.empty(n, dtype=torch.int64, device=labels.device)
+        h = torch.empty(n, dtype=torch.int32, device=labels.device)
+        idx = torch.empty(n, dtype=torch.int64, device=labels.device)
+        check(lib().ftlm_sector_canonicalize(self._h, C.c_void_p(labels.data_ptr()), n, C.c_void_p(rep.data_ptr()),
+                                             C.c_void_p(h.data_ptr()), C.c_void_p(idx.data_ptr()),
+                                             L.stream_handle(stream)))
+        return rep, h, idx
+
+
+class Block:
+    """One (M, Gamma, row) block; owns device tables, shares the sector's."""
+
+    def __init__(self, sector: Sector, irrep, row=0, user_rho=None, hbm_limit=0):
+        self.sector = sector
+        opts = L.make_opts(user_rho=user_rho, hbm_limit=hbm_limit)
+        h = C.c_void_p()
+        check(lib().ftlm_block_create(sector._h, int(irrep), int(row), C.byref(opts), C.byref(h)))
+        self._h = h
+        self._load_info()
+
+    @classmethod
+    def build(cls, cluster, gens, two_M, irrep, row=0, user_rho=None, hv_mode=HV_AUTO, two_s=None):
+        """One call: group + sector + block (ftlm_build_block)."""
+        self = cls.__new__(cls)
+        self.sector = None
+        cl = L.make_cluster(cluster.N, two_s if two_s is not None else cluster.two_s, cluster.bonds, cluster.J)
+        gens = np.ascontiguousarray(np.asarray(gens, dtype=np.int32).reshape(-1, cluster.N))
+        opts = L.make_opts(hv_mode=hv_mode, user_rho=user_rho)
+        h = C.c_void_p()
+        check(lib().ftlm_build_block(C.byref(cl), gens.ctypes.data_as(L.I32P), len(gens), int(two_M), int(irrep),
+                                     int(row), C.byref(opts), C.byref(h)))
+        self._h = h
+        self._load_info()
+        return self
+
+    def _load_info(self):
+        info = L.BlockInfo()
+        check(lib().ftlm_block_info_get(self._h, C.byref(info)))
+        for f, _ in L.BlockInfo._fields_:
+            setattr(self, f, getattr(info, f))
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            lib().ftlm_block_free(self._h)
+            self._h = None
+
+    def export(self):
+        n = self.n_reps
+        reps = np.empty(n, np.uint64)
+        sid = np.empty(n, np.uint16)
+        ng = np.empty(n, np.uint8)
+        norms = np.empty(n, np.float64)
+        offs = np.empty(n, np.uint64)
+        check(lib().ftlm_block_export(self._h, reps.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                      sid.ctypes.data_as(C.POINTER(C.c_uint16)),
+                                      ng.ctypes.data_as(C.POINTER(C.c_uint8)), norms.ctypes.data_as(L.F64P),
+                                      offs.ctypes.data_as(C.POINTER(C.c_uint64))))
+        return dict(reps=reps, stab_id=sid, n_gamma=ng, L=norms, offsets=offs)
+
+    def apply_H(self, X, Y=None, stream=None):
+        """Y = H X for a (D, nvec) torch CUDA tensor (float64 or float32)."""
+        import torch
+        if X.dim() == 1:
+            X = X[:, None]
+        assert X.shape[0] == self.D and X.is_cuda
+        if Y is None:
+            Y = torch.empty_like(X)
+        dtype = F64 if X.dtype == torch.float64 else F32
+        assert X.dtype in (torch.float64, torch.float32) and Y.dtype == X.dtype
+        assert X.stride(1) == 1 and Y.stride(1) == 1 and X.stride(0) == Y.stride(0)
+        check(lib().ftlm_apply_H(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), X.shape[1],
+                                 X.stride(0), dtype, L.stream_handle(stream)))
+        return Y
+
+    def ftlm(self, R, steps, seed, storage=F64, dist=RADEMACHER, stream=None):
+        """Batched Lanczos: returns alpha, beta (R x steps) and nsteps (R)."""
+        alpha = np.zeros((R, steps))
+        beta = np.zeros((R, steps))
+        ns = np.zeros(R, np.int32)
+        check(lib().ftlm_run(self._h, int(R), int(steps), C.c_uint64(seed), int(storage), int(dist),
+                             alpha.ctypes.data_as(L.F64P), beta.ctypes.data_as(L.F64P), ns.ctypes.data_as(L.I32P),
+                             L.stream_handle(stream) if stream is not None else None))
+        return alpha, beta, ns
+
+
+def tridiag_ritz(alpha, beta):
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    beta = np.ascontiguousarray(beta, dtype=np.float64)
+    n = len(alpha)
+    th = np.empty(n)
+    w = np.empty(n)
+    check(lib().ftlm_tridiag_ritz(alpha.ctypes.data_as(L.F64P), beta.ctypes.data_as(L.F64P), n,
+                                  th.ctypes.data_as(L.F64P), w.ctypes.data_as(L.F64P)))
+    return th, w
+
+
+def ritz_from_run(alpha, beta, nsteps):
+    """Per chain Ritz values/weights (lists of arrays) from ftlm() output."""
+    ths, ws = [], []
+    for r in range(len(nsteps)):
+        n = int(nsteps[r])
+        th, w = tridiag_ritz(alpha[r, :n], beta[r, : max(n - 1, 0)] if n > 1 else np.zeros(1))
+        ths.append(th)
+        ws.append(w)
+    return ths, ws
+
+
+def observables(blocks, T, g=1.0):
+    """blocks: list of dicts (two_M, d_gamma, D, thetas, weights) -> E, C, chi, logZ."""
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    arr = (L.Ritz * len(blocks))()
+    keep = []
+    for i, b in enumerate(blocks):
+        R = len(b["thetas"])
+        ld = max([len(t) for t in b["thetas"]] + [1])
+        th = np.zeros((R, ld))
+        w = np.zeros((R, ld))
+        ns = np.zeros(R, np.int32)
+        for r, (t, ww) in enumerate(zip(b["thetas"], b["weights"])):
+            th[r, : len(t)] = t
+            w[r, : len(t)] = ww
+            ns[r] = len(t)
+        keep += [th, w, ns]
+        arr[i] = L.Ritz(int(b["two_M"]), int(b["d_gamma"]), int(b["D"]), R, ld, ns.ctypes.data_as(L.I32P),
+                        th.ctypes.data_as(L.F64P), w.ctypes.data_as(L.F64P))
+    nT = len(T)
+    E, Cv, chi, lz = np.empty(nT), np.empty(nT), np.empty(nT), np.empty(nT)
+    check(lib().ftlm_observables(arr, len(blocks), T.ctypes.data_as(L.F64P), nT, float(g), E.ctypes.data_as(L.F64P),
+                                 Cv.ctypes.data_as(L.F64P), chi.ctypes.data_as(L.F64P), lz.ctypes.data_as(L.F64P)))
+    return E, Cv, chi, lz
+
+
+__all__ = ["Group", "Sector", "Block", "tridiag_ritz", "ritz_from_run", "observables", "FtlmError",
+           "F32", "F64", "RADEMACHER", "GAUSSIAN", "HV_AUTO", "HV_ENTRIES", "HV_ONTHEFLY"]

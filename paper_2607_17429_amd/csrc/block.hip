@@ -1,0 +1,188 @@
+// One (M, Gamma, row) block on top of a sector (paper Section 2.3, Eqs. 8-13).
+//
+// Per stabilizer S (host, FP64): P_S = (1/|S|) sum_{h in S} rho(h) (real
+// irreps), n_Gamma(S) = (1/|S|) sum_h chi(h), V_S = modified Gram-Schmidt
+// over the columns of P_S in index order (a column is dropped when its
+// residual norm is below 1e-8; the kept count must equal n_Gamma), and the
+// orbit length L_S = |G| / |S|.  Per representative (device): n_Gamma and the
+// exclusive prefix sum giving each representative's first block row.
+#include <algorithm>
+#include <cmath>
+
+#include "internal.h"
+
+namespace ftlm {
+
+namespace {
+
+__global__ void k_rep_counts(const uint16_t* __restrict__ stab_id, uint64_t n, const uint8_t* __restrict__ n_stab,
+                             uint64_t* __restrict__ out, unsigned long long* __restrict__ per_stab) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint16_t s = stab_id[i];
+    out[i] = n_stab[s];
+    atomicAdd(&per_stab[s], 1ull);
+  }
+}
+
+__global__ void k_meta(const uint64_t* __restrict__ off, const uint16_t* __restrict__ stab_id, uint64_t n,
+                       uint64_t* __restrict__ meta) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    meta[i] = off[i] | ((uint64_t)stab_id[i] << 48);
+}
+
+unsigned grid1(uint64_t n) {
+  uint64_t g = (n + 255) / 256;
+  return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(g, 65536ull * 4));
+}
+
+double check_user_rho(const Group& G, const double* rho, int d) {
+  const int n = G.order;
+  double worst = 0;
+  for (int a = 0; a < n; ++a) {
+    const double* ra = rho + (size_t)a * d * d;
+    for (int i = 0; i < d; ++i)
+      for (int j = 0; j < d; ++j) {
+        double s = 0;
+        for (int k = 0; k < d; ++k) s += ra[k * d + i] * ra[k * d + j];
+        worst = std::max(worst, std::fabs(s - (i == j ? 1.0 : 0.0)));
+      }
+    for (int b = 0; b < n; ++b) {
+      const double* rb = rho + (size_t)b * d * d;
+      const double* rab = rho + (size_t)G.idx_mul(a, b) * d * d;
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+          double s = 0;
+          for (int k = 0; k < d; ++k) s += ra[i * d + k] * rb[k * d + j];
+          worst = std::max(worst, std::fabs(s - rab[i * d + j]));
+        }
+    }
+  }
+  return worst;
+}
+
+}  // namespace
+
+std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int row, const ftlm_opts* opts) {
+  if (!sec) fail(FTLM_ERR_INVALID_ARG, "null sector");
+  const Group& G = *sec->G;
+  auto B = std::make_unique<Block>();
+  B->sec = sec;
+  B->irrep = irrep;
+  B->row = row;
+  const int n = G.order;
+  if (opts && opts->user_rho && opts->user_rho_dim > 0) {
+    const int d = opts->user_rho_dim;
+    if (d > 12) fail(FTLM_ERR_DIM_GT_12, "irrep dimension above 12");
+    B->dg = d;
+    B->rho.assign(opts->user_rho, opts->user_rho + (size_t)n * d * d);
+    double res = check_user_rho(G, B->rho.data(), d);
+    if (!(res < 1e-9)) fail(FTLM_ERR_BAD_RHO, "user rho is not an orthogonal representation (residual " + std::to_string(res) + ")");
+  } else {
+    if (!G.irreps_computed) fail(FTLM_ERR_UNSUPPORTED, "group irreps not available (|G| > 1024); pass user_rho");
+    if (!G.all_real) fail(FTLM_ERR_COMPLEX_IRREP_UNSUPPORTED, "group has irreps that are not of real type");
+    if (irrep < 0 || irrep >= (int)G.irreps.size()) fail(FTLM_ERR_IRREP_OUT_OF_RANGE, "irrep index out of range");
+    const Irrep& ir = G.irreps[irrep];
+    if (ir.dim > 12) fail(FTLM_ERR_DIM_GT_12, "irrep dimension above 12");
+    B->dg = ir.dim;
+    B->rho = ir.rho;
+  }
+  const int d = B->dg;
+  if (row < 0 || row >= d) fail(FTLM_ERR_ROW_OUT_OF_RANGE, "row must be in 0..d-1");
+  // per stabilizer data
+  const int ns = sec->n_stab;
+  B->n_stab.assign(std::max(ns, 1), 0);
+  B->V_stab.assign((size_t)std::max(ns, 1) * d * d, 0.0);
+  B->L_stab.assign(std::max(ns, 1), 1.0);
+  B->trivial.assign(std::max(ns, 1), 0);
+  for (int s = 0; s < ns; ++s) {
+    const auto& S = sec->stab_elems[s];
+    const double inv = 1.0 / (double)S.size();
+    std::vector<double> P((size_t)d * d, 0.0);
+    double chi = 0;
+    for (int h : S) {
+      const double* r = &B->rho[(size_t)h * d * d];
+      for (int q = 0; q < d * d; ++q) P[q] += r[q] * inv;
+      for (int q = 0; q < d; ++q) chi += r[q * d + q] * inv;
+    }
+    const int nG = (int)std::lround(chi);
+    if (std::fabs(chi - nG) > 1e-6) fail(FTLM_ERR_BAD_RHO, "stabilizer character sum is not an integer");
+    std::vector<std::vector<double>> cols;
+    for (int j = 0; j < d; ++j) {
+      std::vector<double> v(d);
+      for (int i = 0; i < d; ++i) v[i] = P[i * d + j];
+      for (const auto& q : cols) {
+        double dot = 0;
+        for (int i = 0; i < d; ++i) dot += q[i] * v[i];
+        for (int i = 0; i < d; ++i) v[i] -= dot * q[i];
+      }
+      double nrm = 0;
+      for (int i = 0; i < d; ++i) nrm += v[i] * v[i];
+      nrm = std::sqrt(nrm);
+      if (nrm < 1e-8) continue;
+      for (int i = 0; i < d; ++i) v[i] /= nrm;
+      cols.push_back(v);
+    }
+    if ((int)cols.size() != nG) fail(FTLM_ERR_BAD_RHO, "Gram-Schmidt rank differs from the character count");
+    B->n_stab[s] = (uint8_t)nG;
+    for (int k = 0; k < nG; ++k)
+      for (int i = 0; i < d; ++i) B->V_stab[((size_t)s * d + i) * d + k] = cols[k][i];
+    B->L_stab[s] = (double)n / (double)S.size();
+    B->trivial[s] = (S.size() == 1) ? 1 : 0;
+  }
+  hipStream_t st = nullptr;
+  // device tables
+  if (sec->n_reps) {
+    DevBuf<uint8_t> d_n;
+    d_n.upload(B->n_stab);
+    DevBuf<unsigned long long> per;
+    per.alloc(std::max(ns, 1));
+    FTLM_HIP(hipMemsetAsync(per.p, 0, per.bytes(), st));
+    DevBuf<uint64_t> off;
+    off.alloc(sec->n_reps + 1);
+    FTLM_HIP(hipMemsetAsync(off.p + sec->n_reps, 0, sizeof(uint64_t), st));
+    hipLaunchKernelGGL(k_rep_counts, dim3(grid1(sec->n_reps)), dim3(256), 0, st, sec->d_stab_id.p, sec->n_reps, d_n.p,
+                       off.p, per.p);
+    FTLM_HIP(hipGetLastError());
+    uint64_t D = 0;
+    scan_exclusive_u64(off.p, off.p, sec->n_reps + 1, &D, st);
+    if (D >= (1ull << 48)) fail(FTLM_ERR_UNSUPPORTED, "block dimension above 2^48");
+    B->D = D;
+    B->d_meta.alloc(sec->n_reps);
+    hipLaunchKernelGGL(k_meta, dim3(grid1(sec->n_reps)), dim3(256), 0, st, off.p, sec->d_stab_id.p, sec->n_reps,
+                       B->d_meta.p);
+    FTLM_HIP(hipGetLastError());
+    std::vector<unsigned long long> h_per(std::max(ns, 1));
+    FTLM_HIP(hipMemcpyAsync(h_per.data(), per.p, h_per.size() * 8, hipMemcpyDeviceToHost, st));
+    FTLM_HIP(hipStreamSynchronize(st));
+    B->n_active = 0;
+    for (int s = 0; s < ns; ++s)
+      if (B->n_stab[s]) B->n_active += h_per[s];
+  }
+  // rho^T[g][beta][gamma] = rho(g)[gamma][beta]
+  std::vector<double> rt((size_t)n * d * d);
+  for (int g = 0; g < n; ++g)
+    for (int be = 0; be < d; ++be)
+      for (int ga = 0; ga < d; ++ga) rt[((size_t)g * d + be) * d + ga] = B->rho[((size_t)g * d + ga) * d + be];
+  B->d_rhoT64.upload(rt);
+  std::vector<float> rt32(rt.begin(), rt.end());
+  B->d_rhoT32.upload(rt32);
+  B->d_V64.upload(B->V_stab);
+  std::vector<float> v32(B->V_stab.begin(), B->V_stab.end());
+  B->d_V32.upload(v32);
+  std::vector<double> sf((size_t)std::max(ns, 1) * 4, 0.0);
+  for (int s = 0; s < ns; ++s) {
+    sf[4 * s + 0] = B->n_stab[s];
+    sf[4 * s + 1] = std::sqrt(B->L_stab[s]);
+    sf[4 * s + 2] = 1.0 / std::sqrt(B->L_stab[s]);
+    sf[4 * s + 3] = B->trivial[s];
+  }
+  B->d_stabf64.upload(sf);
+  std::vector<float> sf32(sf.begin(), sf.end());
+  B->d_stabf32.upload(sf32);
+  FTLM_HIP(hipStreamSynchronize(st));
+  if (opts && opts->hbm_limit_bytes > 0 && B->device_bytes() > opts->hbm_limit_bytes)
+    fail(FTLM_ERR_OUT_OF_MEMORY, "block tables exceed the HBM limit");
+  return B;
+}
+
+}  // namespace ftlm

@@ -1,0 +1,247 @@
+// extern "C" entry points of ftlm.h: argument checks, exception -> status
+// translation, thread-local last-error message.
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+
+namespace ftlm {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_last_error(const std::string& msg) { g_last_error = msg; }
+
+template <typename F>
+int guarded(F&& f) {
+  try {
+    f();
+    return FTLM_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host out of memory");
+    return FTLM_ERR_OUT_OF_MEMORY;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return FTLM_ERR_INVALID_ARG;
+  }
+}
+
+}  // namespace ftlm
+
+using namespace ftlm;
+
+extern "C" {
+
+const char* ftlm_last_error(void) { return g_last_error.c_str(); }
+
+int ftlm_group_create(int32_t N, const int32_t* gens, int32_t ngens, ftlm_group** out) {
+  return guarded([&] {
+    if (!out) fail(FTLM_ERR_INVALID_ARG, "null output");
+    *out = nullptr;
+    auto G = std::make_shared<Group>(build_group(N, gens, ngens));
+    compute_irreps(*G);
+    *out = new ftlm_group{G};
+  });
+}
+
+int ftlm_group_info(const ftlm_group* g, int32_t* order, int32_t* n_irreps, int32_t* n_classes, int32_t* N) {
+  return guarded([&] {
+    if (!g) fail(FTLM_ERR_INVALID_ARG, "null group");
+    if (order) *order = g->G->order;
+    if (n_irreps) *n_irreps = (int32_t)g->G->irreps.size();
+    if (n_classes) *n_classes = (int32_t)g->G->classes.size();
+    if (N) *N = g->G->N;
+  });
+}
+
+int ftlm_group_elements(const ftlm_group* g, int32_t* perms) {
+  return guarded([&] {
+    if (!g || !perms) fail(FTLM_ERR_INVALID_ARG, "null argument");
+    std::memcpy(perms, g->G->perms.data(), g->G->perms.size() * sizeof(int32_t));
+  });
+}
+
+int ftlm_group_irreps(const ftlm_group* g, int32_t* dims, int32_t* indicators, double* chars, int32_t* class_of,
+                      double* max_residual) {
+  return guarded([&] {
+    if (!g) fail(FTLM_ERR_INVALID_ARG, "null group");
+    const Group& G = *g->G;
+    const size_t nc = G.classes.size();
+    for (size_t i = 0; i < G.irreps.size(); ++i) {
+      if (dims) dims[i] = G.irreps[i].dim;
+      if (indicators) indicators[i] = G.irreps[i].indicator;
+      if (chars)
+        for (size_t c = 0; c < nc; ++c) chars[i * nc + c] = G.irreps[i].chars[c];
+    }
+    if (class_of) std::memcpy(class_of, G.class_of.data(), G.class_of.size() * sizeof(int32_t));
+    if (max_residual) *max_residual = G.max_residual;
+  });
+}
+
+int ftlm_group_rho(const ftlm_group* g, int32_t irrep, double* rho) {
+  return guarded([&] {
+    if (!g || !rho) fail(FTLM_ERR_INVALID_ARG, "null argument");
+    if (irrep < 0 || irrep >= (int)g->G->irreps.size()) fail(FTLM_ERR_IRREP_OUT_OF_RANGE, "irrep index out of range");
+    const auto& r = g->G->irreps[irrep].rho;
+    std::memcpy(rho, r.data(), r.size() * sizeof(double));
+  });
+}
+
+void ftlm_group_free(ftlm_group* g) { delete g; }
+
+int ftlm_sector_create(const ftlm_cluster* cl, const ftlm_group* g, int32_t two_M, const ftlm_opts* opts,
+                       ftlm_sector** out) {
+  return guarded([&] {
+    if (!out || !g) fail(FTLM_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    auto s = build_sector(cl, g->G, two_M, opts);
+    *out = new ftlm_sector{s};
+  });
+}
+
+int ftlm_sector_info_get(const ftlm_sector* s, ftlm_sector_info* info) {
+  return guarded([&] {
+    if (!s || !info) fail(FTLM_ERR_INVALID_ARG, "null argument");
+    const Sector& S = *s->s;
+    info->D_M = S.D_M;
+    info->n_reps = S.n_reps;
+    info->n_entries = S.d_entries.n;
+    info->n_stab = S.n_stab;
+    info->label_bits = S.bits;
+    info->device_bytes = S.device_bytes();
+  });
+}
+
+int ftlm_sector_export(const ftlm_sector* s, uint64_t* reps, uint16_t* stab_id, int32_t* stab_size) {
+  return guarded([&] {
+    if (!s) fail(FTLM_ERR_INVALID_ARG, "null sector");
+    const Sector& S = *s->s;
+    if (reps && S.n_reps) {
+      auto v = sector_export_labels(S);
+      std::memcpy(reps, v.data(), v.size() * 8);
+    }
+    if (stab_id && S.n_reps) {
+      auto v = S.d_stab_id.download();
+      std::memcpy(stab_id, v.data(), v.size() * 2);
+    }
+    if (stab_size)
+      for (int i = 0; i < S.n_stab; ++i) stab_size[i] = S.stab_size[i];
+  });
+}
+
+int ftlm_sector_canonicalize(const ftlm_sector* s, const uint64_t* labels, int64_t n, uint64_t* rep, int32_t* h,
+                             int64_t* index, void* stream) {
+  return guarded([&] {
+    if (!s) fail(FTLM_ERR_INVALID_ARG, "null sector");
+    sector_canonicalize(*s->s, labels, n, rep, h, index, (hipStream_t)stream);
+  });
+}
+
+void ftlm_sector_free(ftlm_sector* s) { delete s; }
+
+int ftlm_block_create(ftlm_sector* s, int32_t irrep, int32_t row, const ftlm_opts* opts, ftlm_block** out) {
+  return guarded([&] {
+    if (!s || !out) fail(FTLM_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    auto b = build_block(s->s, irrep, row, opts);
+    *out = new ftlm_block{std::move(b)};
+  });
+}
+
+int ftlm_build_block(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, int32_t two_M, int32_t irrep,
+                     int32_t row, const ftlm_opts* opts, ftlm_block** out) {
+  return guarded([&] {
+    if (!cl || !out) fail(FTLM_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    auto G = std::make_shared<Group>(build_group(cl->N, gens, ngens));
+    if (!(opts && opts->user_rho)) compute_irreps(*G);
+    auto sec = build_sector(cl, G, two_M, opts);
+    auto b = build_block(sec, irrep, row, opts);
+    b->own_group = G;
+    *out = new ftlm_block{std::move(b)};
+  });
+}
+
+int ftlm_block_info_get(const ftlm_block* b, ftlm_block_info* info) {
+  return guarded([&] {
+    if (!b || !info) fail(FTLM_ERR_INVALID_ARG, "null argument");
+    const Block& B = *b->b;
+    info->D_M = B.sec->D_M;
+    info->n_reps = B.sec->n_reps;
+    info->n_active = B.n_active;
+    info->D = B.D;
+    info->d_gamma = B.dg;
+    info->group_order = B.sec->G->order;
+    info->two_M = B.sec->two_M;
+    info->irrep = B.irrep;
+    info->row = B.row;
+    info->hv_mode = B.sec->hv_mode;
+    info->device_bytes = B.device_bytes();
+  });
+}
+
+int ftlm_block_export(const ftlm_block* b, uint64_t* reps, uint16_t* stab_id, uint8_t* n_gamma, double* norms,
+                      uint64_t* offsets) {
+  return guarded([&] {
+    if (!b) fail(FTLM_ERR_INVALID_ARG, "null block");
+    const Block& B = *b->b;
+    const Sector& S = *B.sec;
+    if (!S.n_reps) return;
+    if (reps) {
+      auto v = sector_export_labels(S);
+      std::memcpy(reps, v.data(), v.size() * 8);
+    }
+    std::vector<uint16_t> sid = S.d_stab_id.download();
+    if (stab_id) std::memcpy(stab_id, sid.data(), sid.size() * 2);
+    if (n_gamma)
+      for (size_t i = 0; i < sid.size(); ++i) n_gamma[i] = B.n_stab[sid[i]];
+    if (norms)
+      for (size_t i = 0; i < sid.size(); ++i) norms[i] = B.L_stab[sid[i]];
+    if (offsets) {
+      auto m = B.d_meta.download();
+      for (size_t i = 0; i < m.size(); ++i) offsets[i] = m[i] & ((1ull << 48) - 1);
+    }
+  });
+}
+
+int ftlm_apply_H(ftlm_block* b, const void* X, void* Y, int32_t nvec, int64_t ld, int32_t dtype, void* stream) {
+  return guarded([&] {
+    if (!b) fail(FTLM_ERR_INVALID_ARG, "null block");
+    if (X == Y && X) fail(FTLM_ERR_INVALID_ARG, "X and Y must not overlap");
+    apply_hv(*b->b, X, Y, nvec, ld, dtype, (hipStream_t)stream);
+  });
+}
+
+int ftlm_run(ftlm_block* b, int32_t R, int32_t steps, uint64_t seed, int32_t storage, int32_t dist, double* alpha,
+             double* beta, int32_t* nsteps, void* stream) {
+  return guarded([&] {
+    if (!b) fail(FTLM_ERR_INVALID_ARG, "null block");
+    run_lanczos(*b->b, R, steps, seed, storage, dist, alpha, beta, nsteps, (hipStream_t)stream);
+  });
+}
+
+int ftlm_tridiag_ritz(const double* alpha, const double* beta, int32_t n, double* theta, double* weight) {
+  return guarded([&] {
+    if (n < 0 || n > 4096) fail(FTLM_ERR_INVALID_ARG, "n must be in 0..4096");
+    if (n > 0 && (!alpha || !theta || !weight || (n > 1 && !beta))) fail(FTLM_ERR_INVALID_ARG, "null argument");
+    tridiag_ritz(alpha, beta, n, theta, weight);
+  });
+}
+
+int ftlm_observables(const ftlm_ritz* blocks, int32_t nblocks, const double* T, int32_t nT, double g, double* E,
+                     double* C, double* chi, double* logZ) {
+  return guarded([&] {
+    if (nblocks <= 0 || !blocks || nT < 0 || (nT > 0 && !T)) fail(FTLM_ERR_INVALID_ARG, "bad arguments");
+    for (int i = 0; i < nT; ++i)
+      if (!(T[i] > 0)) fail(FTLM_ERR_INVALID_ARG, "temperatures must be positive");
+    observables(blocks, nblocks, T, nT, g, E, C, chi, logZ);
+  });
+}
+
+void ftlm_block_free(ftlm_block* b) { delete b; }
+
+}  // extern "C"

@@ -1,0 +1,140 @@
+// Device helpers shared by the sector, block and H.V kernels: packed state
+// labels, sector rank / unrank over digit-sum count tables, successor in
+// label order, and the orbit search.
+//
+// A packed label stores site k's digit a_k = m_k + s in bits [k*b, k*b+b),
+// b = ceil(log2(2s+1)).  Comparing packed labels as integers gives the same
+// order as comparing the labels n of Eq. (2), so "smallest label in the
+// orbit" is the smallest packed word.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ftlm {
+namespace dev {
+
+template <typename W>
+__device__ __forceinline__ int digit(W x, int k, int b, W mask) {
+  return (int)((x >> (k * b)) & mask);
+}
+
+// Number of labels strictly below x in its sector (digits sum to A), in
+// ascending label order.  cnt[k * stride + v] = ways for k digits to sum to v.
+template <typename W>
+__device__ __forceinline__ uint64_t sector_rank(W x, int N, int b, int d, int A, const uint64_t* cnt,
+                                                int stride) {
+  const W mask = (W(1) << b) - 1;
+  uint64_t r = 0;
+  int rem = A;
+  for (int pos = N - 1; pos >= 0; --pos) {
+    int a = digit(x, pos, b, mask);
+    for (int t = 0; t < a; ++t) {
+      int v = rem - t;
+      if (v >= 0) r += cnt[pos * stride + v];
+    }
+    rem -= a;
+  }
+  return r;
+}
+
+// The label of rank i in the sector.
+template <typename W>
+__device__ __forceinline__ W sector_unrank(uint64_t i, int N, int b, int d, int A, const uint64_t* cnt,
+                                           int stride) {
+  W x = 0;
+  int rem = A;
+  for (int pos = N - 1; pos >= 0; --pos) {
+    int a = 0;
+    for (; a < d - 1; ++a) {
+      int v = rem - a;
+      uint64_t c = v >= 0 ? cnt[pos * stride + v] : 0;
+      if (i < c) break;
+      i -= c;
+    }
+    x |= W(a) << (pos * b);
+    rem -= a;
+  }
+  return x;
+}
+
+// Next larger label with the same digit sum.  For b == 1 the next bit
+// permutation with equal popcount; otherwise move one unit up into the
+// lowest raisable digit that has a non-zero digit sum below it and refill the
+// lower digits with the smallest arrangement (largest digits lowest).
+template <typename W>
+__device__ __forceinline__ W sector_next(W x, int N, int b, int d) {
+  if (b == 1) {
+    if (x == 0) return x;
+    W t = x | (x - 1);
+    int tz = (sizeof(W) == 8) ? __builtin_ctzll((unsigned long long)x) : __builtin_ctz((unsigned)x);
+    W nt = ~t;
+    W low = nt & (W(0) - nt);
+    return (t + 1) | (W((low - 1) >> (tz + 1)));
+  }
+  const W mask = (W(1) << b) - 1;
+  int below = 0;
+  for (int k = 0; k < N; ++k) {
+    int a = digit(x, k, b, mask);
+    if (k > 0 && below >= 1 && a < d - 1) {
+      W y = x;
+      // clear digits 0..k, set digit k to a + 1, refill 0..k-1 with below - 1
+      W clear = (k + 1) * b >= (int)(8 * sizeof(W)) ? ~W(0) : ((W(1) << ((k + 1) * b)) - 1);
+      y &= ~clear;
+      y |= W(a + 1) << (k * b);
+      int rem = below - 1;
+      for (int j = 0; j < k && rem > 0; ++j) {
+        int v = rem < d - 1 ? rem : d - 1;
+        y |= W(v) << (j * b);
+        rem -= v;
+      }
+      return y;
+    }
+    below += a;
+  }
+  return x;  // x was the largest label of the sector
+}
+
+// Image of x under group element g through 4-bit chunk tables:
+// tab[(g * NCH + c) * 16 + v] = packed image of chunk value v at chunk c.
+template <typename W, int NCH>
+__device__ __forceinline__ W permute(const W* __restrict__ tab, int g, const int* off) {
+  const W* t = tab + (size_t)g * (NCH * 16);
+  W img = 0;
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) img |= t[off[c]];
+  return img;
+}
+
+template <typename W, int NCH>
+__device__ __forceinline__ void chunk_offsets(W a, int* off) {
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) off[c] = c * 16 + (int)((a >> (4 * c)) & W(15));
+}
+
+// Orbit minimum and the smallest group index h reaching it (U(h) a = best).
+// Every lane of the wave walks the group elements in the same order, so the
+// table reads of one step hit at most 16 distinct words per chunk.
+template <typename W, int NCH>
+__device__ __forceinline__ void canon_min(W a, const W* __restrict__ tab, int G, W& best, int& bestg) {
+  int off[NCH];
+  chunk_offsets<W, NCH>(a, off);
+  best = a;
+  bestg = 0;
+  for (int g = 1; g < G; ++g) {
+    W img = permute<W, NCH>(tab, g, off);
+    if (img < best) {
+      best = img;
+      bestg = g;
+    }
+  }
+}
+
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace dev
+}  // namespace ftlm

@@ -1,0 +1,339 @@
+// Site-permutation group closure and real irreps (paper Section 3).
+//
+// Closure uses Dimino's algorithm: each new generator extends the current
+// subgroup H by the right cosets H x reached by right-multiplying coset
+// representatives with the generators seen so far.  Elements are then sorted
+// lexicographically by permutation image.
+//
+// Irreps: the eigenspaces of a generic real symmetric element
+// S = A + A^T, A = sum_g c_g R(g), of the right regular algebra are invariant
+// under the left regular representation; restricted to one eigenspace Q the
+// left action rho(g) = Q^T L(g) Q is an irrep in real orthogonal form when
+// the irrep has Frobenius-Schur indicator +1.  Eigenspaces carrying a pair of
+// complex (or a quaternionic) irreps are reducible over C; they are detected
+// through their characters and left out (all_real = false).
+#include "group.h"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+
+#include "common.h"
+
+namespace ftlm {
+
+namespace {
+
+using Perm = std::string;  // byte string of images (N <= 64)
+
+Perm compose(const Perm& g, const Perm& h) {  // (g h)[k] = g[h[k]]
+  Perm r(h.size(), 0);
+  for (size_t k = 0; k < h.size(); ++k) r[k] = g[(unsigned char)h[k]];
+  return r;
+}
+
+uint64_t splitmix_next(uint64_t& state) {
+  state += 0x9E3779B97F4A7C15ull;
+  uint64_t z = state;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+}  // namespace
+
+Group build_group(int N, const int32_t* gens, int ngens) {
+  if (N <= 0 || N > 64) fail(FTLM_ERR_INVALID_ARG, "N must be in 1..64");
+  if (ngens < 0 || (ngens > 0 && !gens)) fail(FTLM_ERR_INVALID_ARG, "bad generator array");
+  std::vector<Perm> gen;
+  for (int i = 0; i < ngens; ++i) {
+    Perm p(N, 0);
+    std::vector<char> seen(N, 0);
+    for (int k = 0; k < N; ++k) {
+      int v = gens[(size_t)i * N + k];
+      if (v < 0 || v >= N || seen[v]) fail(FTLM_ERR_NOT_A_PERMUTATION, "generator " + std::to_string(i) + " is not a permutation");
+      seen[v] = 1;
+      p[k] = (char)v;
+    }
+    gen.push_back(p);
+  }
+  Perm e(N, 0);
+  for (int k = 0; k < N; ++k) e[k] = (char)k;
+  std::vector<Perm> elems{e};
+  std::unordered_set<Perm> have{e};
+  std::vector<Perm> used;
+  const size_t limit = 65535;
+  for (const Perm& s : gen) {
+    if (have.count(s)) continue;
+    std::vector<Perm> H = elems;  // current subgroup
+    used.push_back(s);
+    std::vector<Perm> reps{s};
+    auto add_coset = [&](const Perm& x) {
+      for (const Perm& h : H) {
+        Perm y = compose(h, x);
+        if (have.insert(y).second) elems.push_back(y);
+      }
+      if (elems.size() > limit) fail(FTLM_ERR_GROUP_TOO_LARGE, "group order exceeds 65535");
+    };
+    add_coset(s);
+    for (size_t i = 0; i < reps.size(); ++i) {
+      for (const Perm& t : used) {
+        Perm x = compose(reps[i], t);
+        if (!have.count(x)) {
+          reps.push_back(x);
+          add_coset(x);
+        }
+      }
+    }
+  }
+  std::sort(elems.begin(), elems.end(), [](const Perm& a, const Perm& b) {
+    for (size_t k = 0; k < a.size(); ++k)
+      if (a[k] != b[k]) return (unsigned char)a[k] < (unsigned char)b[k];
+    return false;
+  });
+  Group G;
+  G.N = N;
+  G.order = (int)elems.size();
+  const int n = G.order;
+  std::unordered_map<Perm, int> index;
+  index.reserve(n * 2);
+  for (int i = 0; i < n; ++i) index[elems[i]] = i;
+  G.perms.resize((size_t)n * N);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < N; ++k) G.perms[(size_t)i * N + k] = (unsigned char)elems[i][k];
+  G.mul.resize((size_t)n * n);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) G.mul[(size_t)a * n + b] = (uint16_t)index.at(compose(elems[a], elems[b]));
+  G.inv.resize(n);
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b)
+      if (G.mul[(size_t)a * n + b] == 0) { G.inv[a] = (uint16_t)b; break; }
+  G.elem_order.resize(n);
+  for (int a = 0; a < n; ++a) {
+    int k = 1, x = a;
+    while (x != 0) { x = G.idx_mul(x, a); ++k; }
+    G.elem_order[a] = k;
+  }
+  // conjugacy classes, canonical order (element order, size, smallest member)
+  std::vector<int> cls(n, -1);
+  std::vector<std::vector<int32_t>> raw;
+  for (int a = 0; a < n; ++a) {
+    if (cls[a] >= 0) continue;
+    std::vector<int32_t> mem;
+    for (int x = 0; x < n; ++x) mem.push_back(G.idx_mul(G.idx_mul(x, a), G.inv[x]));
+    std::sort(mem.begin(), mem.end());
+    mem.erase(std::unique(mem.begin(), mem.end()), mem.end());
+    for (int m : mem) cls[m] = (int)raw.size();
+    raw.push_back(mem);
+  }
+  std::vector<int> ord(raw.size());
+  for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+  std::sort(ord.begin(), ord.end(), [&](int x, int y) {
+    auto kx = std::make_tuple(G.elem_order[raw[x][0]], raw[x].size(), raw[x][0]);
+    auto ky = std::make_tuple(G.elem_order[raw[y][0]], raw[y].size(), raw[y][0]);
+    return kx < ky;
+  });
+  G.class_of.assign(n, 0);
+  for (size_t ci = 0; ci < ord.size(); ++ci) {
+    G.classes.push_back(raw[ord[ci]]);
+    for (int m : raw[ord[ci]]) G.class_of[m] = (int)ci;
+  }
+  return G;
+}
+
+std::vector<double> jacobi_eigh(std::vector<double>& A, int n, std::vector<double>& V) {
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+  double scale = 0.0;
+  for (size_t i = 0; i < A.size(); ++i) scale = std::max(scale, std::fabs(A[i]));
+  if (scale == 0.0) scale = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += a(p, q) * a(p, q);
+    if (std::sqrt(off) <= 1e-15 * scale * n) break;
+    for (int p = 0; p < n; ++p) {
+      for (int q = p + 1; q < n; ++q) {
+        double apq = a(p, q);
+        if (std::fabs(apq) <= 1e-300) continue;
+        // rotation that zeroes a_pq: tan(phi) = t solves t^2 + 2 theta t - 1 = 0
+        double theta = (a(q, q) - a(p, p)) / (2.0 * apq);
+        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        double c = 1.0 / std::sqrt(t * t + 1.0);
+        double s = t * c;
+        for (int k = 0; k < n; ++k) {
+          double akp = a(k, p), akq = a(k, q);
+          a(k, p) = c * akp - s * akq;
+          a(k, q) = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          double apk = a(p, k), aqk = a(q, k);
+          a(p, k) = c * apk - s * aqk;
+          a(q, k) = s * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = c * vkp - s * vkq;
+          V[(size_t)k * n + q] = s * vkp + c * vkq;
+        }
+      }
+    }
+  }
+  std::vector<double> w(n);
+  for (int i = 0; i < n; ++i) w[i] = a(i, i);
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return w[x] < w[y]; });
+  std::vector<double> ws(n), Vs((size_t)n * n);
+  for (int j = 0; j < n; ++j) {
+    ws[j] = w[idx[j]];
+    for (int i = 0; i < n; ++i) Vs[(size_t)i * n + j] = V[(size_t)i * n + idx[j]];
+  }
+  V.swap(Vs);
+  return ws;
+}
+
+double verify_irreps(const Group& G, const std::vector<const Irrep*>& irs) {
+  const int n = G.order;
+  double worst = 0.0;
+  for (const Irrep* ir : irs) {
+    const int d = ir->dim;
+    const double* r = ir->rho.data();
+    for (int a = 0; a < n; ++a) {
+      // orthogonality rho(a)^T rho(a) = 1
+      for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+          double s = 0;
+          for (int k = 0; k < d; ++k) s += r[((size_t)a * d + k) * d + i] * r[((size_t)a * d + k) * d + j];
+          worst = std::max(worst, std::fabs(s - (i == j ? 1.0 : 0.0)));
+        }
+      for (int b = 0; b < n; ++b) {
+        const double* ab = r + (size_t)G.idx_mul(a, b) * d * d;
+        for (int i = 0; i < d; ++i)
+          for (int j = 0; j < d; ++j) {
+            double s = 0;
+            for (int k = 0; k < d; ++k) s += r[((size_t)a * d + i) * d + k] * r[((size_t)b * d + k) * d + j];
+            worst = std::max(worst, std::fabs(s - ab[i * d + j]));
+          }
+      }
+    }
+  }
+  // great orthogonality (d_A/|G|) sum_g rho_A(g)_ij rho_B(g)_kl = delta_AB delta_ik delta_jl
+  for (size_t x = 0; x < irs.size(); ++x)
+    for (size_t y = x; y < irs.size(); ++y) {
+      const Irrep& A = *irs[x];
+      const Irrep& B = *irs[y];
+      for (int i = 0; i < A.dim; ++i)
+        for (int j = 0; j < A.dim; ++j)
+          for (int k = 0; k < B.dim; ++k)
+            for (int l = 0; l < B.dim; ++l) {
+              double s = 0;
+              for (int g = 0; g < n; ++g)
+                s += A.rho[((size_t)g * A.dim + i) * A.dim + j] * B.rho[((size_t)g * B.dim + k) * B.dim + l];
+              s *= double(A.dim) / n;
+              double ref = (x == y && i == k && j == l) ? 1.0 : 0.0;
+              worst = std::max(worst, std::fabs(s - ref));
+            }
+    }
+  return worst;
+}
+
+void compute_irreps(Group& G) {
+  const int n = G.order;
+  G.irreps_computed = false;
+  G.irreps.clear();
+  if (n > 1024) return;
+  const int nclass = (int)G.classes.size();
+  std::vector<int> rep_of_class(nclass);
+  for (int c = 0; c < nclass; ++c) rep_of_class[c] = G.classes[c][0];
+
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    uint64_t st = 0x1234ABCDull + 7919ull * attempt;
+    std::vector<double> c(n);
+    for (int g = 0; g < n; ++g) c[g] = (double)(splitmix_next(st) >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+    std::vector<double> S((size_t)n * n);
+    for (int x = 0; x < n; ++x)
+      for (int y = 0; y < n; ++y)
+        S[(size_t)x * n + y] = c[G.idx_mul(G.inv[x], y)] + c[G.idx_mul(G.inv[y], x)];
+    std::vector<double> Q;
+    std::vector<double> w = jacobi_eigh(S, n, Q);
+    double spread = w.back() - w.front();
+    double tol = 1e-7 * std::max(1.0, spread);
+    std::vector<std::pair<int, int>> clusters;
+    int start = 0;
+    for (int i = 1; i <= n; ++i)
+      if (i == n || w[i] - w[i - 1] > tol) { clusters.push_back({start, i}); start = i; }
+
+    bool complete = true;
+    std::map<std::vector<long long>, Irrep> found;
+    std::vector<double> chi(n);
+    for (auto [a, b] : clusters) {
+      const int m = b - a;
+      // chi(g) = sum_i sum_x Q[x][a+i] Q[g^-1 x][a+i]
+      for (int g = 0; g < n; ++g) {
+        int gi = G.inv[g];
+        double s = 0;
+        for (int x = 0; x < n; ++x) {
+          const double* qx = &Q[(size_t)x * n + a];
+          const double* qy = &Q[(size_t)G.idx_mul(gi, x) * n + a];
+          for (int i = 0; i < m; ++i) s += qx[i] * qy[i];
+        }
+        chi[g] = s;
+      }
+      double nrm = 0;
+      for (int g = 0; g < n; ++g) nrm += chi[g] * chi[g];
+      if (std::fabs(nrm / n - 1.0) > 1e-6) { complete = false; continue; }
+      std::vector<long long> key(nclass);
+      for (int cc = 0; cc < nclass; ++cc) key[cc] = std::llround(chi[rep_of_class[cc]] * 1e6);
+      if (found.count(key)) continue;
+      Irrep ir;
+      ir.dim = m;
+      ir.rho.assign((size_t)n * m * m, 0.0);
+      for (int g = 0; g < n; ++g) {
+        int gi = G.inv[g];
+        double* rg = &ir.rho[(size_t)g * m * m];
+        for (int x = 0; x < n; ++x) {
+          const double* qx = &Q[(size_t)x * n + a];
+          const double* qy = &Q[(size_t)G.idx_mul(gi, x) * n + a];
+          for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) rg[i * m + j] += qx[i] * qy[j];
+        }
+      }
+      ir.chars.resize(nclass);
+      for (int cc = 0; cc < nclass; ++cc) ir.chars[cc] = chi[rep_of_class[cc]];
+      double nu = 0;
+      for (int g = 0; g < n; ++g) nu += chi[G.idx_mul(g, g)];
+      ir.indicator = (int)std::lround(nu / n);
+      found.emplace(key, std::move(ir));
+    }
+    std::vector<Irrep> irs;
+    for (auto& kv : found) irs.push_back(std::move(kv.second));
+    std::sort(irs.begin(), irs.end(), [&](const Irrep& x, const Irrep& y) {
+      if (x.dim != y.dim) return x.dim < y.dim;
+      for (int cc = 0; cc < nclass; ++cc) {
+        long long a = std::llround(x.chars[cc] * 1e9), b = std::llround(y.chars[cc] * 1e9);
+        if (a != b) return a > b;
+      }
+      return false;
+    });
+    int sumsq = 0;
+    for (auto& ir : irs) sumsq += ir.dim * ir.dim;
+    std::vector<const Irrep*> ptrs;
+    for (auto& ir : irs) ptrs.push_back(&ir);
+    double res = verify_irreps(G, ptrs);
+    if (res > 1e-9) continue;  // retry with another random element
+    if (complete && sumsq != n) continue;
+    G.irreps = std::move(irs);
+    G.all_real = complete && sumsq == n;
+    G.max_residual = res;
+    G.irreps_computed = true;
+    return;
+  }
+  fail(FTLM_ERR_IRREPS_FAILED, "irrep construction did not pass verification");
+}
+
+}  // namespace ftlm

@@ -1,0 +1,122 @@
+// Internal objects behind the opaque C handles.
+#pragma once
+
+#include <atomic>
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "group.h"
+
+struct ftlm_group {
+  std::shared_ptr<ftlm::Group> G;
+};
+
+namespace ftlm {
+
+// Irreducible-representation-independent tables of one M sector.
+struct Sector {
+  std::shared_ptr<const Group> G;
+  // cluster
+  int N = 0, two_s = 0, d = 0, bits = 0, two_M = 0, A = 0;
+  std::vector<int32_t> bonds;   // 2 * nbonds
+  std::vector<double> J;
+  int nbonds = 0;
+  bool wide = false;            // labels need 64 bits (N * bits > 32)
+  int nch = 0;                  // 4-bit chunks of a packed label
+  uint64_t D_M = 0, n_reps = 0, n_words = 0;
+  int hv_mode = FTLM_HV_ENTRIES;
+  // host copies of small tables
+  std::vector<uint64_t> cnt;    // (N+1) x (Amax+1) digit-sum counts
+  int cnt_stride = 0;
+  std::vector<uint16_t> stab_size;               // per stabilizer id
+  std::vector<std::vector<int32_t>> stab_elems;  // per stabilizer id
+  int32_t n_stab = 0;
+  // device tables
+  DevBuf<uint64_t> d_tab;       // |G| x nch x 16 words (uint32 or uint64 payload)
+  DevBuf<uint64_t> d_cnt;
+  DevBuf<uint64_t> d_rank_bits; // bitmap over sector ranks
+  DevBuf<uint32_t> d_rank_base; // representatives before each word
+  DevBuf<uint64_t> d_reps;      // packed labels, ascending
+  DevBuf<uint16_t> d_stab_id;
+  DevBuf<double> d_ediag;       // Eq. (16) per representative
+  DevBuf<uint64_t> d_row_ptr;   // entries of representative i: [row_ptr[i], row_ptr[i+1])
+  DevBuf<uint64_t> d_entries;   // idx | h << 32 | flip << 48
+  uint64_t n_entries = 0;
+  DevBuf<int32_t> d_bonds;
+  DevBuf<double> d_J;
+  DevBuf<double> d_fac;         // [2][d][d] ladder products (J = 1)
+  int64_t device_bytes() const {
+    return (int64_t)(d_tab.bytes() + d_cnt.bytes() + d_rank_bits.bytes() + d_rank_base.bytes() +
+                     d_reps.bytes() + d_stab_id.bytes() + d_ediag.bytes() + d_row_ptr.bytes() +
+                     d_entries.bytes() + d_bonds.bytes() + d_J.bytes() + d_fac.bytes());
+  }
+};
+
+struct Block {
+  std::shared_ptr<Sector> sec;  // shared with other blocks of the sector
+  std::shared_ptr<Group> own_group;
+  int irrep = 0, row = 0, dg = 0;
+  uint64_t D = 0, n_active = 0;
+  std::vector<double> rho;      // |G| x d x d (the irrep used)
+  std::vector<uint8_t> n_stab;  // n_Gamma per stabilizer id
+  std::vector<double> V_stab;   // per stabilizer: d x d (columns k < n valid, rest 0)
+  std::vector<double> L_stab;   // orbit length per stabilizer id
+  std::vector<uint8_t> trivial; // V = identity and n = d
+  // device
+  DevBuf<uint64_t> d_meta;      // per representative: offset | stab_id << 48
+  DevBuf<double> d_rhoT64;      // [g][beta][gamma] = rho(g)[gamma][beta]
+  DevBuf<float> d_rhoT32;
+  DevBuf<double> d_V64;         // [s][gamma][k]
+  DevBuf<float> d_V32;
+  DevBuf<double> d_stabf64;     // [s]: {n, sqrtL, 1/sqrtL, trivial}
+  DevBuf<float> d_stabf32;
+  int64_t device_bytes() const {
+    return (int64_t)(d_meta.bytes() + d_rhoT64.bytes() + d_rhoT32.bytes() + d_V64.bytes() +
+                     d_V32.bytes() + d_stabf64.bytes() + d_stabf32.bytes()) + sec->device_bytes();
+  }
+};
+
+std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<const Group> G, int two_M,
+                                     const ftlm_opts* opts);
+void sector_canonicalize(const Sector& s, const uint64_t* labels, int64_t n, uint64_t* rep, int32_t* h,
+                         int64_t* index, hipStream_t stream);
+std::vector<uint64_t> sector_export_labels(const Sector& s);
+
+std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int row, const ftlm_opts* opts);
+
+// H.V (Eq. 15 in gather form + Eq. 16).  Optional Lanczos epilogue: when
+// lz != nullptr the output is w = s_j H q_j - bs_j q_prev written over q_prev
+// (== Y) and per-workgroup FP64 partial sums of q_j . w are produced.
+struct LanczosEpilogue {
+  const double* scal;   // per vector: [s_j, beta_j * s_{j-1}] pairs
+  double* partials;     // n_groups x nvec
+  int n_groups;
+};
+void apply_hv(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t stream,
+              const LanczosEpilogue* lz = nullptr);
+int hv_partial_groups(const Block& b, int nvec);
+
+void run_lanczos(Block& b, int R, int steps, uint64_t seed, int storage, int dist, double* alpha,
+                 double* beta, int32_t* nsteps, hipStream_t stream);
+
+void tridiag_ritz(const double* alpha, const double* beta, int n, double* theta, double* weight);
+void observables(const ftlm_ritz* blocks, int nb, const double* T, int nT, double g, double* E, double* C,
+                 double* chi, double* logZ);
+
+uint64_t chain_key(uint64_t seed, int two_M, int irrep, int row, int chain);
+
+// exclusive prefix sum over n values of a device array (uint64 in/out, in-place allowed)
+void scan_exclusive_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* total, hipStream_t s);
+
+}  // namespace ftlm
+
+struct ftlm_sector {
+  std::shared_ptr<ftlm::Sector> s;
+};
+
+struct ftlm_block {
+  std::unique_ptr<ftlm::Block> b;
+};

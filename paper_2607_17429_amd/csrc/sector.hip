@@ -1,0 +1,659 @@
+// Irrep-independent preprocessing of one magnetization sector (paper
+// Section 3): orbit representatives, stabilizers, the rank lookup, Eq. (16)
+// diagonal energies and the per-flip entry table (target representative,
+// connecting element, flip), all built by GPU kernels.
+//
+// Representatives (Section 2.3: the smallest label of each orbit) come from a
+// sweep over the sector in rank order: thread t owns ranks [64t, 64t + 64),
+// unranks the first label, steps through the next 63 in label order and sets
+// bit k of word t when no group element maps the label to a smaller one.  The
+// bitmap over sector ranks, with per-word prefix counts, is also the lookup:
+// index(r) = base[rank(r) >> 6] + popcount of the lower bits of that word.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <unordered_map>
+
+#include "device.h"
+#include "dispatch.h"
+#include "internal.h"
+
+namespace ftlm {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename W, bool LDS>
+__device__ __forceinline__ const W* stage_table(const W* g_tab, uint32_t n_words, W* smem) {
+  if constexpr (!LDS) {
+    return g_tab;
+  } else {
+    for (uint32_t i = threadIdx.x; i < n_words; i += blockDim.x) smem[i] = g_tab[i];
+    __syncthreads();
+    return smem;
+  }
+}
+
+struct SecArgs {
+  const void* tab;
+  const uint64_t* cnt;
+  int cnt_stride;
+  int N, b, d, A, G;
+  uint64_t D_M, n_words, n_reps;
+  uint32_t tab_words;
+};
+
+// ---- representative sweep --------------------------------------------------
+template <typename W, int NCH, bool LDS>
+__global__ void __launch_bounds__(kThreads) k_enum(SecArgs a, uint64_t* __restrict__ bits_out) {
+  extern __shared__ uint64_t smem_raw[];
+  const W* tab = stage_table<W, LDS>((const W*)a.tab, a.tab_words, (W*)smem_raw);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.n_words; w += stride) {
+    W x = dev::sector_unrank<W>(w * 64, a.N, a.b, a.d, a.A, a.cnt, a.cnt_stride);
+    uint64_t bits = 0;
+    for (int k = 0; k < 64; ++k) {
+      const bool valid = w * 64 + k < a.D_M;
+      int off[NCH];
+      dev::chunk_offsets<W, NCH>(x, off);
+      bool smaller = false;
+      for (int g = 1; g < a.G; ++g) {
+        W img = dev::permute<W, NCH>(tab, g, off);
+        smaller |= img < x;
+        if ((g & 3) == 3 && __all(smaller || !valid)) break;
+      }
+      if (valid && !smaller) bits |= 1ull << k;
+      x = dev::sector_next<W>(x, a.N, a.b, a.d);
+    }
+    bits_out[w] = bits;
+  }
+}
+
+__global__ void k_popcount(const uint64_t* __restrict__ bits, uint64_t* __restrict__ out, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = __popcll(bits[i]);
+}
+
+__global__ void k_to_u32(const uint64_t* __restrict__ in, uint32_t* __restrict__ out, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    out[i] = (uint32_t)in[i];
+}
+
+template <typename W>
+__global__ void __launch_bounds__(kThreads) k_extract(SecArgs a, const uint64_t* __restrict__ bits,
+                                                     const uint32_t* __restrict__ base, uint64_t* __restrict__ reps) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.n_words; w += stride) {
+    uint64_t m = bits[w];
+    if (!m) continue;
+    W x = dev::sector_unrank<W>(w * 64, a.N, a.b, a.d, a.A, a.cnt, a.cnt_stride);
+    uint64_t j = base[w];
+    const int top = 63 - __clzll(m);
+    for (int k = 0; k <= top; ++k) {
+      if ((m >> k) & 1) reps[j++] = (uint64_t)x;
+      if (k < top) x = dev::sector_next<W>(x, a.N, a.b, a.d);
+    }
+  }
+}
+
+// ---- stabilizers -----------------------------------------------------------
+// flag[i] = 1 when some g != e fixes representative i.
+template <typename W, int NCH, bool LDS>
+__global__ void __launch_bounds__(kThreads) k_stab_flag(SecArgs a, const uint64_t* __restrict__ reps,
+                                                       uint64_t* __restrict__ flag) {
+  extern __shared__ uint64_t smem_raw[];
+  const W* tab = stage_table<W, LDS>((const W*)a.tab, a.tab_words, (W*)smem_raw);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n_reps; i += stride) {
+    const W r = (W)reps[i];
+    int off[NCH];
+    dev::chunk_offsets<W, NCH>(r, off);
+    bool fixed = false;
+    for (int g = 1; g < a.G; ++g) {
+      fixed |= dev::permute<W, NCH>(tab, g, off) == r;
+      if ((g & 3) == 3 && __all(fixed)) break;
+    }
+    flag[i] = fixed ? 1 : 0;
+  }
+}
+
+// Full stabilizer masks of the representatives with a non-trivial stabilizer,
+// written compacted (pos = exclusive scan of the flags, pos[n_reps] = count).
+template <typename W, int NCH, bool LDS>
+__global__ void __launch_bounds__(kThreads) k_stab_mask(SecArgs a, const uint64_t* __restrict__ reps,
+                                                       const uint64_t* __restrict__ pos, int mw,
+                                                       uint64_t* __restrict__ masks, uint64_t* __restrict__ idx_out) {
+  extern __shared__ uint64_t smem_raw[];
+  const W* tab = stage_table<W, LDS>((const W*)a.tab, a.tab_words, (W*)smem_raw);
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n_reps; i += stride) {
+    const uint64_t p = pos[i];
+    if (pos[i + 1] == p) continue;
+    const W r = (W)reps[i];
+    int off[NCH];
+    dev::chunk_offsets<W, NCH>(r, off);
+    for (int wq = 0; wq < mw; ++wq) {
+      uint64_t m = 0;
+      for (int t = 0; t < 64; ++t) {
+        int g = wq * 64 + t;
+        if (g >= a.G) break;
+        if (dev::permute<W, NCH>(tab, g, off) == r) m |= 1ull << t;
+      }
+      masks[p * mw + wq] = m;
+    }
+    idx_out[p] = i;
+  }
+}
+
+__global__ void k_first_trivial(const uint64_t* __restrict__ pos, uint64_t n, unsigned long long* out) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+    if (pos[i + 1] == pos[i]) atomicMin(out, (unsigned long long)i);
+}
+
+__global__ void k_assign_stab(const uint64_t* __restrict__ pos, uint64_t n, const uint16_t* __restrict__ ids_nt,
+                              uint16_t trivial_id, uint16_t* __restrict__ stab_id) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+    const uint64_t p = pos[i];
+    stab_id[i] = (pos[i + 1] != p) ? ids_nt[p] : trivial_id;
+  }
+}
+
+// ---- flips (Eq. 3) -----------------------------------------------------------
+struct FlipArgs {
+  const int32_t* bonds;
+  const double* J;
+  int nbonds;
+};
+
+template <typename W>
+__device__ __forceinline__ bool admissible(W p, int cand, const FlipArgs& f, int b, int d, W mask) {
+  const int bond = cand >> 1;
+  const int i = f.bonds[2 * bond], j = f.bonds[2 * bond + 1];
+  const int ai = dev::digit(p, i, b, mask), aj = dev::digit(p, j, b, mask);
+  return (cand & 1) ? (ai > 0 && aj < d - 1) : (ai < d - 1 && aj > 0);
+}
+
+template <typename W>
+__device__ __forceinline__ W apply_flip(W p, int cand, const FlipArgs& f, int b) {
+  const int bond = cand >> 1;
+  const int i = f.bonds[2 * bond], j = f.bonds[2 * bond + 1];
+  const W ui = W(1) << (i * b), uj = W(1) << (j * b);
+  return (cand & 1) ? (p - ui + uj) : (p + ui - uj);
+}
+
+template <typename W>
+__device__ __forceinline__ int next_admissible(W p, int cur, int ncand, const FlipArgs& f, int b, int d, W mask) {
+  for (int c = cur + 1; c < ncand; ++c)
+    if (admissible(p, c, f, b, d, mask)) return c;
+  return -1;
+}
+
+template <typename W>
+__global__ void __launch_bounds__(kThreads) k_entry_count(SecArgs a, FlipArgs f, const uint64_t* __restrict__ reps,
+                                                         uint64_t* __restrict__ counts, double* __restrict__ ediag) {
+  const W mask = (W(1) << a.b) - 1;
+  const double s = 0.5 * (a.d - 1);
+  const int ncand = 2 * f.nbonds;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n_reps; i += stride) {
+    const W p = (W)reps[i];
+    uint64_t c = 0;
+    for (int q = 0; q < ncand; ++q) c += admissible(p, q, f, a.b, a.d, mask) ? 1 : 0;
+    counts[i] = c;
+    double e = 0;
+    for (int bnd = 0; bnd < f.nbonds; ++bnd) {
+      const double mi = dev::digit(p, f.bonds[2 * bnd], a.b, mask) - s;
+      const double mj = dev::digit(p, f.bonds[2 * bnd + 1], a.b, mask) - s;
+      e += f.J[bnd] * mi * mj;
+    }
+    ediag[i] = e;
+  }
+}
+
+template <typename W>
+__device__ __forceinline__ bool lookup(W r, const SecArgs& a, const uint64_t* __restrict__ bits,
+                                       const uint32_t* __restrict__ base, uint64_t& idx) {
+  const uint64_t rk = dev::sector_rank<W>(r, a.N, a.b, a.d, a.A, a.cnt, a.cnt_stride);
+  if (rk >= a.D_M) return false;
+  const uint64_t w = rk >> 6;
+  const uint64_t m = bits[w];
+  const int k = (int)(rk & 63);
+  idx = base[w] + (uint64_t)__popcll(m & ((1ull << k) - 1));
+  return (m >> k) & 1;
+}
+
+// One lane per representative; in round t every lane canonicalizes its t-th
+// admissible flip, so all lanes walk the group elements together.
+template <typename W, int NCH, bool LDS>
+__global__ void __launch_bounds__(kThreads) k_entry_fill(SecArgs a, FlipArgs f, const uint64_t* __restrict__ reps,
+                                                        const uint64_t* __restrict__ row_ptr,
+                                                        const uint64_t* __restrict__ bits,
+                                                        const uint32_t* __restrict__ base,
+                                                        uint64_t* __restrict__ entries) {
+  extern __shared__ uint64_t smem_raw[];
+  const W* tab = stage_table<W, LDS>((const W*)a.tab, a.tab_words, (W*)smem_raw);
+  const W mask = (W(1) << a.b) - 1;
+  const int ncand = 2 * f.nbonds;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t n_iter = (a.n_reps + stride - 1) / stride;  // same trip count on every lane
+  for (uint64_t it = 0; it < n_iter; ++it) {
+    const uint64_t i = it * stride + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i < a.n_reps;
+    const W p = live ? (W)reps[i] : W(0);
+    uint64_t out = live ? row_ptr[i] : 0;
+    int cur = live ? next_admissible<W>(p, -1, ncand, f, a.b, a.d, mask) : -1;
+    while (__any(cur >= 0)) {
+      const W x = cur >= 0 ? apply_flip<W>(p, cur, f, a.b) : p;
+      W r;
+      int h;
+      dev::canon_min<W, NCH>(x, tab, a.G, r, h);
+      if (cur >= 0) {
+        uint64_t idx = 0;
+        bool ok = lookup<W>(r, a, bits, base, idx);
+        // a canonical label of the sector is always a representative
+        entries[out++] = (ok ? idx : 0xFFFFFFFFull) | ((uint64_t)h << 32) | ((uint64_t)cur << 48);
+        cur = next_admissible<W>(p, cur, ncand, f, a.b, a.d, mask);
+      }
+    }
+  }
+}
+
+// ---- orbit search for arbitrary labels (test / export entry point) ---------
+template <typename W, int NCH, bool LDS>
+__global__ void __launch_bounds__(kThreads) k_canon_labels(SecArgs a, const uint64_t* __restrict__ bits,
+                                                          const uint32_t* __restrict__ base,
+                                                          const uint64_t* __restrict__ labels, int64_t n,
+                                                          uint64_t* __restrict__ rep_out, int32_t* __restrict__ h_out,
+                                                          int64_t* __restrict__ idx_out) {
+  extern __shared__ uint64_t smem_raw[];
+  const W* tab = stage_table<W, LDS>((const W*)a.tab, a.tab_words, (W*)smem_raw);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t n_iter = (n + stride - 1) / stride;
+  for (int64_t it = 0; it < n_iter; ++it) {
+    const int64_t i = it * stride + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = i < n;
+    uint64_t lab = live ? labels[i] : 0;
+    // Eq. (2) label -> packed digits
+    W x = 0;
+    int sum = 0;
+    bool in_range = true;
+    {
+      uint64_t y = lab;
+      for (int k = 0; k < a.N; ++k) {
+        int dg = (int)(y % (uint64_t)a.d);
+        y /= (uint64_t)a.d;
+        x |= W(dg) << (k * a.b);
+        sum += dg;
+      }
+      in_range = (y == 0) && (sum == a.A);
+    }
+    W r;
+    int h;
+    dev::canon_min<W, NCH>(x, tab, a.G, r, h);
+    if (live) {
+      uint64_t idx = 0;
+      bool ok = in_range && lookup<W>(r, a, bits, base, idx);
+      // packed -> Eq. (2)
+      uint64_t outlab = 0;
+      const W mask = (W(1) << a.b) - 1;
+      for (int k = a.N - 1; k >= 0; --k) outlab = outlab * (uint64_t)a.d + (uint64_t)dev::digit(r, k, a.b, mask);
+      rep_out[i] = in_range ? outlab : 0;
+      h_out[i] = in_range ? h : -1;
+      idx_out[i] = ok ? (int64_t)idx : -1;
+    }
+  }
+}
+
+unsigned grid_for(uint64_t n, int threads = kThreads, unsigned cap = 65536u * 4) {
+  uint64_t g = (n + threads - 1) / threads;
+  if (g < 1) g = 1;
+  return (unsigned)std::min<uint64_t>(g, cap);
+}
+
+int max_lds_bytes() {
+  static int v = -1;
+  if (v < 0) {
+    int dev = 0, x = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&x, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && x > 0)
+      v = std::min(x, 65536);
+    else
+      v = 65536;
+  }
+  return v;
+}
+
+}  // namespace
+
+std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<const Group> G, int two_M,
+                                     const ftlm_opts* opts) {
+  if (!cl || !G) fail(FTLM_ERR_INVALID_ARG, "null cluster or group");
+  auto S = std::make_shared<Sector>();
+  Sector& s = *S;
+  s.G = G;
+  s.N = cl->N;
+  s.two_s = cl->two_s;
+  s.two_M = two_M;
+  if (s.N != G->N) fail(FTLM_ERR_INVALID_ARG, "cluster N differs from the group's N");
+  if (s.two_s < 1 || s.two_s > 62) fail(FTLM_ERR_INVALID_ARG, "two_s must be in 1..62");
+  if (G->order > 1024) fail(FTLM_ERR_GROUP_TOO_LARGE, "sector tables support |G| <= 1024");
+  s.d = s.two_s + 1;
+  s.bits = 0;
+  while ((1 << s.bits) < s.d) ++s.bits;
+  if (s.N * s.bits > 64) fail(FTLM_ERR_UNSUPPORTED, "packed labels need more than 64 bits");
+  s.wide = s.N * s.bits > 32;
+  s.nch = nch_bucket((s.N * s.bits + 3) / 4);
+  if (cl->nbonds < 0 || (cl->nbonds > 0 && !cl->bonds)) fail(FTLM_ERR_INVALID_ARG, "bad bond list");
+  if (cl->nbonds > 16000) fail(FTLM_ERR_INVALID_ARG, "too many bonds");
+  s.nbonds = cl->nbonds;
+  s.bonds.assign(cl->bonds, cl->bonds + 2 * (size_t)cl->nbonds);
+  s.J.resize(s.nbonds);
+  std::map<std::pair<int, int>, double> bondmap;
+  for (int b = 0; b < s.nbonds; ++b) {
+    int i = s.bonds[2 * b], j = s.bonds[2 * b + 1];
+    if (i < 0 || j < 0 || i >= s.N || j >= s.N || i == j) fail(FTLM_ERR_INVALID_ARG, "bond site out of range");
+    s.J[b] = cl->J ? cl->J[b] : 1.0;
+    bondmap[{std::min(i, j), std::max(i, j)}] += s.J[b];
+  }
+  // bond invariance under every group element (weighted, Section 3)
+  for (int g = 0; g < G->order; ++g) {
+    const int32_t* p = &G->perms[(size_t)g * s.N];
+    for (auto& kv : bondmap) {
+      int a = p[kv.first.first], c = p[kv.first.second];
+      auto it = bondmap.find({std::min(a, c), std::max(a, c)});
+      if (it == bondmap.end() || std::fabs(it->second - kv.second) > 1e-12 * std::max(1.0, std::fabs(kv.second)))
+        fail(FTLM_ERR_BONDS_NOT_INVARIANT, "bond list is not invariant under the group");
+    }
+  }
+  // digit-sum counts
+  const int Amax = s.N * (s.d - 1);
+  s.cnt_stride = Amax + 1;
+  s.cnt.assign((size_t)(s.N + 1) * s.cnt_stride, 0);
+  s.cnt[0] = 1;
+  for (int k = 1; k <= s.N; ++k)
+    for (int v = 0; v <= Amax; ++v) {
+      unsigned __int128 c = 0;
+      for (int a = 0; a < s.d && a <= v; ++a) c += s.cnt[(size_t)(k - 1) * s.cnt_stride + v - a];
+      s.cnt[(size_t)k * s.cnt_stride + v] = (uint64_t)c;
+    }
+  const int A2 = s.N * s.two_s + two_M;
+  hipStream_t st = nullptr;
+  if (A2 % 2 != 0 || A2 < 0 || A2 / 2 > Amax) {
+    s.A = 0;
+    s.D_M = 0;
+  } else {
+    s.A = A2 / 2;
+    s.D_M = s.cnt[(size_t)s.N * s.cnt_stride + s.A];
+  }
+  s.n_words = (s.D_M + 63) / 64;
+  // permutation chunk tables
+  const int G_ = G->order;
+  const size_t tab_words = (size_t)G_ * s.nch * 16;
+  {
+    std::vector<uint64_t> tab(tab_words, 0);
+    for (int g = 0; g < G_; ++g) {
+      const int32_t* p = &G->perms[(size_t)g * s.N];
+      for (int c = 0; c < s.nch; ++c)
+        for (int v = 0; v < 16; ++v) {
+          uint64_t img = 0;
+          for (int t = 0; t < 4; ++t) {
+            if (!((v >> t) & 1)) continue;
+            int bit = 4 * c + t;
+            if (bit >= s.N * s.bits) continue;
+            int site = bit / s.bits, sub = bit % s.bits;
+            img |= 1ull << (p[site] * s.bits + sub);
+          }
+          tab[((size_t)g * s.nch + c) * 16 + v] = img;
+        }
+    }
+    if (!s.wide) {
+      std::vector<uint32_t> t32(tab_words);
+      for (size_t i = 0; i < tab_words; ++i) t32[i] = (uint32_t)tab[i];
+      s.d_tab.alloc((tab_words + 1) / 2);
+      FTLM_HIP(hipMemcpy(s.d_tab.p, t32.data(), tab_words * 4, hipMemcpyHostToDevice));
+    } else {
+      s.d_tab.upload(tab);
+    }
+  }
+  s.d_cnt.upload(s.cnt);
+  s.d_bonds.upload(s.bonds);
+  s.d_J.upload(s.J);
+  {
+    std::vector<double> fac(2 * s.d * s.d);
+    const double sp = 0.5 * s.two_s, ss = sp * (sp + 1);
+    for (int ai = 0; ai < s.d; ++ai)
+      for (int aj = 0; aj < s.d; ++aj) {
+        double mi = ai - sp, mj = aj - sp;
+        // sign 0: s_i^+ s_j^-; sign 1: s_i^- s_j^+ (Eq. 3 with J = 1)
+        fac[(0 * s.d + ai) * s.d + aj] = 0.5 * std::sqrt(std::max(0.0, ss - mi * (mi + 1))) *
+                                         std::sqrt(std::max(0.0, ss - mj * (mj - 1)));
+        fac[(1 * s.d + ai) * s.d + aj] = 0.5 * std::sqrt(std::max(0.0, ss - mi * (mi - 1))) *
+                                         std::sqrt(std::max(0.0, ss - mj * (mj + 1)));
+      }
+    s.d_fac.upload(fac);
+  }
+  const size_t wbytes = s.wide ? 8 : 4;
+  const size_t tab_bytes = tab_words * wbytes;
+  const bool lds = tab_bytes <= (size_t)max_lds_bytes();
+  SecArgs a{};
+  a.tab = s.d_tab.p;
+  a.cnt = s.d_cnt.p;
+  a.cnt_stride = s.cnt_stride;
+  a.N = s.N;
+  a.b = s.bits;
+  a.d = s.d;
+  a.A = s.A;
+  a.G = G_;
+  a.D_M = s.D_M;
+  a.n_words = s.n_words;
+  a.tab_words = (uint32_t)tab_words;
+  const size_t shm = lds ? tab_bytes : 0;
+  FlipArgs f{s.d_bonds.p, s.d_J.p, s.nbonds};
+
+  if (s.D_M == 0) {
+    s.n_reps = 0;
+    s.d_row_ptr.alloc(1);
+    FTLM_HIP(hipMemset(s.d_row_ptr.p, 0, sizeof(uint64_t)));
+    return S;
+  }
+  const int64_t limit = opts ? opts->hbm_limit_bytes : 0;
+  // representatives
+  s.d_rank_bits.alloc(s.n_words);
+  FTLM_DISPATCH_NCH(s.nch, {
+    if (lds)
+      hipLaunchKernelGGL((k_enum<W, NCH, true>), dim3(grid_for(s.n_words)), dim3(kThreads), shm, st, a, s.d_rank_bits.p);
+    else
+      hipLaunchKernelGGL((k_enum<W, NCH, false>), dim3(grid_for(s.n_words)), dim3(kThreads), 0, st, a, s.d_rank_bits.p);
+  });
+  FTLM_HIP(hipGetLastError());
+  {
+    DevBuf<uint64_t> tmp;
+    tmp.alloc(s.n_words);
+    hipLaunchKernelGGL(k_popcount, dim3(grid_for(s.n_words)), dim3(kThreads), 0, st, s.d_rank_bits.p, tmp.p, s.n_words);
+    uint64_t total = 0;
+    scan_exclusive_u64(tmp.p, tmp.p, s.n_words, &total, st);
+    if (total >= 0xFFFFFFFFull) fail(FTLM_ERR_UNSUPPORTED, "more than 2^32 - 1 representatives");
+    s.n_reps = total;
+    s.d_rank_base.alloc(s.n_words);
+    hipLaunchKernelGGL(k_to_u32, dim3(grid_for(s.n_words)), dim3(kThreads), 0, st, tmp.p, s.d_rank_base.p, s.n_words);
+    FTLM_HIP(hipGetLastError());
+    FTLM_HIP(hipStreamSynchronize(st));
+  }
+  a.n_reps = s.n_reps;
+  s.d_reps.alloc(s.n_reps);
+  FTLM_DISPATCH_NCH(s.nch, {
+    hipLaunchKernelGGL((k_extract<W>), dim3(grid_for(s.n_words)), dim3(kThreads), 0, st, a, s.d_rank_bits.p,
+                       s.d_rank_base.p, s.d_reps.p);
+  });
+  FTLM_HIP(hipGetLastError());
+
+  // stabilizers: flags -> compaction -> host interning in first-appearance order
+  {
+    DevBuf<uint64_t> pos;
+    pos.alloc(s.n_reps + 1);
+    FTLM_HIP(hipMemsetAsync(pos.p + s.n_reps, 0, sizeof(uint64_t), st));
+    FTLM_DISPATCH_NCH(s.nch, {
+      if (lds)
+        hipLaunchKernelGGL((k_stab_flag<W, NCH, true>), dim3(grid_for(s.n_reps)), dim3(kThreads), shm, st, a, s.d_reps.p, pos.p);
+      else
+        hipLaunchKernelGGL((k_stab_flag<W, NCH, false>), dim3(grid_for(s.n_reps)), dim3(kThreads), 0, st, a, s.d_reps.p, pos.p);
+    });
+    FTLM_HIP(hipGetLastError());
+    uint64_t n_nt = 0;
+    scan_exclusive_u64(pos.p, pos.p, s.n_reps + 1, &n_nt, st);
+    const int mw = (G_ + 63) / 64;
+    DevBuf<uint64_t> masks, idx;
+    masks.alloc(std::max<uint64_t>(n_nt, 1) * mw);
+    idx.alloc(std::max<uint64_t>(n_nt, 1));
+    if (n_nt) {
+      FTLM_DISPATCH_NCH(s.nch, {
+        if (lds)
+          hipLaunchKernelGGL((k_stab_mask<W, NCH, true>), dim3(grid_for(s.n_reps)), dim3(kThreads), shm, st, a, s.d_reps.p,
+                             pos.p, mw, masks.p, idx.p);
+        else
+          hipLaunchKernelGGL((k_stab_mask<W, NCH, false>), dim3(grid_for(s.n_reps)), dim3(kThreads), 0, st, a, s.d_reps.p,
+                             pos.p, mw, masks.p, idx.p);
+      });
+      FTLM_HIP(hipGetLastError());
+    }
+    DevBuf<unsigned long long> first;
+    first.alloc(1);
+    unsigned long long init = ~0ull;
+    FTLM_HIP(hipMemcpyAsync(first.p, &init, sizeof(init), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(k_first_trivial, dim3(grid_for(s.n_reps)), dim3(kThreads), 0, st, pos.p, s.n_reps, first.p);
+    FTLM_HIP(hipGetLastError());
+    std::vector<uint64_t> h_masks(n_nt * mw), h_idx(n_nt);
+    if (n_nt) {
+      FTLM_HIP(hipMemcpyAsync(h_masks.data(), masks.p, n_nt * mw * 8, hipMemcpyDeviceToHost, st));
+      FTLM_HIP(hipMemcpyAsync(h_idx.data(), idx.p, n_nt * 8, hipMemcpyDeviceToHost, st));
+    }
+    unsigned long long first_trivial = 0;
+    FTLM_HIP(hipMemcpyAsync(&first_trivial, first.p, sizeof(first_trivial), hipMemcpyDeviceToHost, st));
+    FTLM_HIP(hipStreamSynchronize(st));
+    std::map<std::vector<uint64_t>, uint16_t> ids;
+    std::vector<uint64_t> trivial_mask(mw, 0);
+    trivial_mask[0] = 1;  // identity only
+    std::vector<uint16_t> ids_nt(std::max<uint64_t>(n_nt, 1), 0);
+    auto intern = [&](const std::vector<uint64_t>& m) -> uint16_t {
+      auto it = ids.find(m);
+      if (it != ids.end()) return it->second;
+      if (ids.size() >= 65535) fail(FTLM_ERR_UNSUPPORTED, "too many distinct stabilizers");
+      uint16_t id = (uint16_t)ids.size();
+      ids.emplace(m, id);
+      std::vector<int32_t> el;
+      for (int g = 0; g < G_; ++g)
+        if ((m[g / 64] >> (g % 64)) & 1) el.push_back(g);
+      s.stab_elems.push_back(el);
+      s.stab_size.push_back((uint16_t)el.size());
+      return id;
+    };
+    const bool has_trivial = first_trivial != ~0ull;
+    bool trivial_done = !has_trivial;
+    uint16_t trivial_id = 0;
+    for (uint64_t q = 0; q < n_nt; ++q) {
+      if (!trivial_done && h_idx[q] > first_trivial) {
+        trivial_id = intern(trivial_mask);
+        trivial_done = true;
+      }
+      std::vector<uint64_t> m(h_masks.begin() + q * mw, h_masks.begin() + (q + 1) * mw);
+      ids_nt[q] = intern(m);
+    }
+    if (!trivial_done) trivial_id = intern(trivial_mask);
+    s.n_stab = (int32_t)ids.size();
+    DevBuf<uint16_t> d_ids;
+    d_ids.upload(ids_nt);
+    s.d_stab_id.alloc(s.n_reps);
+    hipLaunchKernelGGL(k_assign_stab, dim3(grid_for(s.n_reps)), dim3(kThreads), 0, st, pos.p, s.n_reps, d_ids.p,
+                       trivial_id, s.d_stab_id.p);
+    FTLM_HIP(hipGetLastError());
+    FTLM_HIP(hipStreamSynchronize(st));
+  }
+
+  // diagonal energies and the entry table
+  s.d_ediag.alloc(s.n_reps);
+  s.d_row_ptr.alloc(s.n_reps + 1);
+  FTLM_HIP(hipMemsetAsync(s.d_row_ptr.p + s.n_reps, 0, sizeof(uint64_t), st));
+  FTLM_DISPATCH_NCH(s.nch, {
+    hipLaunchKernelGGL((k_entry_count<W>), dim3(grid_for(s.n_reps)), dim3(kThreads), 0, st, a, f, s.d_reps.p,
+                       s.d_row_ptr.p, s.d_ediag.p);
+  });
+  FTLM_HIP(hipGetLastError());
+  uint64_t n_ent = 0;
+  scan_exclusive_u64(s.d_row_ptr.p, s.d_row_ptr.p, s.n_reps + 1, &n_ent, st);
+  s.n_entries = n_ent;
+  int mode = opts ? opts->hv_mode : FTLM_HV_AUTO;
+  if (mode == FTLM_HV_AUTO) {
+    size_t free_b = 0, total_b = 0;
+    FTLM_HIP(hipMemGetInfo(&free_b, &total_b));
+    mode = (n_ent * 8 < free_b / 3) ? FTLM_HV_ENTRIES : FTLM_HV_ONTHEFLY;
+  }
+  if (limit > 0 && (int64_t)(s.device_bytes() + (mode == FTLM_HV_ENTRIES ? n_ent * 8 : 0)) > limit)
+    fail(FTLM_ERR_OUT_OF_MEMORY, "sector tables exceed the HBM limit");
+  s.hv_mode = mode;
+  if (mode == FTLM_HV_ENTRIES && n_ent) {
+    s.d_entries.alloc(n_ent);
+    FTLM_DISPATCH_NCH(s.nch, {
+      if (lds)
+        hipLaunchKernelGGL((k_entry_fill<W, NCH, true>), dim3(grid_for(s.n_reps)), dim3(kThreads), shm, st, a, f,
+                           s.d_reps.p, s.d_row_ptr.p, s.d_rank_bits.p, s.d_rank_base.p, s.d_entries.p);
+      else
+        hipLaunchKernelGGL((k_entry_fill<W, NCH, false>), dim3(grid_for(s.n_reps)), dim3(kThreads), 0, st, a, f,
+                           s.d_reps.p, s.d_row_ptr.p, s.d_rank_bits.p, s.d_rank_base.p, s.d_entries.p);
+    });
+    FTLM_HIP(hipGetLastError());
+  }
+  FTLM_HIP(hipStreamSynchronize(st));
+  return S;
+}
+
+void sector_canonicalize(const Sector& s, const uint64_t* labels, int64_t n, uint64_t* rep, int32_t* h,
+                         int64_t* index, hipStream_t st) {
+  if (n < 0 || (n > 0 && (!labels || !rep || !h || !index))) fail(FTLM_ERR_INVALID_ARG, "bad canonicalize arguments");
+  if (n == 0) return;
+  SecArgs a{};
+  a.tab = s.d_tab.p;
+  a.cnt = s.d_cnt.p;
+  a.cnt_stride = s.cnt_stride;
+  a.N = s.N;
+  a.b = s.bits;
+  a.d = s.d;
+  a.A = s.A;
+  a.G = s.G->order;
+  a.D_M = s.D_M;
+  a.n_words = s.n_words;
+  a.n_reps = s.n_reps;
+  const size_t tab_words = (size_t)a.G * s.nch * 16;
+  a.tab_words = (uint32_t)tab_words;
+  const size_t tab_bytes = tab_words * (s.wide ? 8 : 4);
+  const bool lds = tab_bytes <= (size_t)max_lds_bytes();
+  const uint64_t* bits = s.d_rank_bits.p;
+  const uint32_t* base = s.d_rank_base.p;
+  if (s.D_M == 0) {
+    // empty sector: nothing is in range; still run the search for rep/h
+    a.D_M = 0;
+  }
+  FTLM_DISPATCH_NCH(s.nch, {
+    if (lds)
+      hipLaunchKernelGGL((k_canon_labels<W, NCH, true>), dim3(grid_for((uint64_t)n)), dim3(kThreads), tab_bytes, st, a,
+                         bits, base, labels, n, rep, h, index);
+    else
+      hipLaunchKernelGGL((k_canon_labels<W, NCH, false>), dim3(grid_for((uint64_t)n)), dim3(kThreads), 0, st, a, bits,
+                         base, labels, n, rep, h, index);
+  });
+  FTLM_HIP(hipGetLastError());
+}
+
+std::vector<uint64_t> sector_export_labels(const Sector& s) {
+  std::vector<uint64_t> packed = s.d_reps.download();
+  if (s.d == (1 << s.bits)) return packed;  // packed digits are the Eq. (2) label
+  const uint64_t mask = (1ull << s.bits) - 1;
+  for (auto& x : packed) {
+    uint64_t lab = 0;
+    for (int k = s.N - 1; k >= 0; --k) lab = lab * (uint64_t)s.d + ((x >> (k * s.bits)) & mask);
+    x = lab;
+  }
+  return packed;
+}
+
+}  // namespace ftlm

@@ -1,0 +1,117 @@
+// Host FP64 stages of the FTLM estimator (paper Section 2.2, Eqs. 4-7, 14):
+// Ritz data of each chain's tridiagonal matrix and the thermal sums.
+#include <algorithm>
+#include <cmath>
+#include <limits>
+#include <vector>
+
+#include "common.h"
+
+namespace ftlm {
+
+// Eigenvalues and squared first eigenvector components of a symmetric
+// tridiagonal matrix by the implicit QL method with Wilkinson-type shifts.
+// Only the first row of the accumulated rotation product is tracked, which is
+// all the FTLM weights need.  d: diagonal (n), e: off-diagonal (n-1).
+void tridiag_ritz(const double* alpha, const double* beta, int n, double* theta, double* weight) {
+  std::vector<double> d(alpha, alpha + n), e(n, 0.0), z(n, 0.0);
+  for (int i = 0; i + 1 < n; ++i) e[i] = beta[i];
+  if (n > 0) z[0] = 1.0;
+  const double eps = std::numeric_limits<double>::epsilon();
+  for (int l = 0; l < n; ++l) {
+    for (int iter = 0;; ++iter) {
+      int m = l;
+      for (; m < n - 1; ++m) {
+        double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+        if (std::fabs(e[m]) <= eps * dd) break;
+      }
+      if (m == l) break;
+      if (iter > 200) fail(FTLM_ERR_INVALID_ARG, "tridiagonal QL did not converge");
+      // shift from the leading 2x2 block at l
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::hypot(g, 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+      double s = 1.0, c = 1.0, p = 0.0;
+      int i = m - 1;
+      bool deflated = false;
+      for (; i >= l; --i) {
+        double f = s * e[i];
+        double b = c * e[i];
+        r = std::hypot(f, g);
+        e[i + 1] = r;
+        if (r == 0.0) {  // underflow: split the problem here
+          d[i + 1] -= p;
+          e[m] = 0.0;
+          deflated = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - p;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        p = s * r;
+        d[i + 1] = g + p;
+        g = c * r - b;
+        double zi1 = z[i + 1];
+        z[i + 1] = s * z[i] + c * zi1;
+        z[i] = c * z[i] - s * zi1;
+      }
+      if (deflated) continue;
+      d[l] -= p;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
+  std::vector<int> idx(n);
+  for (int i = 0; i < n; ++i) idx[i] = i;
+  std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return d[a] < d[b]; });
+  for (int k = 0; k < n; ++k) {
+    theta[k] = d[idx[k]];
+    weight[k] = z[idx[k]] * z[idx[k]];
+  }
+}
+
+void observables(const ftlm_ritz* blocks, int nb, const double* T, int nT, double g, double* E,
+                 double* C, double* chi, double* logZ) {
+  double E0 = std::numeric_limits<double>::infinity();
+  for (int b = 0; b < nb; ++b) {
+    const ftlm_ritz& B = blocks[b];
+    if (B.D == 0) continue;
+    for (int r = 0; r < B.R; ++r)
+      for (int k = 0; k < B.nsteps[r]; ++k) E0 = std::min(E0, B.theta[(size_t)r * B.ld + k]);
+  }
+  if (!std::isfinite(E0)) fail(FTLM_ERR_INVALID_ARG, "no Ritz values in the given blocks");
+  for (int t = 0; t < nT; ++t) {
+    const double beta = 1.0 / T[t];
+    double Z = 0, H1 = 0, H2 = 0, num = 0, den = 0;
+    for (int b = 0; b < nb; ++b) {
+      const ftlm_ritz& B = blocks[b];
+      if (B.D == 0 || B.R == 0) continue;
+      const double mult = B.two_M == 0 ? 1.0 : 2.0;
+      double z = 0, h1 = 0, h2 = 0;
+      for (int r = 0; r < B.R; ++r)
+        for (int k = 0; k < B.nsteps[r]; ++k) {
+          double sh = B.theta[(size_t)r * B.ld + k] - E0;
+          double bz = std::exp(-beta * sh) * B.weight[(size_t)r * B.ld + k];
+          z += bz;
+          h1 += bz * sh;
+          h2 += bz * sh * sh;
+        }
+      const double zblock = double(B.d_gamma) * double(B.D) / double(B.R) * z;  // d_Gamma Z_{M,Gamma}
+      Z += mult * zblock;
+      const double fac = mult * double(B.d_gamma) * double(B.D) / double(B.R);
+      H1 += fac * h1;
+      H2 += fac * h2;
+      const double M = 0.5 * B.two_M;
+      num += mult * M * M * zblock;
+      den += mult * zblock;
+    }
+    const double e1 = H1 / Z, e2 = H2 / Z;
+    if (E) E[t] = E0 + e1;
+    if (C) C[t] = beta * beta * (e2 - e1 * e1);
+    if (chi) chi[t] = g * g * beta * num / den;
+    if (logZ) logZ[t] = std::log(Z) - beta * E0;
+  }
+}
+
+}  // namespace ftlm
