@@ -1,0 +1,241 @@
+#!/usr/bin/env python
+"""Benchmark of the symmetry-adapted FTLM hot path on one MI355X.
+
+One step = one complete FTLM job on one block: group closure and irreps,
+sector tables (representatives, stabilizers, lookup, entry table), block data,
+R batched Lanczos chains (one H.V launch per step for all chains), Ritz data
+and the thermal sums on 50 temperatures.  Default workload: the s=1/2
+icosidodecahedron, M=0, irrep H_g (D = 6,465,762), R = 24 Gaussian chains,
+60 steps, FP32 vector storage with FP64 reductions.
+
+value = D * (sum over chains of H.V products) / step time, in basis
+elements x vectors per second.  The roofline object describes the H.V kernel
+(timed with HIP events on the launch stream), the CPU baseline times the FP64
+oracle on sampled output rows of the same block.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+WORKLOADS = {
+    # name: cluster, 2s, 2M, irrep index (library order), R, steps, dist, storage
+    "icosidodecahedron_Hg": dict(cluster="icosidodecahedron", two_s=1, two_M=0, irrep=8, R=24, steps=60,
+                                 dist="gaussian", storage="f32",
+                                 desc="s=1/2 Heisenberg icosidodecahedron (N=30, 60 bonds), I_h, M=0, "
+                                      "irrep H_g row 1 (D=6,465,762); R=24 Gaussian chains, 60 Lanczos steps, "
+                                      "FP32 storage, FP64 reductions"),
+    "dodecahedron_Hg": dict(cluster="dodecahedron", two_s=1, two_M=0, irrep=8, R=24, steps=60, dist="rademacher",
+                            storage="f64",
+                            desc="s=1/2 dodecahedron (N=20), I_h, M=0, irrep H_g (D=7,800); R=24 Rademacher, "
+                                 "60 steps, FP64"),
+}
+
+
+def sha_of(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def algorithmic_bytes(stats, D, n_reps, nvec, elem):
+    """Bytes one H.V launch must move (no cache reuse credited).
+
+    per active connection: the gathered X rows (n_r * nvec * elem) + the 8-byte
+    entry + the 8-byte metadata word of the target; per connection with an
+    inactive target: the entry; per block row: read X once (diagonal) and
+    write Y; per active output representative: label, metadata, row pointer
+    and diagonal energy (32 bytes); per inactive one: its metadata word.
+    """
+    act = stats["active_connections"]
+    inact = stats["connections"] - act
+    return (stats["gathered_rows"] * nvec * elem + 16 * act + 8 * inact + 2 * D * nvec * elem
+            + 32 * stats["n_active"] + 8 * (n_reps - stats["n_active"]))
+
+
+def cpu_baseline(wl, seconds):
+    """FP64 oracle H.v (nvec = 1) on sampled output rows of the same block."""
+    import numpy as np
+
+    from oracle import basis as obasis
+    from oracle import group as ogroup
+    from oracle import hv as ohv
+    from oracle import irreps as oirreps
+    from synth import clusters
+    from synth.vectors import label_keyed_values
+
+    cl = clusters.get(wl["cluster"])
+    G = ogroup.close(cl.gens, cl.N)
+    ir = oirreps.compute_irreps(G)[wl["irrep"]]
+    d = wl["two_s"] + 1
+    rng = np.random.default_rng(17)
+    A = (cl.N * wl["two_s"] + wl["two_M"]) // 2
+
+    def xfun(r, n):
+        return label_keyed_values(5, np.full(n, r, dtype=np.uint64), np.arange(n, dtype=np.uint64), np.zeros(n, np.uint64))[:, None]
+
+    rows = 0
+    reps_done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        if d == 2:
+            bits = rng.choice(cl.N, A, replace=False)
+            lab = int(np.sum(2 ** bits.astype(np.int64)))
+        else:
+            raise NotImplementedError
+        p, _ = obasis.canonicalize(G, np.array([lab]), cl.N, d)
+        out = ohv.sampled_rows(G, ir, 0, cl.N, wl["two_s"], cl.bonds, cl.J, [int(p[0])], xfun, 1)
+        rows += out[0].shape[0]
+        reps_done += 1
+    el = time.perf_counter() - t0
+    return dict(value=rows / el, unit="basis-elems*vecs/s", cores=1, kind="oracle",
+                sample=f"{reps_done} random output representatives of the same block ({rows} rows, nvec=1, FP64), "
+                       f"{el:.1f} s single-threaded Python/NumPy")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="icosidodecahedron_Hg", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--hv-reps", type=int, default=20)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only "
+                                   "(see DESIGN.md), so --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2607_17429_amd as P
+    from synth import clusters
+
+    wl = WORKLOADS[args.workload]
+    cl = clusters.get(wl["cluster"])
+    storage = P.F32 if wl["storage"] == "f32" else P.F64
+    dist = P.GAUSSIAN if wl["dist"] == "gaussian" else P.RADEMACHER
+    T = np.geomspace(0.05, 10, 50)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    def job(seed):
+        t0 = time.perf_counter()
+        G = P.Group(cl.N, cl.gens)
+        S = P.Sector(cl, G, wl["two_M"], two_s=wl["two_s"])
+        t1 = time.perf_counter()
+        B = P.Block(S, wl["irrep"], 0)
+        a, b, n = B.ftlm(wl["R"], wl["steps"], seed, storage=storage, dist=dist, stream=stream)
+        t2 = time.perf_counter()
+        ths, ws = P.ritz_from_run(a, b, n)
+        E, C, chi, lz = P.observables([dict(two_M=wl["two_M"], d_gamma=B.d_gamma, D=B.D, thetas=ths, weights=ws)], T)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        return dict(D=B.D, products=int(n.sum()), build=t1 - t0, lanczos=t2 - t1, thermo=t3 - t2, total=t3 - t0,
+                    E0=float(min(t.min() for t in ths)))
+
+    # autotune the H.V lane layout once for this kernel shape (cached process-wide)
+    G0 = P.Group(cl.N, cl.gens)
+    S0 = P.Sector(cl, G0, wl["two_M"], two_s=wl["two_s"])
+    B0 = P.Block(S0, wl["irrep"], 0)
+    tuned = B0.autotune(wl["R"], storage, stream=stream)
+    del B0, S0, G0
+    for w in range(args.warmup):
+        job(0x5EED0003 + 1000 + w)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    recs = [job(0x5EED0003 + k) for k in range(args.steps)]
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    D = recs[0]["D"]
+    work = sum(r["D"] * r["products"] for r in recs)
+    value = work / wall
+    lat = np.array([r["total"] for r in recs]) * 1e3
+
+    # ---- H.V kernel alone: same block, nvec = R, storage dtype, HIP events on the launch stream
+    G = P.Group(cl.N, cl.gens)
+    S = P.Sector(cl, G, wl["two_M"], two_s=wl["two_s"])
+    B = P.Block(S, wl["irrep"], 0)
+    tdt = torch.float32 if storage == P.F32 else torch.float64
+    elem = 4 if storage == P.F32 else 8
+    X = torch.randn((B.D, wl["R"]), dtype=tdt, device=dev)
+    Y = torch.empty_like(X)
+    for _ in range(3):
+        B.apply_H(X, Y, stream=stream)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.hv_reps):
+        B.apply_H(X, Y, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    hv_ms = ev0.elapsed_time(ev1) / args.hv_reps
+    stats = B.hv_stats()
+    balg = algorithmic_bytes(stats, B.D, S.n_reps, wl["R"], elem)
+    achieved = balg / (hv_ms * 1e-3) / 1e9
+    # plain single-vector FP64 H.V for the speedup figure
+    X1 = torch.randn((B.D, 1), dtype=torch.float64, device=dev)
+    Y1 = torch.empty_like(X1)
+    B.apply_H(X1, Y1, stream=stream)
+    ev0.record(stream)
+    for _ in range(5):
+        B.apply_H(X1, Y1, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    hv1_ms = ev0.elapsed_time(ev1) / 5
+
+    traffic = None
+    tp = os.path.join(ROOT, "profiles", f"hv_traffic_{args.workload}.json")
+    if os.path.exists(tp):
+        tj = json.load(open(tp))
+        if tj.get("source_sha") == sha_of(os.path.join(ROOT, "paper_2607_17429_amd", "csrc", "hv.hip")):
+            traffic = tj.get("bytes_per_launch")
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(wl, args.cpu_seconds)
+
+    out = {
+        "metric": "sym-adapted H.V basis-elems x vecs/s (whole FTLM job), % HBM roofline of H.V; job p50/p99 latency",
+        "value": value,
+        "unit": "basis-elems*vecs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": wl["storage"],
+        "data": "synthetic (cluster geometry + seeded SplitMix64 start vectors)",
+        "config": {"workload": wl["desc"], "D": D, "R": wl["R"], "lanczos_steps": wl["steps"],
+                   "n_reps": int(S.n_reps), "group_order": B.group_order, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "kernel": "k_hv (entry-table mode)", "algorithmic_bytes_per_launch": balg,
+                     "avg_launch_ms": hv_ms, "nvec": wl["R"]},
+        "cpu_baseline": cpu,
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+        "breakdown_ms": {k: float(np.mean([r[k] for r in recs]) * 1e3) for k in ("build", "lanczos", "thermo")},
+        "hv": {"batched_elem_vec_per_s": B.D * wl["R"] / (hv_ms * 1e-3),
+               "single_fp64_elem_vec_per_s": B.D / (hv1_ms * 1e-3), "single_fp64_ms": hv1_ms,
+               "connections": stats["connections"], "active_connections": stats["active_connections"]},
+        "E0": recs[0]["E0"],
+        "autotune": {"lanes_per_rep": tuned[0], "ms": tuned[1], "tried_ms": tuned[2]},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -184,11 +184,35 @@ int ftlm_block_info_get(const ftlm_block* b, ftlm_block_info* info);
 int ftlm_block_export(const ftlm_block* b, uint64_t* reps, uint16_t* stab_id, uint8_t* n_gamma,
                       double* norms, uint64_t* offsets);
 
+/* Work counts of one H.V on this block, for the algorithmic byte model:
+ * connections of active output representatives (entries read), those whose
+ * target representative is active in this irrep, and the rows gathered for
+ * them (sum of n_Gamma(target)).  Device reduction, synchronous. */
+typedef struct ftlm_hv_stats {
+  uint64_t n_active;          /* output representatives with n_Gamma > 0 */
+  uint64_t connections;       /* flips of active output representatives */
+  uint64_t active_connections;
+  uint64_t gathered_rows;
+} ftlm_hv_stats;
+int ftlm_block_hv_stats(const ftlm_block* b, ftlm_hv_stats* stats);
+
 /* Y = H X for nvec columns of D x ld device arrays of dtype (F64 or F32;
- * F32 multiplies in FP32).  X and Y must not overlap.  Enqueued on stream
+ * F32 is storage only: products and sums are formed in FP64 and rounded once
+ * when Y is stored).  X and Y must not overlap.  Enqueued on stream
  * (asynchronous).  Errors: INVALID_ARG, HIP. */
 int ftlm_apply_H(ftlm_block* b, const void* X, void* Y, int32_t nvec, int64_t ld, int32_t dtype,
                  void* stream);
+
+/* Autotuner: times every lane layout of the H.V kernel (lanes per output
+ * representative 1..64, vectors per lane) for nvec columns of dtype on this
+ * block, on stream, and keeps the fastest in a process-wide cache keyed by
+ * (N, 2s, |G|, irrep dimension, nvec, dtype, H.V mode); later apply and run
+ * calls with that key use it.  Outputs (may be NULL): the chosen lanes per
+ * representative and its time per launch in ms; up to 8 (lanes, ms) pairs in
+ * tried/tried_ms with their count in n_tried.  Allocates two D x nvec
+ * scratch arrays for the duration of the call.  Synchronous. */
+int ftlm_block_autotune(ftlm_block* b, int32_t nvec, int32_t dtype, void* stream, int32_t* best_lanes,
+                        double* best_ms, int32_t* tried, double* tried_ms, int32_t* n_tried);
 
 /* R independent Lanczos chains batched into one H.V launch per step
  * (Sections 2.2, 3).  Chain r starts from a SplitMix64 vector keyed by

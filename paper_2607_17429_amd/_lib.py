@@ -57,6 +57,11 @@ class BlockInfo(C.Structure):
                 ("hv_mode", C.c_int32), ("device_bytes", C.c_int64)]
 
 
+class HvStats(C.Structure):
+    _fields_ = [("n_active", C.c_uint64), ("connections", C.c_uint64), ("active_connections", C.c_uint64),
+                ("gathered_rows", C.c_uint64)]
+
+
 class Ritz(C.Structure):
     _fields_ = [("two_M", C.c_int32), ("d_gamma", C.c_int32), ("D", C.c_uint64), ("R", C.c_int32),
                 ("ld", C.c_int32), ("nsteps", C.POINTER(C.c_int32)),
@@ -87,7 +92,9 @@ SIGNATURES = {
     "ftlm_block_info_get": (C.c_int, [VP, C.POINTER(BlockInfo)]),
     "ftlm_block_export": (C.c_int, [VP, C.POINTER(C.c_uint64), C.POINTER(C.c_uint16), C.POINTER(C.c_uint8),
                                     F64P, C.POINTER(C.c_uint64)]),
+    "ftlm_block_hv_stats": (C.c_int, [VP, C.POINTER(HvStats)]),
     "ftlm_apply_H": (C.c_int, [VP, VP, VP, C.c_int32, C.c_int64, C.c_int32, VP]),
+    "ftlm_block_autotune": (C.c_int, [VP, C.c_int32, C.c_int32, VP, I32P, F64P, I32P, F64P, I32P]),
     "ftlm_run": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, F64P, F64P, I32P, VP]),
     "ftlm_tridiag_ritz": (C.c_int, [F64P, F64P, C.c_int32, F64P, F64P]),
     "ftlm_observables": (C.c_int, [C.POINTER(Ritz), C.c_int32, F64P, C.c_int32, C.c_double, F64P, F64P, F64P, F64P]),

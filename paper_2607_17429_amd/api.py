@@ -21,13 +21,14 @@ class Group:
         h = C.c_void_p()
         check(lib().ftlm_group_create(int(N), gens.ctypes.data_as(L.I32P), len(gens), C.byref(h)))
         self._h = h
+        self._free = lib().ftlm_group_free
         o, ni, nc, n = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
         check(lib().ftlm_group_info(h, C.byref(o), C.byref(ni), C.byref(nc), C.byref(n)))
         self.order, self.n_irreps, self.n_classes, self.N = o.value, ni.value, nc.value, n.value
 
     def __del__(self):
         if getattr(self, "_h", None):
-            lib().ftlm_group_free(self._h)
+            self._free(self._h)
             self._h = None
 
     def elements(self):
@@ -65,6 +66,7 @@ class Sector:
         h = C.c_void_p()
         check(lib().ftlm_sector_create(C.byref(cl), group._h, int(two_M), C.byref(opts), C.byref(h)))
         self._h = h
+        self._free = lib().ftlm_sector_free
         self.two_M = int(two_M)
         info = L.SectorInfo()
         check(lib().ftlm_sector_info_get(h, C.byref(info)))
@@ -73,7 +75,7 @@ class Sector:
 
     def __del__(self):
         if getattr(self, "_h", None):
-            lib().ftlm_sector_free(self._h)
+            self._free(self._h)
             self._h = None
 
     def export(self):
@@ -107,6 +109,7 @@ class Block:
         h = C.c_void_p()
         check(lib().ftlm_block_create(sector._h, int(irrep), int(row), C.byref(opts), C.byref(h)))
         self._h = h
+        self._free = lib().ftlm_block_free
         self._load_info()
 
     @classmethod
@@ -121,6 +124,7 @@ class Block:
         check(lib().ftlm_build_block(C.byref(cl), gens.ctypes.data_as(L.I32P), len(gens), int(two_M), int(irrep),
                                      int(row), C.byref(opts), C.byref(h)))
         self._h = h
+        self._free = lib().ftlm_block_free
         self._load_info()
         return self
 
@@ -132,7 +136,7 @@ class Block:
 
     def __del__(self):
         if getattr(self, "_h", None):
-            lib().ftlm_block_free(self._h)
+            self._free(self._h)
             self._h = None
 
     def export(self):
@@ -147,6 +151,23 @@ class Block:
                                       ng.ctypes.data_as(C.POINTER(C.c_uint8)), norms.ctypes.data_as(L.F64P),
                                       offs.ctypes.data_as(C.POINTER(C.c_uint64))))
         return dict(reps=reps, stab_id=sid, n_gamma=ng, L=norms, offsets=offs)
+
+    def hv_stats(self):
+        st = L.HvStats()
+        check(lib().ftlm_block_hv_stats(self._h, C.byref(st)))
+        return {f: getattr(st, f) for f, _ in L.HvStats._fields_}
+
+    def autotune(self, nvec, dtype=F32, stream=None):
+        """Time every H.V lane layout for nvec columns; the fastest is cached process-wide."""
+        best = C.c_int32()
+        best_ms = C.c_double()
+        tried = np.zeros(8, np.int32)
+        tried_ms = np.zeros(8)
+        n = C.c_int32()
+        check(lib().ftlm_block_autotune(self._h, int(nvec), int(dtype), L.stream_handle(stream), C.byref(best),
+                                        C.byref(best_ms), tried.ctypes.data_as(L.I32P), tried_ms.ctypes.data_as(L.F64P),
+                                        C.byref(n)))
+        return best.value, best_ms.value, dict(zip(tried[: n.value].tolist(), tried_ms[: n.value].tolist()))
 
     def apply_H(self, X, Y=None, stream=None):
         """Y = H X for a (D, nvec) torch CUDA tensor (float64 or float32)."""

@@ -8,6 +8,7 @@
 // exclusive prefix sum giving each representative's first block row.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "internal.h"
 
@@ -60,7 +61,52 @@ double check_user_rho(const Group& G, const double* rho, int d) {
   return worst;
 }
 
+__global__ void k_hv_stats(const uint64_t* __restrict__ meta, const uint64_t* __restrict__ row_ptr,
+                           const uint64_t* __restrict__ entries, const uint8_t* __restrict__ n_stab, uint64_t n,
+                           unsigned long long* __restrict__ out) {
+  unsigned long long c = 0, ca = 0, rows = 0, act = 0;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (uint64_t)gridDim.x * blockDim.x) {
+    if (n_stab[meta[p] >> 48] == 0) continue;
+    ++act;
+    for (uint64_t e = row_ptr[p]; e < row_ptr[p + 1]; ++e) {
+      const uint64_t idx = entries[e] & 0xffffffffull;
+      ++c;
+      if (idx == 0xffffffffull) continue;
+      const unsigned nr = n_stab[meta[idx] >> 48];
+      if (nr) {
+        ++ca;
+        rows += nr;
+      }
+    }
+  }
+  atomicAdd(&out[0], act);
+  atomicAdd(&out[1], c);
+  atomicAdd(&out[2], ca);
+  atomicAdd(&out[3], rows);
+}
+
 }  // namespace
+
+void block_hv_stats(const Block& b, ftlm_hv_stats* st) {
+  std::memset(st, 0, sizeof(*st));
+  const Sector& s = *b.sec;
+  if (!s.n_reps) return;
+  if (s.hv_mode != FTLM_HV_ENTRIES) fail(FTLM_ERR_UNSUPPORTED, "work counts need the entry table");
+  DevBuf<uint8_t> d_n;
+  d_n.upload(b.n_stab);
+  DevBuf<unsigned long long> out;
+  out.alloc(4);
+  FTLM_HIP(hipMemset(out.p, 0, out.bytes()));
+  hipLaunchKernelGGL(k_hv_stats, dim3(grid1(s.n_reps)), dim3(256), 0, nullptr, b.d_meta.p, s.d_row_ptr.p,
+                     s.d_entries.p, d_n.p, s.n_reps, out.p);
+  FTLM_HIP(hipGetLastError());
+  unsigned long long h[4];
+  FTLM_HIP(hipMemcpy(h, out.p, sizeof(h), hipMemcpyDeviceToHost));
+  st->n_active = h[0];
+  st->connections = h[1];
+  st->active_connections = h[2];
+  st->gathered_rows = h[3];
+}
 
 std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int row, const ftlm_opts* opts) {
   if (!sec) fail(FTLM_ERR_INVALID_ARG, "null sector");
@@ -88,6 +134,7 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
   }
   const int d = B->dg;
   if (row < 0 || row >= d) fail(FTLM_ERR_ROW_OUT_OF_RANGE, "row must be in 0..d-1");
+  B->dgp = irrep_dim_bucket(d);
   // per stabilizer data
   const int ns = sec->n_stab;
   B->n_stab.assign(std::max(ns, 1), 0);
@@ -158,17 +205,18 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
     for (int s = 0; s < ns; ++s)
       if (B->n_stab[s]) B->n_active += h_per[s];
   }
-  // rho^T[g][beta][gamma] = rho(g)[gamma][beta]
-  std::vector<double> rt((size_t)n * d * d);
+  // rho^T[g][beta][gamma] = rho(g)[gamma][beta], zero-padded to the kernel's dimension bucket
+  const int dp = B->dgp;
+  std::vector<double> rt((size_t)n * dp * dp, 0.0);
   for (int g = 0; g < n; ++g)
     for (int be = 0; be < d; ++be)
-      for (int ga = 0; ga < d; ++ga) rt[((size_t)g * d + be) * d + ga] = B->rho[((size_t)g * d + ga) * d + be];
+      for (int ga = 0; ga < d; ++ga) rt[((size_t)g * dp + be) * dp + ga] = B->rho[((size_t)g * d + ga) * d + be];
   B->d_rhoT64.upload(rt);
-  std::vector<float> rt32(rt.begin(), rt.end());
-  B->d_rhoT32.upload(rt32);
-  B->d_V64.upload(B->V_stab);
-  std::vector<float> v32(B->V_stab.begin(), B->V_stab.end());
-  B->d_V32.upload(v32);
+  std::vector<double> vp((size_t)std::max(ns, 1) * dp * dp, 0.0);
+  for (int s = 0; s < ns; ++s)
+    for (int i = 0; i < d; ++i)
+      for (int k = 0; k < d; ++k) vp[((size_t)s * dp + i) * dp + k] = B->V_stab[((size_t)s * d + i) * d + k];
+  B->d_V64.upload(vp);
   std::vector<double> sf((size_t)std::max(ns, 1) * 4, 0.0);
   for (int s = 0; s < ns; ++s) {
     sf[4 * s + 0] = B->n_stab[s];
@@ -177,8 +225,6 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
     sf[4 * s + 3] = B->trivial[s];
   }
   B->d_stabf64.upload(sf);
-  std::vector<float> sf32(sf.begin(), sf.end());
-  B->d_stabf32.upload(sf32);
   FTLM_HIP(hipStreamSynchronize(st));
   if (opts && opts->hbm_limit_bytes > 0 && B->device_bytes() > opts->hbm_limit_bytes)
     fail(FTLM_ERR_OUT_OF_MEMORY, "block tables exceed the HBM limit");

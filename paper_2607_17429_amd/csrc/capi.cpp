@@ -1,5 +1,6 @@
 // extern "C" entry points of ftlm.h: argument checks, exception -> status
 // translation, thread-local last-error message.
+#include <algorithm>
 #include <cstring>
 #include <string>
 
@@ -208,11 +209,39 @@ int ftlm_block_export(const ftlm_block* b, uint64_t* reps, uint16_t* stab_id, ui
   });
 }
 
+int ftlm_block_hv_stats(const ftlm_block* b, ftlm_hv_stats* stats) {
+  return guarded([&] {
+    if (!b || !stats) fail(FTLM_ERR_INVALID_ARG, "null argument");
+    block_hv_stats(*b->b, stats);
+  });
+}
+
 int ftlm_apply_H(ftlm_block* b, const void* X, void* Y, int32_t nvec, int64_t ld, int32_t dtype, void* stream) {
   return guarded([&] {
     if (!b) fail(FTLM_ERR_INVALID_ARG, "null block");
     if (X == Y && X) fail(FTLM_ERR_INVALID_ARG, "X and Y must not overlap");
     apply_hv(*b->b, X, Y, nvec, ld, dtype, (hipStream_t)stream);
+  });
+}
+
+int ftlm_block_autotune(ftlm_block* b, int32_t nvec, int32_t dtype, void* stream, int32_t* best_lanes,
+                        double* best_ms, int32_t* tried, double* tried_ms, int32_t* n_tried) {
+  return guarded([&] {
+    if (!b) fail(FTLM_ERR_INVALID_ARG, "null block");
+    if (nvec <= 0 || nvec > 4096) fail(FTLM_ERR_INVALID_ARG, "nvec must be in 1..4096");
+    if (dtype != FTLM_F64 && dtype != FTLM_F32) fail(FTLM_ERR_INVALID_ARG, "bad dtype");
+    auto res = autotune_hv(*b->b, nvec, dtype, (hipStream_t)stream, 5);
+    int bi = -1;
+    for (size_t i = 0; i < res.size(); ++i)
+      if (bi < 0 || res[i].second < res[bi].second) bi = (int)i;
+    if (best_lanes) *best_lanes = bi >= 0 ? res[bi].first : 0;
+    if (best_ms) *best_ms = bi >= 0 ? res[bi].second : 0.0;
+    const int n = (int)std::min<size_t>(res.size(), 8);
+    for (int i = 0; i < n; ++i) {
+      if (tried) tried[i] = res[i].first;
+      if (tried_ms) tried_ms[i] = res[i].second;
+    }
+    if (n_tried) *n_tried = n;
   });
 }
 

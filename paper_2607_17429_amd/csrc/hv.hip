@@ -1,326 +1,207 @@
-// Matrix-free H.V in the symmetry-adapted basis (paper Eqs. 15-16).
-//
-// Gather form used here (derived from Eq. 15 with U(h) a = r for the flipped
-// state a = flip_e(p) of output representative p):
-//
-//   Y[p] = E_diag(p) X[p]
-//        + sqrt(L_p) V_p^T  sum_e  c_e(p) / sqrt(L_r)  rho(h)^T  V_r X[r]
-//
-// with c_e(p) the Eq. (3) coefficient of flip e evaluated on p's digits and
-// L = |G| / |Stab|.  One output representative is owned by a group of GL
-// lanes (GL = smallest power of two >= nvec, at most 64), lane = vector
-// column, so every output element is written by exactly one lane and the sum
-// over flips runs in a fixed order (deterministic, no atomics).  Per flip the
-// group gathers the n_r contiguous rows of X[r] (n_r * nvec contiguous
-// elements), expands them with V_r when the stabilizer is non-trivial,
-// contracts with rho(h)^T and accumulates in the d-dimensional irrep space;
-// the projection with V_p happens once per output representative.
-//
-// The flips come either from the sector's entry table (target index, h and
-// flip id precomputed once per sector and shared by all irreps) or are found
-// on the fly: flip, orbit search over the group, rank lookup.
-//
-// Lanczos epilogue (EPI): the kernel writes w = s_j (H q_j) - bs_j q_prev
-// over q_prev (Y holds q_prev on entry) and per-workgroup FP64 partial sums
-// of q_j . w (w as stored), so alpha_j needs no extra pass over the vectors.
-#include <algorithm>
-#include <cmath>
+// Host side of the H.V (paper Eqs. 15-16): LDS layout of the small tables,
+// lane layout (lanes per representative, vectors per lane) and dispatch to the
+// kernel instantiations in hv_dg*.hip.  The kernel itself is in hv_kernel.h.
+#include <map>
+#include <mutex>
+#include <tuple>
 
-#include "device.h"
-#include "dispatch.h"
-#include "internal.h"
+#include "hv_kernel.h"
 
 namespace ftlm {
 
+using namespace hvk;
+
 namespace {
 
-constexpr int kThreads = 256;
-constexpr uint64_t kOffMask = (1ull << 48) - 1;
+constexpr uint32_t kSmallLdsBudget = 48 * 1024;
+constexpr uint32_t kLdsLimit = 65536 - 2048;  // dynamic LDS; 2 KiB stay for the epilogue reduction
 
-template <typename T, typename A>
-struct HvArgs {
-  const uint64_t* reps;
-  const uint64_t* row_ptr;
-  const uint64_t* entries;
-  const uint64_t* meta;
-  const double* ediag;
-  const A* rhoT;      // [g][beta][gamma]
-  const A* V;         // [s][gamma][k]
-  const A* stabf;     // [s][4] = n, sqrtL, 1/sqrtL, trivial
-  const int32_t* bonds;
-  const double* J;
-  const double* fac;  // [2][dloc][dloc]
-  int b, dloc, nbonds, G, n_stab;
-  uint64_t n_reps;
-  const T* X;
-  T* Y;
-  int64_t ld;
-  int nvec, GL, log2GL;
-  // on-the-fly search
-  const void* tab;
-  const uint64_t* cnt;
-  const uint64_t* rank_bits;
-  const uint32_t* rank_base;
-  int cnt_stride, N, A_tot;
-  uint64_t D_M;
-  uint32_t tab_words;
-  // Lanczos epilogue
-  const double* scal;
-  double* partials;
+struct Layout {
+  int GL, log2GL, VPL, tile_w, tiles;
 };
 
-template <typename W>
-__device__ __forceinline__ bool lookup_rep(W r, int N, int b, int d, int A, const uint64_t* cnt, int stride,
-                                           uint64_t D_M, const uint64_t* bits, const uint32_t* base, uint64_t& idx) {
-  const uint64_t rk = dev::sector_rank<W>(r, N, b, d, A, cnt, stride);
-  if (rk >= D_M) return false;
-  const uint64_t m = bits[rk >> 6];
-  const int k = (int)(rk & 63);
-  idx = base[rk >> 6] + (uint64_t)__popcll(m & ((1ull << k) - 1));
-  return (m >> k) & 1;
+int pow2_at_least(int n) {
+  int p = 1;
+  while (p < n) p <<= 1;
+  return p;
 }
 
-__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
-  uint32_t lo = __shfl((unsigned)(v & 0xffffffffu), src);
-  uint32_t hi = __shfl((unsigned)(v >> 32), src);
-  return ((uint64_t)hi << 32) | lo;
+int vpl_bucket(int need, bool otf) {
+  if (otf) return need <= 1 ? 1 : 4;
+  const int opts[] = {1, 2, 3, 4, 6, 8};
+  for (int o : opts)
+    if (o >= need) return o;
+  return 8;
 }
 
-template <typename T, typename A, int DG, bool OTF, int NCH, bool LDS_TAB>
-__global__ void __launch_bounds__(kThreads) k_hv(HvArgs<T, A> a) {
-  const bool EPI = a.partials != nullptr;
-  using W = word_t<NCH>;
-  extern __shared__ uint64_t smem_raw[];
-  const W* tab = nullptr;
-  if constexpr (OTF) {
-    if constexpr (LDS_TAB) {
-      W* s = (W*)smem_raw;
-      for (uint32_t i = threadIdx.x; i < a.tab_words; i += blockDim.x) s[i] = ((const W*)a.tab)[i];
-      __syncthreads();
-      tab = s;
-    } else {
-      tab = (const W*)a.tab;
-    }
-  }
-  const int lane = threadIdx.x & 63;
-  const int GL = a.GL;
-  const int lg = lane & (GL - 1);
-  const int gbase = lane - lg;
-  const int v = blockIdx.y * 64 + lg;
-  const bool vok = lg < 64 && v < a.nvec;
-  const int slots_per_wave = 64 >> a.log2GL;
-  const int waves = blockDim.x >> 6;
-  const uint64_t slot = ((uint64_t)blockIdx.x * waves + (threadIdx.x >> 6)) * slots_per_wave + (lane >> a.log2GL);
-  const uint64_t slot_stride = (uint64_t)gridDim.x * waves * slots_per_wave;
-  const W lmask = (W(1) << a.b) - 1;
-  const int ncand = 2 * a.nbonds;
-  double dot = 0.0;
-
-  for (uint64_t p = slot; p < a.n_reps; p += slot_stride) {
-    const uint64_t mp = a.meta[p];
-    const int sp = (int)(mp >> 48);
-    const int np_ = (int)a.stabf[4 * sp];
-    if (np_ == 0) continue;
-    const uint64_t offp = mp & kOffMask;
-    const W plab = (W)a.reps[p];
-    A acc[DG];
-#pragma unroll
-    for (int q = 0; q < DG; ++q) acc[q] = A(0);
-
-    const uint64_t e_begin = OTF ? 0 : a.row_ptr[p];
-    const uint64_t e_end = OTF ? (uint64_t)ncand : a.row_ptr[p + 1];
-    for (uint64_t e = e_begin; e < e_end; e += GL) {
-      uint64_t my = ~0ull;
-      if constexpr (!OTF) {
-        if (e + lg < e_end) my = a.entries[e + lg];
-      } else {
-        const int cand = (int)e + lg;
-        bool ok = false;
-        W x = plab;
-        if (cand < ncand) {
-          const int bond = cand >> 1;
-          const int i = a.bonds[2 * bond], j = a.bonds[2 * bond + 1];
-          const int ai = dev::digit(plab, i, a.b, lmask), aj = dev::digit(plab, j, a.b, lmask);
-          ok = (cand & 1) ? (ai > 0 && aj < a.dloc - 1) : (ai < a.dloc - 1 && aj > 0);
-          const W ui = W(1) << (i * a.b), uj = W(1) << (j * a.b);
-          if (ok) x = (cand & 1) ? (plab - ui + uj) : (plab + ui - uj);
-        }
-        W r;
-        int h;
-        dev::canon_min<W, NCH>(x, tab, a.G, r, h);
-        uint64_t idx = 0;
-        if (ok && lookup_rep<W>(r, a.N, a.b, a.dloc, a.A_tot, a.cnt, a.cnt_stride, a.D_M, a.rank_bits, a.rank_base, idx))
-          my = idx | ((uint64_t)h << 32) | ((uint64_t)cand << 48);
-      }
-      const int cnt = (int)min((uint64_t)GL, e_end - e);
-      for (int jj = 0; jj < cnt; ++jj) {
-        const uint64_t ent = shfl64(my, gbase + jj);
-        const uint32_t idx = (uint32_t)(ent & 0xffffffffu);
-        if (idx == 0xffffffffu) continue;
-        const int h = (int)((ent >> 32) & 0xffff);
-        const int cand = (int)(ent >> 48);
-        const uint64_t mr = a.meta[idx];
-        const int sr = (int)(mr >> 48);
-        const int nr = (int)a.stabf[4 * sr];
-        if (nr == 0) continue;
-        const uint64_t offr = mr & kOffMask;
-        const int bond = cand >> 1;
-        const int bi = a.bonds[2 * bond], bj = a.bonds[2 * bond + 1];
-        const int ai = dev::digit(plab, bi, a.b, lmask), aj = dev::digit(plab, bj, a.b, lmask);
-        const A c = (A)(a.J[bond] * a.fac[((cand & 1) * a.dloc + ai) * a.dloc + aj]) * a.stabf[4 * sr + 2];
-        A t[DG];
-        if (a.stabf[4 * sr + 3] != A(0)) {
-#pragma unroll
-          for (int q = 0; q < DG; ++q) t[q] = vok ? (A)a.X[(offr + q) * a.ld + v] : A(0);
-        } else {
-          A xk[DG];
-#pragma unroll
-          for (int k = 0; k < DG; ++k) xk[k] = (vok && k < nr) ? (A)a.X[(offr + k) * a.ld + v] : A(0);
-          const A* Vr = a.V + (size_t)sr * DG * DG;
-#pragma unroll
-          for (int q = 0; q < DG; ++q) {
-            A s = A(0);
-#pragma unroll
-            for (int k = 0; k < DG; ++k) s += Vr[q * DG + k] * xk[k];
-            t[q] = s;
-          }
-        }
-        const A* R = a.rhoT + (size_t)h * DG * DG;
-#pragma unroll
-        for (int be = 0; be < DG; ++be) {
-          A s = A(0);
-#pragma unroll
-          for (int q = 0; q < DG; ++q) s += R[be * DG + q] * t[q];
-          acc[be] += c * s;
-        }
-      }
-    }
-    // project with V_p, add the diagonal, write
-    const A sqL = a.stabf[4 * sp + 1];
-    const bool ptriv = a.stabf[4 * sp + 3] != A(0);
-    const A* Vp = a.V + (size_t)sp * DG * DG;
-    const double ed = a.ediag[p];
-#pragma unroll
-    for (int k = 0; k < DG; ++k) {
-      if (k >= np_) break;
-      A y;
-      if (ptriv) {
-        y = acc[k];
-      } else {
-        A s = A(0);
-#pragma unroll
-        for (int be = 0; be < DG; ++be) s += Vp[be * DG + k] * acc[be];
-        y = s;
-      }
-      y *= sqL;
-      if (vok) {
-        const uint64_t at = (offp + k) * a.ld + v;
-        const A xv = (A)a.X[at];
-        const A hx = y + (A)ed * xv;
-        if (!EPI) {
-          a.Y[at] = (T)hx;
-        } else {
-          const A sj = (A)a.scal[2 * v], bsj = (A)a.scal[2 * v + 1];
-          const A w = sj * hx - bsj * (A)a.Y[at];
-          const T ws = (T)w;
-          a.Y[at] = ws;
-          dot += (double)a.X[at] * (double)ws;
-        }
-      }
-    }
-  }
-  if (EPI) {
-    __shared__ double red[kThreads];
-    red[threadIdx.x] = vok ? dot : 0.0;
-    __syncthreads();
-    if ((int)threadIdx.x < GL) {
-      double s = 0.0;
-      for (int q = 0; q < kThreads / GL; ++q) s += red[q * GL + threadIdx.x];
-      const int vv = blockIdx.y * 64 + threadIdx.x;
-      if (vv < a.nvec) a.partials[(size_t)blockIdx.x * a.nvec + vv] = s;
-    }
-  }
-}
-
-template <typename T, typename A, int DG, bool OTF, int NCH, bool LDS_TAB>
-void launch(const HvArgs<T, A>& a, dim3 grid, size_t shm, hipStream_t st) {
-  hipLaunchKernelGGL((k_hv<T, A, DG, OTF, NCH, LDS_TAB>), grid, dim3(kThreads), shm, st, a);
-}
-
-template <typename T, typename A, int DG>
-void launch_mode(const HvArgs<T, A>& a, const Sector& s, dim3 grid, hipStream_t st, bool otf, size_t tab_bytes,
-                 bool lds) {
-  if (!otf) {
-    // the label word width still matters: flips read p's digits
-    if (s.wide)
-      launch<T, A, DG, false, 16, false>(a, grid, 0, st);
+// Lanes per output representative (GL) and vectors per lane (VPL).  Default
+// (measured on MI355X for the s=1/2 icosidodecahedron H_g block): one lane per
+// vector up to 4 vectors, then about 3 vectors per lane, which keeps 64/GL
+// representatives in flight per wave.  gl > 0 forces GL (the autotuner's choice).
+Layout choose_layout(int nvec, bool otf, int gl = 0) {
+  Layout L{};
+  if (gl <= 0) {
+    if (nvec <= 4)
+      gl = pow2_at_least(nvec);
     else
-      launch<T, A, DG, false, 8, false>(a, grid, 0, st);
-    return;
+      gl = otf ? std::min(16, pow2_at_least((nvec + 3) / 4)) : pow2_at_least((nvec + 2) / 3);
   }
-  FTLM_DISPATCH_NCH(s.nch, {
-    if (lds)
-      launch<T, A, DG, true, NCH, true>(a, grid, tab_bytes, st);
-    else
-      launch<T, A, DG, true, NCH, false>(a, grid, 0, st);
-  });
-}
-
-template <typename T, typename A>
-void dispatch(const Block& b, const HvArgs<T, A>& a, dim3 grid, hipStream_t st, bool otf, size_t tab_bytes,
-              bool lds) {
-  const Sector& s = *b.sec;
-#define FTLM_DG_CASE(n)                                                           \
-  case n:                                                                         \
-    launch_mode<T, A, n>(a, s, grid, st, otf, tab_bytes, lds);                    \
-    break;
-  switch (b.dg) {
-    FTLM_DG_CASE(1) FTLM_DG_CASE(2) FTLM_DG_CASE(3) FTLM_DG_CASE(4) FTLM_DG_CASE(5) FTLM_DG_CASE(6)
-    FTLM_DG_CASE(7) FTLM_DG_CASE(8) FTLM_DG_CASE(9) FTLM_DG_CASE(10) FTLM_DG_CASE(11) FTLM_DG_CASE(12)
-    default:
-      fail(FTLM_ERR_DIM_GT_12, "irrep dimension above 12");
+  L.GL = std::min(64, pow2_at_least(gl));
+  L.VPL = vpl_bucket((std::min(nvec, 64 * 8) + L.GL - 1) / L.GL, otf);
+  if (L.GL * L.VPL > 64 && L.GL > 1) {
+    // keep a tile within 64 vectors
+    L.VPL = vpl_bucket(std::max(1, 64 / L.GL), otf);
   }
-#undef FTLM_DG_CASE
+  L.log2GL = 0;
+  while ((1 << L.log2GL) < L.GL) ++L.log2GL;
+  L.tile_w = L.GL * L.VPL;
+  L.tiles = (nvec + L.tile_w - 1) / L.tile_w;
+  return L;
 }
 
-int group_lanes(int nvec) {
-  int gl = 1;
-  while (gl < nvec && gl < 64) gl <<= 1;
-  return gl;
-}
-
-dim3 hv_grid(const Block& b, int nvec) {
-  const int gl = group_lanes(nvec);
-  const uint64_t slots_per_block = (uint64_t)(kThreads / 64) * (64 / gl);
+dim3 hv_grid(const Block& b, const Layout& L) {
+  const uint64_t slots_per_block = (uint64_t)(kThreads / 64) * (64 / L.GL);
   uint64_t gx = (b.sec->n_reps + slots_per_block - 1) / slots_per_block;
   gx = std::max<uint64_t>(1, std::min<uint64_t>(gx, 8192));
-  return dim3((unsigned)gx, (unsigned)((nvec + 63) / 64), 1);
+  return dim3((unsigned)gx, (unsigned)L.tiles, 1);
+}
+
+uint32_t align16(uint64_t x) { return (uint32_t)((x + 15u) & ~uint64_t(15)); }
+
+// Process-wide autotuner cache: lanes per representative for a kernel shape.
+struct TuneKey {
+  int N, two_s, G, dgp, nvec, dtype, mode;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(N, two_s, G, dgp, nvec, dtype, mode) < std::tie(o.N, o.two_s, o.G, o.dgp, o.nvec, o.dtype, o.mode);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+
+TuneKey tune_key(const Block& b, int nvec, int dtype) {
+  const Sector& s = *b.sec;
+  return TuneKey{s.N, s.two_s, s.G->order, b.dgp, nvec, dtype, s.hv_mode};
+}
+
+int tuned_gl(const Block& b, int nvec, int dtype) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune.find(tune_key(b, nvec, dtype));
+  return it == g_tune.end() ? 0 : it->second;
 }
 
 }  // namespace
 
-int hv_partial_groups(const Block& b, int nvec) { return (int)hv_grid(b, nvec).x; }
+int irrep_dim_bucket(int d) {
+  if (d >= 1 && d <= 6) return d;
+  if (d <= 8) return 8;
+  if (d <= 12) return 12;
+  return -1;
+}
+
+int hv_layout_lanes(const Block& b, int nvec, int dtype) {
+  return choose_layout(nvec, b.sec->hv_mode == FTLM_HV_ONTHEFLY, tuned_gl(b, nvec, dtype)).GL;
+}
+
+int hv_partial_groups(const Block& b, int nvec, int gl) {
+  return (int)hv_grid(b, choose_layout(nvec, b.sec->hv_mode == FTLM_HV_ONTHEFLY, gl)).x;
+}
 
 void apply_hv(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t st,
               const LanczosEpilogue* lz) {
+  apply_hv_gl(b, X, Y, nvec, ld, dtype, st, lz, tuned_gl(b, nvec, dtype));
+}
+
+std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dtype, hipStream_t st, int reps) {
+  std::vector<std::pair<int, double>> out;
+  if (b.D == 0 || b.sec->n_reps == 0) return out;
+  const size_t elem = dtype == FTLM_F64 ? 8 : 4;
+  DevBuf<uint8_t> X, Y;
+  X.alloc((size_t)b.D * nvec * elem);
+  Y.alloc((size_t)b.D * nvec * elem);
+  FTLM_HIP(hipMemsetAsync(X.p, 0, X.bytes(), st));
+  hipEvent_t e0, e1;
+  FTLM_HIP(hipEventCreate(&e0));
+  FTLM_HIP(hipEventCreate(&e1));
+  int best = 0;
+  double best_ms = 1e300;
+  for (int gl = 1; gl <= 64; gl <<= 1) {
+    if (gl * 8 < nvec || gl > pow2_at_least(nvec)) continue;  // VPL <= 8, no empty lanes beyond one pow2
+    apply_hv_gl(b, X.p, Y.p, nvec, nvec, dtype, st, nullptr, gl);  // warm
+    FTLM_HIP(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r) apply_hv_gl(b, X.p, Y.p, nvec, nvec, dtype, st, nullptr, gl);
+    FTLM_HIP(hipEventRecord(e1, st));
+    FTLM_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    FTLM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    const double per = ms / reps;
+    out.push_back({gl, per});
+    if (per < best_ms) {
+      best_ms = per;
+      best = gl;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(b, nvec, dtype)] = best;
+  }
+  return out;
+}
+
+void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t st,
+                 const LanczosEpilogue* lz, int gl) {
   const Sector& s = *b.sec;
   if (nvec <= 0 || ld < nvec) fail(FTLM_ERR_INVALID_ARG, "need 0 < nvec <= ld");
   if (b.D == 0 || s.n_reps == 0) return;
   if (!X || !Y) fail(FTLM_ERR_INVALID_ARG, "null vector");
   const bool otf = s.hv_mode == FTLM_HV_ONTHEFLY;
-  const int gl = group_lanes(nvec);
-  int log2gl = 0;
-  while ((1 << log2gl) < gl) ++log2gl;
-  const dim3 grid = hv_grid(b, nvec);
-  const size_t tab_words = (size_t)s.G->order * s.nch * 16;
-  const size_t tab_bytes = tab_words * (s.wide ? 8 : 4);
-  const bool lds = tab_bytes <= 65536;
+  const Layout L = choose_layout(nvec, otf, gl);
+  LaunchCfg c{};
+  c.grid = hv_grid(b, L);
+  c.otf = otf;
+  c.wide = s.wide;
+  c.nch = s.nch;
+  c.vpl = L.VPL;
+  const uint64_t tab_words = (uint64_t)s.G->order * s.nch * 16;
+  const uint64_t tab_bytes = tab_words * (s.wide ? 8 : 4);
+  const uint64_t DG = (uint64_t)b.dgp;
+  const uint64_t ns = (uint64_t)std::max(s.n_stab, 1);
+  // small tables first priority; the permutation table joins them in LDS when
+  // both fit, otherwise it is read through the caches
+  uint64_t small = 0;
+  small = align16(small + (uint64_t)s.G->order * (uint64_t)b.dgp * b.dgp * 8);
+  small = align16(small + (uint64_t)std::max(s.n_stab, 1) * b.dgp * b.dgp * 8);
+  small = align16(small + (uint64_t)std::max(s.n_stab, 1) * 4 * 8);
+  small = align16(small + (uint64_t)s.nbonds * 8);
+  small = align16(small + (uint64_t)(2 * s.d * s.d) * 8);
+  small = align16(small + (uint64_t)s.nbonds * 2 * 4);
+  c.lds_tab = otf && align16(tab_bytes) + (small <= kSmallLdsBudget ? small : 0) <= kLdsLimit;
+  const uint32_t base = c.lds_tab ? align16(tab_bytes) : 0;
+  uint64_t o = base;
+  const uint32_t o_rho = (uint32_t)o;
+  o = align16(o + (uint64_t)s.G->order * DG * DG * 8);
+  const uint32_t o_V = (uint32_t)o;
+  o = align16(o + ns * DG * DG * 8);
+  const uint32_t o_stab = (uint32_t)o;
+  o = align16(o + ns * 4 * 8);
+  const uint32_t o_J = (uint32_t)o;
+  o = align16(o + (uint64_t)s.nbonds * 8);
+  const uint32_t o_fac = (uint32_t)o;
+  o = align16(o + (uint64_t)(2 * s.d * s.d) * 8);
+  const uint32_t o_bonds = (uint32_t)o;
+  o = align16(o + (uint64_t)s.nbonds * 2 * 4);
+  c.slds = (o - base) <= kSmallLdsBudget && o <= kLdsLimit;
+  c.shm = c.slds ? o : base;
   auto fill = [&](auto& a) {
     a.reps = s.d_reps.p;
     a.row_ptr = s.d_row_ptr.p;
     a.entries = s.d_entries.p;
     a.meta = b.d_meta.p;
     a.ediag = s.d_ediag.p;
+    a.rhoT = b.d_rhoT64.p;
+    a.V = b.d_V64.p;
+    a.stabf = b.d_stabf64.p;
     a.bonds = s.d_bonds.p;
     a.J = s.d_J.p;
     a.fac = s.d_fac.p;
@@ -328,12 +209,20 @@ void apply_hv(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int 
     a.dloc = s.d;
     a.nbonds = s.nbonds;
     a.G = s.G->order;
-    a.n_stab = s.n_stab;
+    a.n_stab = (int)ns;
     a.n_reps = s.n_reps;
     a.ld = ld;
     a.nvec = nvec;
-    a.GL = gl;
-    a.log2GL = log2gl;
+    a.GL = L.GL;
+    a.log2GL = L.log2GL;
+    a.tile_w = L.tile_w;
+    a.zero = 0;
+    a.o_rho = o_rho;
+    a.o_V = o_V;
+    a.o_stab = o_stab;
+    a.o_J = o_J;
+    a.o_fac = o_fac;
+    a.o_bonds = o_bonds;
     a.tab = s.d_tab.p;
     a.cnt = s.d_cnt.p;
     a.rank_bits = s.d_rank_bits.p;
@@ -346,26 +235,33 @@ void apply_hv(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int 
     a.scal = lz ? lz->scal : nullptr;
     a.partials = lz ? lz->partials : nullptr;
   };
+  HvArgs<double> a64{};
+  HvArgs<float> a32{};
+  const HvArgs<double>* p64 = nullptr;
+  const HvArgs<float>* p32 = nullptr;
   if (dtype == FTLM_F64) {
-    HvArgs<double, double> a{};
-    fill(a);
-    a.rhoT = b.d_rhoT64.p;
-    a.V = b.d_V64.p;
-    a.stabf = b.d_stabf64.p;
-    a.X = (const double*)X;
-    a.Y = (double*)Y;
-    dispatch<double, double>(b, a, grid, st, otf, tab_bytes, lds);
+    fill(a64);
+    a64.X = (const double*)X;
+    a64.Y = (double*)Y;
+    p64 = &a64;
   } else if (dtype == FTLM_F32) {
-    HvArgs<float, float> a{};
-    fill(a);
-    a.rhoT = b.d_rhoT32.p;
-    a.V = b.d_V32.p;
-    a.stabf = b.d_stabf32.p;
-    a.X = (const float*)X;
-    a.Y = (float*)Y;
-    dispatch<float, float>(b, a, grid, st, otf, tab_bytes, lds);
+    fill(a32);
+    a32.X = (const float*)X;
+    a32.Y = (float*)Y;
+    p32 = &a32;
   } else {
     fail(FTLM_ERR_INVALID_ARG, "dtype must be FTLM_F64 or FTLM_F32");
+  }
+  switch (b.dgp) {
+    case 1: launch_dg<1>(p64, p32, c, st); break;
+    case 2: launch_dg<2>(p64, p32, c, st); break;
+    case 3: launch_dg<3>(p64, p32, c, st); break;
+    case 4: launch_dg<4>(p64, p32, c, st); break;
+    case 5: launch_dg<5>(p64, p32, c, st); break;
+    case 6: launch_dg<6>(p64, p32, c, st); break;
+    case 8: launch_dg<8>(p64, p32, c, st); break;
+    case 12: launch_dg<12>(p64, p32, c, st); break;
+    default: fail(FTLM_ERR_DIM_GT_12, "irrep dimension above 12");
   }
   FTLM_HIP(hipGetLastError());
 }

@@ -59,6 +59,7 @@ struct Block {
   std::shared_ptr<Sector> sec;  // shared with other blocks of the sector
   std::shared_ptr<Group> own_group;
   int irrep = 0, row = 0, dg = 0;
+  int dgp = 0;                  // kernel dimension bucket (tables zero-padded to it)
   uint64_t D = 0, n_active = 0;
   std::vector<double> rho;      // |G| x d x d (the irrep used)
   std::vector<uint8_t> n_stab;  // n_Gamma per stabilizer id
@@ -68,14 +69,11 @@ struct Block {
   // device
   DevBuf<uint64_t> d_meta;      // per representative: offset | stab_id << 48
   DevBuf<double> d_rhoT64;      // [g][beta][gamma] = rho(g)[gamma][beta]
-  DevBuf<float> d_rhoT32;
   DevBuf<double> d_V64;         // [s][gamma][k]
-  DevBuf<float> d_V32;
   DevBuf<double> d_stabf64;     // [s]: {n, sqrtL, 1/sqrtL, trivial}
-  DevBuf<float> d_stabf32;
   int64_t device_bytes() const {
-    return (int64_t)(d_meta.bytes() + d_rhoT64.bytes() + d_rhoT32.bytes() + d_V64.bytes() +
-                     d_V32.bytes() + d_stabf64.bytes() + d_stabf32.bytes()) + sec->device_bytes();
+    return (int64_t)(d_meta.bytes() + d_rhoT64.bytes() + d_V64.bytes() + d_stabf64.bytes()) +
+           sec->device_bytes();
   }
 };
 
@@ -86,6 +84,7 @@ void sector_canonicalize(const Sector& s, const uint64_t* labels, int64_t n, uin
 std::vector<uint64_t> sector_export_labels(const Sector& s);
 
 std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int row, const ftlm_opts* opts);
+void block_hv_stats(const Block& b, ftlm_hv_stats* st);
 
 // H.V (Eq. 15 in gather form + Eq. 16).  Optional Lanczos epilogue: when
 // lz != nullptr the output is w = s_j H q_j - bs_j q_prev written over q_prev
@@ -97,7 +96,16 @@ struct LanczosEpilogue {
 };
 void apply_hv(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t stream,
               const LanczosEpilogue* lz = nullptr);
-int hv_partial_groups(const Block& b, int nvec);
+// Lane layout: lanes per output representative for (nvec, dtype) (autotuned
+// or default), the partial-sum groups of that layout, and H.V with it fixed.
+int hv_layout_lanes(const Block& b, int nvec, int dtype);
+int hv_partial_groups(const Block& b, int nvec, int gl);
+void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t stream,
+                 const LanczosEpilogue* lz, int gl);
+// Times every lane layout for (nvec, dtype) on this block, caches the fastest
+// process-wide and returns (lanes per representative, ms per launch) pairs.
+std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dtype, hipStream_t st, int reps);
+int irrep_dim_bucket(int d);
 
 void run_lanczos(Block& b, int R, int steps, uint64_t seed, int storage, int dist, double* alpha,
                  double* beta, int32_t* nsteps, hipStream_t stream);

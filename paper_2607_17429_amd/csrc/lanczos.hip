@@ -86,11 +86,11 @@ __global__ void __launch_bounds__(256) k_update(const Chain* __restrict__ ch, ui
   const int t = threadIdx.x;
   const int RB = blockDim.x / R;
   const int v = t % R, r0 = t / R;
-  const T ca = (T)ch[v].ca;
+  const double ca = ch[v].ca;
   double acc = 0.0;
   for (uint64_t row = (uint64_t)blockIdx.x * RB + r0; row < D; row += (uint64_t)gridDim.x * RB) {
     const uint64_t at = row * R + v;
-    const T w = Wv[at] - ca * Qj[at];
+    const T w = (T)((double)Wv[at] - ca * (double)Qj[at]);
     Wv[at] = w;
     acc += (double)w * (double)w;
   }
@@ -212,7 +212,9 @@ void run_typed(Block& b, int R, int steps, uint64_t seed, int dist, int storage,
   const int TB = R * (256 / R);
   const int RB = TB / R;
   const unsigned nb_vec = blocks_for(D, RB);
-  const int ng_hv = hv_partial_groups(b, R);
+  // one lane layout for the whole run (the partial-sum buffer is sized for it)
+  const int gl = hv_layout_lanes(b, R, sizeof(T) == 8 ? FTLM_F64 : FTLM_F32);
+  const int ng_hv = hv_partial_groups(b, R, gl);
   const int ng_max = std::max<int>((int)nb_vec, ng_hv);
   DevBuf<T> q0, q1;
   q0.alloc(D * R);
@@ -247,7 +249,7 @@ void run_typed(Block& b, int R, int steps, uint64_t seed, int dist, int storage,
   const int dtype = sizeof(T) == 8 ? FTLM_F64 : FTLM_F32;
   for (int j = 0; j < target; ++j) {
     LanczosEpilogue lz{scal.p, partials.p, ng_hv};
-    apply_hv(b, qj, qprev, R, R, dtype, st, &lz);  // qprev <- w
+    apply_hv_gl(b, qj, qprev, R, R, dtype, st, &lz, gl);  // qprev <- w
     hipLaunchKernelGGL(k_alpha, dim3(R), dim3(256), 0, st, partials.p, ng_hv, R, ch.p, d_alpha.p, j, steps);
     hipLaunchKernelGGL((k_update<T>), dim3(nb_vec), dim3(TB), 0, st, ch.p, D, R, qj, qprev, partials.p);
     hipLaunchKernelGGL(k_beta, dim3(R), dim3(256), 0, st, partials.p, (int)nb_vec, R, ch.p, d_alpha.p, d_beta.p, scal.p, j,

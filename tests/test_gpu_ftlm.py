@@ -1,0 +1,98 @@
+"""GPU parity of the FTLM stage: batched Lanczos coefficients, Ritz data and E, C, chi.
+
+The oracle draws the same SplitMix64 start vectors with its own generator and
+runs its own FP64 Lanczos on Psi^H H Psi.  alpha/beta are compared only over the
+first steps (before any Ritz value converges, after which two correct FP64
+runs with different summation orders drift apart); the thermal observables
+are compared on the whole temperature grid.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import lib_block, log, oracle_block, oracle_group, oracle_sector
+from oracle import ftlm as oftlm
+from oracle import hv
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2607_17429_amd")
+
+T_GRID = np.geomspace(0.05, 10, 50)
+
+
+def test_lanczos_coefficients_fp64():
+    name, two_s, two_M, gi = "dodecahedron", 1, 0, 8
+    log(f"[lanczos] {name} irrep {gi}")
+    sec, H = oracle_sector(name, two_s, two_M)
+    B = oracle_block(name, two_s, two_M, gi)
+    LB = lib_block(name, two_s, two_M, gi)
+    Hb = (B.Psi.T @ H @ B.Psi).tocsr()
+    for dist, dname in ((P.RADEMACHER, "rademacher"), (P.GAUSSIAN, "gaussian")):
+        a, b, n = LB.ftlm(3, 40, 99, storage=P.F64, dist=dist)
+        assert np.all(n == 40)
+        for r in range(3):
+            v0 = oftlm.start_vector(B.D, 99, two_M, gi, 0, r, dname)
+            oa, ob = oftlm.lanczos(lambda x: Hb @ x, v0, 40)
+            assert np.max(np.abs(a[r, :15] - oa[:15])) < 1e-10 * np.max(np.abs(oa))
+            assert np.max(np.abs(b[r, :15] - ob[:15])) < 1e-10 * np.max(np.abs(ob))
+        # deterministic: a second run is bitwise identical
+        a2, b2, n2 = LB.ftlm(3, 40, 99, storage=P.F64, dist=dist)
+        assert np.array_equal(a, a2) and np.array_equal(b, b2)
+
+
+def test_small_and_empty_blocks():
+    # icosahedron M=5/2... all blocks of 2M=10 have D <= 1; A_u at 2M=6 is empty
+    log("[lanczos] tiny blocks")
+    for two_M, gi in ((10, 0), (10, 4), (6, 1)):
+        B = oracle_block("icosahedron", 1, two_M, gi)
+        LB = lib_block("icosahedron", 1, two_M, gi)
+        a, b, n = LB.ftlm(2, 30, 5, storage=P.F64)
+        assert np.all(n == min(B.D, 30))
+        if B.D == 1:
+            _, H = oracle_sector("icosahedron", 1, two_M)
+            assert np.allclose(a[:, 0], hv.block_matrix(B, H)[0, 0], atol=1e-14)
+
+
+def _ftlm_all_blocks(name, two_s, R, steps, seed, storage, dist):
+    cl, G, irs = oracle_group(name)
+    lib_blocks, ora_blocks = [], []
+    for two_M in range((cl.N * two_s) % 2, cl.N * two_s + 1, 2):
+        sec, H = oracle_sector(name, two_s, two_M)
+        for gi, ir in enumerate(irs):
+            B = oracle_block(name, two_s, two_M, gi)
+            if B.D == 0:
+                continue
+            LB = lib_block(name, two_s, two_M, gi)
+            a, b, n = LB.ftlm(R, steps, seed, storage=storage, dist=dist)
+            ths, ws = P.ritz_from_run(a, b, n)
+            lib_blocks.append(dict(two_M=two_M, d_gamma=ir.dim, D=B.D, thetas=ths, weights=ws))
+            Hb = hv.block_matrix(B, H)
+            oth, ow = [], []
+            for r in range(R):
+                v0 = oftlm.start_vector(B.D, seed, two_M, gi, 0, r, "rademacher" if dist == P.RADEMACHER else "gaussian")
+                t, w = oftlm.ritz(*oftlm.lanczos(lambda x: Hb @ x, v0, steps))
+                oth.append(t)
+                ow.append(w)
+            ora_blocks.append(oftlm.BlockRitz(two_M, ir.dim, B.D, oth, ow))
+    return lib_blocks, ora_blocks
+
+
+def _rel(x, ref):
+    return np.abs(x - ref) / np.abs(ref)
+
+
+@pytest.mark.parametrize("storage,tol", [(0, 1e-9), (1, 1e-6)])
+def test_observables_icosahedron_all_sectors(storage, tol):
+    """Icosahedron s=1/2, all M >= 0, all 10 irreps, R=4 Rademacher, 30 steps (per-T relative error)."""
+    log(f"[ftlm] icosahedron storage={storage}")
+    lib_blocks, ora_blocks = _ftlm_all_blocks("icosahedron", 1, 4, 30, 0x5EED0001, storage, P.RADEMACHER)
+    E, C, chi, lz = P.observables(lib_blocks, T_GRID)
+    Eo, Co, chio, lzo = oftlm.observables(ora_blocks, T_GRID, with_logZ=True)
+    eE, eC, eX = _rel(E, Eo), _rel(C, Co), _rel(chi, chio)
+    log(f"  max rel err E {eE.max():.2e} C {eC.max():.2e} chi {eX.max():.2e}")
+    assert eE.max() < tol and eC.max() < tol and eX.max() < tol
+    # exact high-temperature limits of the aggregate (Section 4.1)
+    E2, C2, chi2, lz2 = P.observables(lib_blocks, np.array([1e9]))
+    assert abs(np.exp(lz2[0]) / 2 ** 12 - 1) < 1e-6
+    assert abs(1e9 * chi2[0] / (12 * 0.75 / 3) - 1) < 1e-6

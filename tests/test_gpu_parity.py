@@ -2,8 +2,9 @@
 
 Integer data (representatives, stabilizer ids, orbit search, lookup, n_Gamma,
 offsets) must be bit-exact; FP64 H.V within 1e-12 relative (per column,
-infinity norm); FP32 H.V within 2e-6 relative of the oracle applied to the
-same FP32-rounded input.
+infinity norm); FP32 H.V within 2e-7 relative of the oracle applied to the
+same FP32-rounded input (FP32 is a storage format: the kernel forms products
+and sums in FP64 and rounds once on the store).
 """
 import numpy as np
 import pytest
@@ -112,7 +113,7 @@ def test_hv_batched_fp32_and_modes(name, two_s, two_M, gi):
             assert torch.equal(Yv[:, 0], Y[:, v])
         X32 = X.astype(np.float32)
         Y32 = LB.apply_H(torch.from_numpy(X32).cuda()).cpu().numpy()
-        assert rel_err_cols(Y32, hv.apply(B, H, X32.astype(np.float64))) <= 2e-6
+        assert rel_err_cols(Y32, hv.apply(B, H, X32.astype(np.float64))) <= 2e-7
     # repeated launches are bitwise identical
     X = torch.from_numpy(rng.standard_normal((B.D, 24))).cuda()
     Y1 = LB.apply_H(X)
