@@ -16,7 +16,6 @@ oracle on sampled output rows of the same block.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -39,11 +38,6 @@ WORKLOADS = {
                             desc="s=1/2 dodecahedron (N=20), I_h, M=0, irrep H_g (D=7,800); R=24 Rademacher, "
                                  "60 steps, FP64"),
 }
-
-
-def sha_of(path):
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
 def algorithmic_bytes(stats, D, n_reps, nvec, elem):
@@ -110,6 +104,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hv-reps", type=int, default=20)
+    ap.add_argument("--profile-hv", action="store_true",
+                    help="counter run: one 1 GiB copy (calibration) and 5 H.V launches, then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only "
@@ -145,6 +141,29 @@ def main():
         t3 = time.perf_counter()
         return dict(D=B.D, products=int(n.sum()), build=t1 - t0, lanczos=t2 - t1, thermo=t3 - t2, total=t3 - t0,
                     E0=float(min(t.min() for t in ths)))
+
+    if args.profile_hv:
+        G0 = P.Group(cl.N, cl.gens)
+        S0 = P.Sector(cl, G0, wl["two_M"], two_s=wl["two_s"])
+        B0 = P.Block(S0, wl["irrep"], 0)
+        tuned = B0.autotune(wl["R"], storage, stream=stream)
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)                     # calibration: reads and writes 1 GiB
+        tdt = torch.float32 if storage == P.F32 else torch.float64
+        X = torch.randn((B0.D, wl["R"]), dtype=tdt, device=dev)
+        Y = torch.empty_like(X)
+        torch.cuda.synchronize()
+        for _ in range(5):
+            B0.apply_H(X, Y, stream=stream)
+        torch.cuda.synchronize()
+        st = B0.hv_stats()
+        elem = 4 if storage == P.F32 else 8
+        print(json.dumps({"copy_bytes": 1 << 30, "hv_launches": 5, "lanes_per_rep": tuned[0],
+                          "algorithmic_bytes_per_launch": algorithmic_bytes(st, B0.D, S0.n_reps, wl["R"], elem),
+                          "stats": st}), flush=True)
+        return
 
     # autotune the H.V lane layout once for this kernel shape (cached process-wide)
     G0 = P.Group(cl.N, cl.gens)
@@ -195,11 +214,14 @@ def main():
     torch.cuda.synchronize()
     hv1_ms = ev0.elapsed_time(ev1) / 5
 
+    # HBM bytes per launch from the committed counter summary, valid only while
+    # the kernel source is the one the counters were taken on
+    from paper_2607_17429_amd.profiling import hv_source_sha
     traffic = None
     tp = os.path.join(ROOT, "profiles", f"hv_traffic_{args.workload}.json")
     if os.path.exists(tp):
         tj = json.load(open(tp))
-        if tj.get("source_sha") == sha_of(os.path.join(ROOT, "paper_2607_17429_amd", "csrc", "hv.hip")):
+        if tj.get("source_sha") == hv_source_sha():
             traffic = tj.get("bytes_per_launch")
 
     cpu = None

@@ -16,13 +16,25 @@ namespace ftlm {
 
 namespace {
 
-__global__ void k_rep_counts(const uint16_t* __restrict__ stab_id, uint64_t n, const uint8_t* __restrict__ n_stab,
-                             uint64_t* __restrict__ out, unsigned long long* __restrict__ per_stab) {
+// n_Gamma per representative, and the number of active representatives
+// (block-level sum, one atomic per workgroup).
+__global__ void __launch_bounds__(256) k_rep_counts(const uint16_t* __restrict__ stab_id, uint64_t n,
+                                                   const uint8_t* __restrict__ n_stab, uint64_t* __restrict__ out,
+                                                   unsigned long long* __restrict__ n_active) {
+  __shared__ unsigned long long red[256];
+  unsigned long long act = 0;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint16_t s = stab_id[i];
-    out[i] = n_stab[s];
-    atomicAdd(&per_stab[s], 1ull);
+    const uint8_t c = n_stab[stab_id[i]];
+    out[i] = c;
+    act += c ? 1 : 0;
   }
+  red[threadIdx.x] = act;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(n_active, red[0]);
 }
 
 __global__ void k_meta(const uint64_t* __restrict__ off, const uint16_t* __restrict__ stab_id, uint64_t n,
@@ -182,7 +194,7 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
     DevBuf<uint8_t> d_n;
     d_n.upload(B->n_stab);
     DevBuf<unsigned long long> per;
-    per.alloc(std::max(ns, 1));
+    per.alloc(1);
     FTLM_HIP(hipMemsetAsync(per.p, 0, per.bytes(), st));
     DevBuf<uint64_t> off;
     off.alloc(sec->n_reps + 1);
@@ -198,12 +210,10 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
     hipLaunchKernelGGL(k_meta, dim3(grid1(sec->n_reps)), dim3(256), 0, st, off.p, sec->d_stab_id.p, sec->n_reps,
                        B->d_meta.p);
     FTLM_HIP(hipGetLastError());
-    std::vector<unsigned long long> h_per(std::max(ns, 1));
-    FTLM_HIP(hipMemcpyAsync(h_per.data(), per.p, h_per.size() * 8, hipMemcpyDeviceToHost, st));
+    unsigned long long h_act = 0;
+    FTLM_HIP(hipMemcpyAsync(&h_act, per.p, sizeof(h_act), hipMemcpyDeviceToHost, st));
     FTLM_HIP(hipStreamSynchronize(st));
-    B->n_active = 0;
-    for (int s = 0; s < ns; ++s)
-      if (B->n_stab[s]) B->n_active += h_per[s];
+    B->n_active = h_act;
   }
   // rho^T[g][beta][gamma] = rho(g)[gamma][beta], zero-padded to the kernel's dimension bucket
   const int dp = B->dgp;

@@ -1,0 +1,116 @@
+"""Summaries of rocprofv3 output for the H.V kernel.
+
+* kernel-trace statistics (``--kernel-trace --stats --output-format csv``):
+  a table of the kernels by total time;
+* HBM traffic of the H.V kernel from two counter runs (``--pmc FETCH_SIZE``
+  and ``--pmc WRITE_SIZE`` of ``bench.py --profile-hv``): each counter is
+  scaled by what it reads for the 1 GiB device copy that the profile run does
+  first, and averaged over the H.V launches that follow the copy.
+
+Usage (after the rocprofv3 runs):
+  python -m paper_2607_17429_amd.profiling --stats DIR/trace_kernel_stats.csv \\
+      --fetch DIR/fetch_counter_collection.csv --write DIR/write_counter_collection.csv \\
+      --workload icosidodecahedron_Hg --out profiles --cmd "<the rocprofv3 commands>"
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+HV_SOURCES = ("csrc/hv_kernel.h", "csrc/hv.hip")
+
+
+def hv_source_sha() -> str:
+    h = hashlib.sha256()
+    for rel in HV_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_stats_markdown(stats_csv: str, top: int = 14) -> str:
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["| kernel | calls | avg ms | total ms | % |", "|---|---:|---:|---:|---:|"]
+    for r in rows[:top]:
+        name = r["Name"].replace("|", "/")
+        if len(name) > 110:
+            name = name[:107] + "..."
+        out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
+                   f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
+def _dispatches(path):
+    return list(csv.DictReader(open(path)))
+
+
+def counter_traffic(fetch_csv: str, write_csv: str, copy_bytes: int = 1 << 30, kernel_prefix: str = "void ftlm::hvk::k_hv"):
+    res = {}
+    for name, path in (("FETCH_SIZE", fetch_csv), ("WRITE_SIZE", write_csv)):
+        rows = _dispatches(path)
+        copy_idx = [i for i, r in enumerate(rows) if "copyBuffer" in r["Kernel_Name"] and float(r["Counter_Value"]) > 1e5]
+        if not copy_idx:
+            raise RuntimeError(f"no calibration copy in {path}")
+        ci = copy_idx[-1]
+        copy_kib = float(rows[ci]["Counter_Value"])
+        scale = copy_bytes / (copy_kib * 1024.0)
+        hv = [r for r in rows[ci + 1:] if r["Kernel_Name"].startswith(kernel_prefix)]
+        if not hv:
+            raise RuntimeError(f"no H.V dispatch after the copy in {path}")
+        kib = sum(float(r["Counter_Value"]) for r in hv) / len(hv)
+        ms = sum((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) for r in hv) / len(hv) / 1e6
+        res[name] = dict(raw_kib_per_launch=kib, copy_raw_kib=copy_kib, scale=scale,
+                         bytes_per_launch=kib * 1024.0 * scale, launches=len(hv), avg_ms_under_counters=ms,
+                         kernel=hv[0]["Kernel_Name"])
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--stats", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--out", default="profiles")
+    ap.add_argument("--cmd", default="")
+    ap.add_argument("--bench-json", default=None, help="bench.py output line, for the algorithmic bytes")
+    args = ap.parse_args()
+    os.makedirs(args.out, exist_ok=True)
+    tr = counter_traffic(args.fetch, args.write)
+    total = tr["FETCH_SIZE"]["bytes_per_launch"] + tr["WRITE_SIZE"]["bytes_per_launch"]
+    balg = None
+    if args.bench_json:
+        bj = json.loads(open(args.bench_json).read().strip().splitlines()[-1])
+        balg = bj["roofline"]["algorithmic_bytes_per_launch"]
+    rec = dict(source_sha=hv_source_sha(), bytes_per_launch=total, fetch=tr["FETCH_SIZE"], write=tr["WRITE_SIZE"],
+               algorithmic_bytes_per_launch=balg, command=args.cmd)
+    with open(os.path.join(args.out, f"hv_traffic_{args.workload}.json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    md = [f"# k_hv on {args.workload}: rocprofv3 summary", "",
+          "Commands (from the repository root of the GPU box):", "", "```", args.cmd, "```", "",
+          "## Kernel trace statistics (one bench step, `bench.py --steps 1 --warmup 0 --no-cpu-baseline`)", "",
+          kernel_stats_markdown(args.stats), "",
+          "## HBM traffic of one H.V launch (`bench.py --profile-hv`)", "",
+          "| counter | raw KiB / launch | calibration (1 GiB copy) raw KiB | scale | bytes / launch |",
+          "|---|---:|---:|---:|---:|"]
+    for k in ("FETCH_SIZE", "WRITE_SIZE"):
+        t = tr[k]
+        md.append(f"| {k} | {t['raw_kib_per_launch']:.0f} | {t['copy_raw_kib']:.0f} | {t['scale']:.3f} | "
+                  f"{t['bytes_per_launch'] / 1e9:.3f} GB |")
+    md.append(f"| total | | | | {total / 1e9:.3f} GB |")
+    if balg:
+        md += ["", f"Algorithmic bytes per launch (byte model): {balg / 1e9:.3f} GB; "
+                   f"measured / algorithmic = {total / balg:.3f}."]
+    md += ["", f"Kernel source hash (hv_kernel.h + hv.hip): `{rec['source_sha']}`", ""]
+    with open(os.path.join(args.out, f"k_hv_{args.workload}.md"), "w") as f:
+        f.write("\n".join(md))
+    print(json.dumps({"traffic_bytes_per_launch": total, "algorithmic": balg}))
+
+
+if __name__ == "__main__":
+    main()
