@@ -95,6 +95,79 @@ def cpu_baseline(wl, seconds):
                        f"{el:.1f} s single-threaded Python/NumPy")
 
 
+SERVE_CLUSTERS = ("icosahedron", "cuboctahedron", "dodecahedron", "square4x4", "square6x6")
+SERVE_DESC = ("Poisson stream of FTLM jobs drawn uniformly from the s=1/2 icosahedron (I_h), cuboctahedron "
+              "(O_h), dodecahedron (I_h), 4x4 and 6x6 square tori (translations x C4v, orders 128, 288); "
+              "uniform 2M >= 0, irrep, row; R uniform in 4..24; 60 steps; FP64 or FP32 storage; Rademacher")
+
+
+def draw_jobs(rng, n, groups, clusters):
+    """Seeded job descriptions of the serving mix."""
+    jobs = []
+    for _ in range(n):
+        name = SERVE_CLUSTERS[rng.integers(len(SERVE_CLUSTERS))]
+        cl = clusters.get(name)
+        dims = groups[name]
+        gi = int(rng.integers(len(dims)))
+        jobs.append(dict(cluster=name, two_M=int(2 * rng.integers(cl.N // 2 + 1)), irrep=gi,
+                         row=int(rng.integers(dims[gi])), R=int(rng.integers(4, 25)), steps=60,
+                         seed=int(rng.integers(1 << 62)), storage=("f64", "f32")[int(rng.integers(2))]))
+    return jobs
+
+
+def serve(P, np, n_warm, n_jobs, rate, budget_gb, max_active, seed=0x5E4E):
+    """Warm-up burst, a closed burst (capacity), then an open Poisson stream (latency).
+
+    A job's latency runs from its submission to its coefficients on the host;
+    queueing, table builds on a cold cache and the Lanczos run are all inside.
+    """
+    from synth import clusters
+    groups = {n: list(P.Group(clusters.get(n).N, clusters.get(n).gens).irreps()["dims"]) for n in SERVE_CLUSTERS}
+    rng = np.random.default_rng(seed)
+    srv = P.Server(int(budget_gb * (1 << 30)), max_active=max_active)
+    F = {"f64": P.F64, "f32": P.F32}
+
+    def submit(j):
+        cl = clusters.get(j["cluster"])
+        return srv.submit(cl, cl.gens, j["two_M"], j["irrep"], j["row"], j["R"], j["steps"], j["seed"],
+                          storage=F[j["storage"]], dist=P.RADEMACHER, two_s=1)
+
+    def run(jobs, arrivals):
+        t0 = time.perf_counter()
+        ids = []
+        for j, ta in zip(jobs, arrivals):
+            dt = ta - (time.perf_counter() - t0)
+            if dt > 0:
+                time.sleep(dt)
+            ids.append(submit(j))
+        res = [srv.wait(i) for i in ids]
+        for r, j in zip(res, jobs):
+            if r[0]["status"] != 0:
+                raise RuntimeError(f"serving job failed: {j} -> {r[0]}")
+        span = max(r[0]["end_s"] for r in res) - min(r[0]["submit_s"] for r in res)
+        lat = np.array([r[0]["end_s"] - r[0]["submit_s"] for r in res]) * 1e3
+        wait = np.array([r[0]["start_s"] - r[0]["submit_s"] for r in res]) * 1e3
+        work = sum(int(r[0]["D"]) * int(r[3].sum()) for r in res)
+        return dict(jobs=len(jobs), span_s=span, jobs_per_s=len(jobs) / span, elem_vec_per_s=work / span,
+                    p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                    max_ms=float(lat.max()), queue_p50_ms=float(np.percentile(wait, 50)),
+                    queue_p99_ms=float(np.percentile(wait, 99)))
+
+    t = time.perf_counter()
+    warm = draw_jobs(rng, n_warm, groups, clusters)
+    run(warm, [0.0] * n_warm)
+    warm_s = time.perf_counter() - t
+    burst = run(draw_jobs(rng, n_jobs, groups, clusters), [0.0] * n_jobs)
+    lam = rate if rate else 0.7 * burst["jobs_per_s"]
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, n_jobs))
+    stream = run(draw_jobs(rng, n_jobs, groups, clusters), arrivals)
+    stats = srv.stats()
+    srv.close()
+    return dict(workload=SERVE_DESC, warmup_jobs=n_warm, warmup_s=warm_s, max_active=max_active,
+                budget_gb=budget_gb, closed_burst=burst, poisson=dict(rate_jobs_per_s=lam, **stream),
+                resident_bytes_after=stats["used_bytes"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,6 +179,12 @@ def main():
     ap.add_argument("--hv-reps", type=int, default=20)
     ap.add_argument("--profile-hv", action="store_true",
                     help="counter run: one 1 GiB copy (calibration) and 5 H.V launches, then exit")
+    ap.add_argument("--serve", action="store_true", help="run the job-server benchmark (serving mix) instead")
+    ap.add_argument("--serve-jobs", type=int, default=200)
+    ap.add_argument("--serve-warm", type=int, default=100)
+    ap.add_argument("--serve-rate", type=float, default=0.0, help="Poisson rate in jobs/s (0: 0.7 x burst rate)")
+    ap.add_argument("--serve-active", type=int, default=8)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only "
@@ -117,6 +196,17 @@ def main():
 
     import paper_2607_17429_amd as P
     from synth import clusters
+
+    if args.serve:
+        torch.cuda.set_device(0)
+        res = serve(P, np, args.serve_warm, args.serve_jobs, args.serve_rate, args.serve_budget_gb,
+                    args.serve_active)
+        p = res["poisson"]
+        print(json.dumps({"metric": "FTLM job latency under a Poisson stream (serving mix)", "value": p["p50_ms"],
+                          "unit": "ms (p50)", "n_gpus": 1, "higher_is_better": False, "dtype": "f64/f32",
+                          "data": "synthetic", "config": {"workload": SERVE_DESC}, "p99_ms": p["p99_ms"],
+                          "serving": res}), flush=True)
+        return
 
     wl = WORKLOADS[args.workload]
     cl = clusters.get(wl["cluster"])

@@ -62,6 +62,17 @@ class HvStats(C.Structure):
                 ("gathered_rows", C.c_uint64)]
 
 
+class JobDesc(C.Structure):
+    _fields_ = [("cluster", Cluster), ("gens", C.POINTER(C.c_int32)), ("ngens", C.c_int32), ("two_M", C.c_int32),
+                ("irrep", C.c_int32), ("row", C.c_int32), ("R", C.c_int32), ("steps", C.c_int32),
+                ("seed", C.c_uint64), ("storage", C.c_int32), ("dist", C.c_int32)]
+
+
+class JobResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("R", C.c_int32), ("steps", C.c_int32), ("d_gamma", C.c_int32),
+                ("D", C.c_uint64), ("submit_s", C.c_double), ("start_s", C.c_double), ("end_s", C.c_double)]
+
+
 class Ritz(C.Structure):
     _fields_ = [("two_M", C.c_int32), ("d_gamma", C.c_int32), ("D", C.c_uint64), ("R", C.c_int32),
                 ("ld", C.c_int32), ("nsteps", C.POINTER(C.c_int32)),
@@ -72,7 +83,7 @@ VP = C.c_void_p
 I32P = C.POINTER(C.c_int32)
 F64P = C.POINTER(C.c_double)
 
-# name -> (restype, argtypes); every symbol declared in include/ftlm.h
+# name -> (restype, argtypes); every symbol declared in include/ftlm.h and include/ftlm_server.h
 SIGNATURES = {
     "ftlm_last_error": (C.c_char_p, []),
     "ftlm_group_create": (C.c_int, [C.c_int32, I32P, C.c_int32, C.POINTER(VP)]),
@@ -99,6 +110,14 @@ SIGNATURES = {
     "ftlm_tridiag_ritz": (C.c_int, [F64P, F64P, C.c_int32, F64P, F64P]),
     "ftlm_observables": (C.c_int, [C.POINTER(Ritz), C.c_int32, F64P, C.c_int32, C.c_double, F64P, F64P, F64P, F64P]),
     "ftlm_block_free": (None, [VP]),
+    # include/ftlm_server.h
+    "ftlm_server_create": (C.c_int, [C.c_int64, C.c_int32, C.POINTER(VP)]),
+    "ftlm_server_submit": (C.c_int, [VP, C.POINTER(JobDesc), C.POINTER(C.c_int64)]),
+    "ftlm_server_wait": (C.c_int, [VP, C.c_int64, C.POINTER(JobResult), F64P, F64P, I32P]),
+    "ftlm_server_poll": (C.c_int, [VP, C.c_int64, I32P]),
+    "ftlm_server_cancel": (C.c_int, [VP, C.c_int64]),
+    "ftlm_server_stats": (C.c_int, [VP, C.POINTER(C.c_int64), I32P, I32P]),
+    "ftlm_server_free": (None, [VP]),
 }
 
 _lib = None

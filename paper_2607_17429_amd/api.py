@@ -117,7 +117,8 @@ class Block:
         """One call: group + sector + block (ftlm_build_block)."""
         self = cls.__new__(cls)
         self.sector = None
-        cl = L.make_cluster(cluster.N, two_s if two_s is not None else cluster.two_s, cluster.bonds, cluster.J)
+        cl = L.make_cluster(cluster.N, two_s if two_s is not None else getattr(cluster, "two_s", 1), cluster.bonds,
+                            cluster.J)
         gens = np.ascontiguousarray(np.asarray(gens, dtype=np.int32).reshape(-1, cluster.N))
         opts = L.make_opts(hv_mode=hv_mode, user_rho=user_rho)
         h = C.c_void_p()

@@ -99,8 +99,8 @@ __global__ void k_hv_stats(const uint64_t* __restrict__ meta, const uint64_t* __
 
 }  // namespace
 
-void block_hv_stats(const Block& b, ftlm_hv_stats* st) {
-  std::memset(st, 0, sizeof(*st));
+void block_hv_stats(const Block& b, ftlm_hv_stats* res) {
+  std::memset(res, 0, sizeof(*res));
   const Sector& s = *b.sec;
   if (!s.n_reps) return;
   if (s.hv_mode != FTLM_HV_ENTRIES) fail(FTLM_ERR_UNSUPPORTED, "work counts need the entry table");
@@ -108,16 +108,18 @@ void block_hv_stats(const Block& b, ftlm_hv_stats* st) {
   d_n.upload(b.n_stab);
   DevBuf<unsigned long long> out;
   out.alloc(4);
-  FTLM_HIP(hipMemset(out.p, 0, out.bytes()));
-  hipLaunchKernelGGL(k_hv_stats, dim3(grid1(s.n_reps)), dim3(256), 0, nullptr, b.d_meta.p, s.d_row_ptr.p,
+  hipStream_t st = tl_alloc_stream;
+  FTLM_HIP(hipMemsetAsync(out.p, 0, out.bytes(), st));
+  hipLaunchKernelGGL(k_hv_stats, dim3(grid1(s.n_reps)), dim3(256), 0, st, b.d_meta.p, s.d_row_ptr.p,
                      s.d_entries.p, d_n.p, s.n_reps, out.p);
   FTLM_HIP(hipGetLastError());
   unsigned long long h[4];
-  FTLM_HIP(hipMemcpy(h, out.p, sizeof(h), hipMemcpyDeviceToHost));
-  st->n_active = h[0];
-  st->connections = h[1];
-  st->active_connections = h[2];
-  st->gathered_rows = h[3];
+  FTLM_HIP(hipMemcpyAsync(h, out.p, sizeof(h), hipMemcpyDeviceToHost, st));
+  FTLM_HIP(hipStreamSynchronize(st));
+  res->n_active = h[0];
+  res->connections = h[1];
+  res->active_connections = h[2];
+  res->gathered_rows = h[3];
 }
 
 std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int row, const ftlm_opts* opts) {
@@ -188,7 +190,7 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
     B->L_stab[s] = (double)n / (double)S.size();
     B->trivial[s] = (S.size() == 1) ? 1 : 0;
   }
-  hipStream_t st = nullptr;
+  hipStream_t st = tl_alloc_stream;  // the caller's build stream, or the null stream
   // device tables
   if (sec->n_reps) {
     DevBuf<uint8_t> d_n;

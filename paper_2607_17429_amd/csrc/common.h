@@ -32,42 +32,78 @@ void set_last_error(const std::string& msg);
     }                                                                                    \
   } while (0)
 
+// Stream for stream-ordered allocation on this thread (nullptr: plain
+// hipMalloc/hipFree).  The job server sets it so that building one job's
+// tables never waits for other jobs' kernels (hipFree synchronizes the device).
+inline thread_local hipStream_t tl_alloc_stream = nullptr;
+
+struct AllocStreamScope {
+  hipStream_t prev;
+  explicit AllocStreamScope(hipStream_t s) : prev(tl_alloc_stream) { tl_alloc_stream = s; }
+  ~AllocStreamScope() { tl_alloc_stream = prev; }
+};
+
 // Device buffer owned by a host object (freed in the destructor).
 template <typename T>
 struct DevBuf {
   T* p = nullptr;
   size_t n = 0;
+  hipStream_t s = nullptr;  // allocation stream when stream-ordered
+  bool async = false;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), n(o.n), s(o.s), async(o.async) { o.p = nullptr; o.n = 0; }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; n = o.n; s = o.s; async = o.async;
+      o.p = nullptr; o.n = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
   void alloc(size_t count) {
     release();
     if (count == 0) return;
-    FTLM_HIP(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
+    if (tl_alloc_stream) {
+      FTLM_HIP(hipMallocAsync(reinterpret_cast<void**>(&p), count * sizeof(T), tl_alloc_stream));
+      s = tl_alloc_stream;
+      async = true;
+    } else {
+      FTLM_HIP(hipMalloc(reinterpret_cast<void**>(&p), count * sizeof(T)));
+      s = nullptr;
+      async = false;
+    }
     n = count;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (async)
+        (void)hipFreeAsync(p, s);
+      else
+        (void)hipFree(p);
+    }
     p = nullptr;
     n = 0;
   }
   size_t bytes() const { return n * sizeof(T); }
-  void upload(const T* h, size_t count, hipStream_t s = nullptr) {
+  // Synchronous host -> device copy (the host array may go away afterwards).
+  void upload(const T* h, size_t count, hipStream_t st = nullptr) {
     alloc(count);
-    if (count) FTLM_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, s));
+    if (!st) st = tl_alloc_stream;
+    if (count) {
+      FTLM_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, st));
+      FTLM_HIP(hipStreamSynchronize(st));
+    }
   }
-  void upload(const std::vector<T>& v, hipStream_t s = nullptr) { upload(v.data(), v.size(), s); }
-  std::vector<T> download(hipStream_t s = nullptr) const {
+  void upload(const std::vector<T>& v, hipStream_t st = nullptr) { upload(v.data(), v.size(), st); }
+  std::vector<T> download(hipStream_t st = nullptr) const {
     std::vector<T> h(n);
+    if (!st) st = tl_alloc_stream;
     if (n) {
-      FTLM_HIP(hipMemcpyAsync(h.data(), p, n * sizeof(T), hipMemcpyDeviceToHost, s));
-      FTLM_HIP(hipStreamSynchronize(s));
+      FTLM_HIP(hipMemcpyAsync(h.data(), p, n * sizeof(T), hipMemcpyDeviceToHost, st));
+      FTLM_HIP(hipStreamSynchronize(st));
     }
     return h;
   }

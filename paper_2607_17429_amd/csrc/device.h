@@ -112,20 +112,57 @@ __device__ __forceinline__ void chunk_offsets(W a, int* off) {
   for (int c = 0; c < NCH; ++c) off[c] = c * 16 + (int)((a >> (4 * c)) & W(15));
 }
 
-// Orbit minimum and the smallest group index h reaching it (U(h) a = best).
-// Every lane of the wave walks the group elements in the same order, so the
-// table reads of one step hit at most 16 distinct words per chunk.
+// Chunk tables of a factored group G = T H (every g = t h exactly once):
+// the tables of the |H| elements, then those of the |T| elements, then
+// gidx[t * |H| + h] = index of t h (uint16).  With H = {e} the T tables are
+// those of every element in index order.
 template <typename W, int NCH>
-__device__ __forceinline__ void canon_min(W a, const W* __restrict__ tab, int G, W& best, int& bestg) {
-  int off[NCH];
-  chunk_offsets<W, NCH>(a, off);
+struct OrbitTabs {
+  const W* H;
+  const W* T;
+  const uint16_t* gidx;
+  int nH, nT;
+};
+
+template <typename W, int NCH>
+__device__ __forceinline__ OrbitTabs<W, NCH> orbit_tabs(const W* tab, int nH, int nT) {
+  OrbitTabs<W, NCH> o;
+  o.H = tab;
+  o.T = tab + (size_t)nH * NCH * 16;
+  o.gidx = reinterpret_cast<const uint16_t*>(tab + (size_t)(nH + nT) * NCH * 16);
+  o.nH = nH;
+  o.nT = nT;
+  return o;
+}
+
+// Orbit minimum and the smallest group index h reaching it (U(h) a = best).
+// Every lane of the wave walks the (h, t) pairs in the same order, so the
+// table reads of one step hit at most 16 distinct words per chunk; ties on
+// the image are broken by the group index, so the result does not depend on
+// the walk order.
+template <typename W, int NCH>
+__device__ __forceinline__ void canon_min(W a, const OrbitTabs<W, NCH>& o, W& best, int& bestg) {
+  int offa[NCH];
+  chunk_offsets<W, NCH>(a, offa);
   best = a;
   bestg = 0;
-  for (int g = 1; g < G; ++g) {
-    W img = permute<W, NCH>(tab, g, off);
-    if (img < best) {
-      best = img;
-      bestg = g;
+  for (int hi = 0; hi < o.nH; ++hi) {
+    int off[NCH];
+    if (hi == 0) {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) off[c] = offa[c];
+    } else {
+      chunk_offsets<W, NCH>(permute<W, NCH>(o.H, hi, offa), off);
+    }
+    for (int ti = hi == 0 ? 1 : 0; ti < o.nT; ++ti) {
+      const W img = permute<W, NCH>(o.T, ti, off);
+      if (img <= best) {
+        const int g = o.gidx[ti * o.nH + hi];
+        if (img < best || g < bestg) {
+          best = img;
+          bestg = g;
+        }
+      }
     }
   }
 }

@@ -104,6 +104,7 @@ Group build_group(int N, const int32_t* gens, int ngens) {
   G.perms.resize((size_t)n * N);
   for (int i = 0; i < n; ++i)
     for (int k = 0; k < N; ++k) G.perms[(size_t)i * N + k] = (unsigned char)elems[i][k];
+  for (const Perm& g : gen) G.gen_idx.push_back(index.at(g));
   G.mul.resize((size_t)n * n);
   for (int a = 0; a < n; ++a)
     for (int b = 0; b < n; ++b) G.mul[(size_t)a * n + b] = (uint16_t)index.at(compose(elems[a], elems[b]));
@@ -334,6 +335,85 @@ void compute_irreps(Group& G) {
     return;
   }
   fail(FTLM_ERR_IRREPS_FAILED, "irrep construction did not pass verification");
+}
+
+}  // namespace ftlm
+
+namespace ftlm {
+
+namespace {
+
+// Subgroup generated by the given elements (closure under right
+// multiplication by the generators), as a membership mask.
+std::vector<char> generated(const Group& G, const std::vector<int>& gens) {
+  std::vector<char> in(G.order, 0);
+  std::vector<int> list{0};
+  in[0] = 1;
+  for (size_t i = 0; i < list.size(); ++i)
+    for (int s : gens) {
+      const int y = G.idx_mul(list[i], s);
+      if (!in[y]) {
+        in[y] = 1;
+        list.push_back(y);
+      }
+    }
+  return in;
+}
+
+}  // namespace
+
+Factorization factor_group(const Group& G, int max_plain) {
+  const int n = G.order;
+  std::vector<char> best;
+  int best_h = 1;
+  if (n > max_plain) {
+    long best_cost = (long)n + 1;
+    auto consider = [&](const std::vector<int>& gens) {
+      std::vector<char> in = generated(G, gens);
+      int h = 0;
+      for (char c : in) h += c;
+      const long cost = (long)h + n / h;
+      if (cost < best_cost || (cost == best_cost && h < best_h)) {
+        best_cost = cost;
+        best_h = h;
+        best = std::move(in);
+      }
+    };
+    const int ng = std::min<int>((int)G.gen_idx.size(), 10);
+    for (int m = 1; m < (1 << ng); ++m) {
+      std::vector<int> gs;
+      for (int k = 0; k < ng; ++k)
+        if ((m >> k) & 1) gs.push_back(G.gen_idx[k]);
+      consider(gs);
+    }
+    for (int g = 1; g < n; ++g) consider({g});
+    std::vector<int> reps;
+    for (const auto& c : G.classes) reps.push_back(c[0]);
+    if (reps.size() > 64) reps.clear();  // pairs only while they stay cheap
+    for (size_t i = 0; i < reps.size(); ++i)
+      for (size_t j = i + 1; j < reps.size(); ++j) consider({reps[i], reps[j]});
+  }
+  Factorization f;
+  if (best.empty()) {
+    best.assign(n, 0);
+    best[0] = 1;
+    best_h = 1;
+  }
+  for (int g = 0; g < n; ++g)
+    if (best[g]) f.H.push_back(g);  // ascending, so H[0] = identity
+  // left cosets t H, each represented by its smallest element
+  std::vector<char> covered(n, 0);
+  for (int g = 0; g < n; ++g) {
+    if (covered[g]) continue;
+    f.T.push_back(g);
+    for (int h : f.H) covered[G.idx_mul(g, h)] = 1;
+  }
+  const int nH = (int)f.H.size(), nT = (int)f.T.size();
+  if ((long)nH * nT != n) fail(FTLM_ERR_INVALID_ARG, "internal: coset decomposition does not cover the group");
+  f.gidx.resize((size_t)nT * nH);
+  for (int t = 0; t < nT; ++t)
+    for (int h = 0; h < nH; ++h) f.gidx[(size_t)t * nH + h] = (uint16_t)G.idx_mul(f.T[t], f.H[h]);
+  return f;
 }
 
 }  // namespace ftlm

@@ -163,7 +163,7 @@ void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
   c.wide = s.wide;
   c.nch = s.nch;
   c.vpl = L.VPL;
-  const uint64_t tab_words = (uint64_t)s.G->order * s.nch * 16;
+  const uint64_t tab_words = s.tab_words;
   const uint64_t tab_bytes = tab_words * (s.wide ? 8 : 4);
   const uint64_t DG = (uint64_t)b.dgp;
   const uint64_t ns = (uint64_t)std::max(s.n_stab, 1);
@@ -209,6 +209,8 @@ void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
     a.dloc = s.d;
     a.nbonds = s.nbonds;
     a.G = s.G->order;
+    a.nH = s.fac_nH;
+    a.nT = s.fac_nT;
     a.n_stab = (int)ns;
     a.n_reps = s.n_reps;
     a.ld = ld;

@@ -68,6 +68,7 @@ struct HvArgs {
   const double* J;
   const double* fac;    // [2][dloc][dloc]
   int b, dloc, nbonds, G, n_stab;
+  int nH, nT;           // factored group G = T H of the on-the-fly search
   uint64_t n_reps;
   const T* X;
   T* Y;
@@ -130,6 +131,7 @@ k_hv(HvArgs<T> a) {
   const bool EPI = a.partials != nullptr;
   const W* tab = nullptr;
   if constexpr (OTF) tab = LDS_TAB ? stage<W>((const W*)a.tab, a.tab_words, sm) : (const W*)a.tab;
+  const dev::OrbitTabs<W, NCH> otabs = dev::orbit_tabs<W, NCH>(tab, a.nH, a.nT);
   const double* rhoT = a.rhoT;
   const double* Vt = a.V;
   const double* stabf = a.stabf;
@@ -198,7 +200,7 @@ k_hv(HvArgs<T> a) {
         }
         W r;
         int h;
-        dev::canon_min<W, NCH>(x, tab, a.G, r, h);
+        dev::canon_min<W, NCH>(x, otabs, r, h);
         uint64_t idx = 0;
         if (ok && lookup_rep<W>(r, a.N, a.b, a.dloc, a.A_tot, a.cnt, a.cnt_stride, a.D_M, a.rank_bits, a.rank_base, idx))
           my = idx | ((uint64_t)h << 32) | ((uint64_t)cand << 48);

@@ -35,7 +35,11 @@ struct Sector {
   std::vector<std::vector<int32_t>> stab_elems;  // per stabilizer id
   int32_t n_stab = 0;
   // device tables
-  DevBuf<uint64_t> d_tab;       // |G| x nch x 16 words (uint32 or uint64 payload)
+  // chunk tables of the factored group G = T H: (|H| + |T|) x nch x 16 words
+  // (uint32 or uint64 payload), then |T| x |H| uint16 element indices
+  DevBuf<uint64_t> d_tab;
+  int fac_nH = 1, fac_nT = 1;
+  uint32_t tab_words = 0;       // in payload words
   DevBuf<uint64_t> d_cnt;
   DevBuf<uint64_t> d_rank_bits; // bitmap over sector ranks
   DevBuf<uint32_t> d_rank_base; // representatives before each word
@@ -106,6 +110,25 @@ void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
 // process-wide and returns (lanes per representative, ms per launch) pairs.
 std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dtype, hipStream_t st, int reps);
 int irrep_dim_bucket(int d);
+
+// One batched Lanczos run of R chains on a block: device state, an enqueue of
+// every kernel on one stream (no host synchronisation) and an asynchronous
+// copy of alpha, beta and the per-chain step counts.
+struct LanczosRun {
+  const Block* block;
+  int R, steps, storage, dist;
+  uint64_t seed;
+  int target = 0, TB = 0, nb_vec = 0, gl = 0, ng_hv = 0;
+  DevBuf<uint8_t> q0, q1, chain;
+  DevBuf<uint64_t> keys;
+  DevBuf<double> partials, inv_norm, scal, d_alpha, d_beta;
+  DevBuf<int32_t> d_n;
+  LanczosRun(const Block& b, int R, int steps, uint64_t seed, int storage, int dist);
+  static size_t estimate_bytes(const Block& b, int R, int steps, int storage);
+  void allocate();                 // device buffers (stream-ordered if an allocation stream is set)
+  void enqueue(hipStream_t st);    // start vectors + all steps
+  void download(hipStream_t st, double* alpha, double* beta, int32_t* nsteps);
+};
 
 void run_lanczos(Block& b, int R, int steps, uint64_t seed, int storage, int dist, double* alpha,
                  double* beta, int32_t* nsteps, hipStream_t stream);

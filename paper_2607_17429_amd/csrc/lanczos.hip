@@ -201,68 +201,43 @@ unsigned blocks_for(uint64_t rows, int RB) {
 }
 
 template <typename T>
-void run_typed(Block& b, int R, int steps, uint64_t seed, int dist, int storage, double* alpha, double* beta,
-               int32_t* nsteps, hipStream_t st) {
+void enqueue_typed(LanczosRun& L, hipStream_t st) {
+  const Block& b = *L.block;
+  const int R = L.R, steps = L.steps;
   const uint64_t D = b.D;
-  const int target = (int)std::min<uint64_t>((uint64_t)steps, D);
-  std::fill(alpha, alpha + (size_t)R * steps, 0.0);
-  std::fill(beta, beta + (size_t)R * steps, 0.0);
-  std::fill(nsteps, nsteps + R, 0);
-  if (D == 0 || target == 0) return;
-  const int TB = R * (256 / R);
-  const int RB = TB / R;
-  const unsigned nb_vec = blocks_for(D, RB);
-  // one lane layout for the whole run (the partial-sum buffer is sized for it)
-  const int gl = hv_layout_lanes(b, R, sizeof(T) == 8 ? FTLM_F64 : FTLM_F32);
-  const int ng_hv = hv_partial_groups(b, R, gl);
-  const int ng_max = std::max<int>((int)nb_vec, ng_hv);
-  DevBuf<T> q0, q1;
-  q0.alloc(D * R);
-  q1.alloc(D * R);
-  DevBuf<uint64_t> keys;
-  std::vector<uint64_t> hkeys(R);
-  for (int v = 0; v < R; ++v) hkeys[v] = chain_key(seed, b.sec->two_M, b.irrep, b.row, v);
-  keys.upload(hkeys, st);
-  DevBuf<double> partials, inv_norm, scal, d_alpha, d_beta;
-  partials.alloc((size_t)ng_max * R);
-  inv_norm.alloc(R);
-  scal.alloc(2 * R);
-  d_alpha.alloc((size_t)R * steps);
-  d_beta.alloc((size_t)R * steps);
-  FTLM_HIP(hipMemsetAsync(d_alpha.p, 0, d_alpha.bytes(), st));
-  FTLM_HIP(hipMemsetAsync(d_beta.p, 0, d_beta.bytes(), st));
-  DevBuf<Chain> ch;
-  ch.alloc(R);
-  DevBuf<int32_t> d_n;
-  d_n.alloc(R);
-  // start vectors: norm of the FP64 draw, then the stored, normalised q_0 and its norm
-  hipLaunchKernelGGL((k_start<T>), dim3(nb_vec), dim3(TB), 0, st, keys.p, dist, D, R, (const double*)nullptr,
-                     q0.p, partials.p);
-  hipLaunchKernelGGL(k_init_chain, dim3(R), dim3(256), 0, st, partials.p, (int)nb_vec, R, inv_norm.p, ch.p, 0);
-  hipLaunchKernelGGL((k_start<T>), dim3(nb_vec), dim3(TB), 0, st, keys.p, dist, D, R, inv_norm.p, q0.p, partials.p);
-  hipLaunchKernelGGL(k_init_chain, dim3(R), dim3(256), 0, st, partials.p, (int)nb_vec, R, inv_norm.p, ch.p, 1);
-  FTLM_HIP(hipMemsetAsync(q1.p, 0, q1.bytes(), st));
-  hipLaunchKernelGGL(k_scal, dim3((R + 63) / 64), dim3(64), 0, st, ch.p, R, scal.p);
-  FTLM_HIP(hipGetLastError());
-  T* qj = q0.p;
-  T* qprev = q1.p;
-  const int dtype = sizeof(T) == 8 ? FTLM_F64 : FTLM_F32;
-  for (int j = 0; j < target; ++j) {
-    LanczosEpilogue lz{scal.p, partials.p, ng_hv};
-    apply_hv_gl(b, qj, qprev, R, R, dtype, st, &lz, gl);  // qprev <- w
-    hipLaunchKernelGGL(k_alpha, dim3(R), dim3(256), 0, st, partials.p, ng_hv, R, ch.p, d_alpha.p, j, steps);
-    hipLaunchKernelGGL((k_update<T>), dim3(nb_vec), dim3(TB), 0, st, ch.p, D, R, qj, qprev, partials.p);
-    hipLaunchKernelGGL(k_beta, dim3(R), dim3(256), 0, st, partials.p, (int)nb_vec, R, ch.p, d_alpha.p, d_beta.p, scal.p, j,
-                       steps, target);
+  T* q0 = (T*)L.q0.p;
+  T* q1 = (T*)L.q1.p;
+  Chain* ch = (Chain*)L.chain.p;
+  FTLM_HIP(hipMemsetAsync(L.d_alpha.p, 0, L.d_alpha.bytes(), st));
+  FTLM_HIP(hipMemsetAsync(L.d_beta.p, 0, L.d_beta.bytes(), st));
+  FTLM_HIP(hipMemsetAsync(L.d_n.p, 0, L.d_n.bytes(), st));
+  if (L.target > 0) {
+    // start vectors: norm of the FP64 draw, then the stored, normalised q_0 and its norm
+    hipLaunchKernelGGL((k_start<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, L.keys.p, L.dist, D, R, (const double*)nullptr,
+                       q0, L.partials.p);
+    hipLaunchKernelGGL(k_init_chain, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, L.inv_norm.p, ch, 0);
+    hipLaunchKernelGGL((k_start<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, L.keys.p, L.dist, D, R, L.inv_norm.p, q0,
+                       L.partials.p);
+    hipLaunchKernelGGL(k_init_chain, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, L.inv_norm.p, ch, 1);
+    FTLM_HIP(hipMemsetAsync(q1, 0, L.q1.bytes(), st));
+    hipLaunchKernelGGL(k_scal, dim3((R + 63) / 64), dim3(64), 0, st, ch, R, L.scal.p);
     FTLM_HIP(hipGetLastError());
-    std::swap(qj, qprev);
+    T* qj = q0;
+    T* qprev = q1;
+    const int dtype = sizeof(T) == 8 ? FTLM_F64 : FTLM_F32;
+    for (int j = 0; j < L.target; ++j) {
+      LanczosEpilogue lz{L.scal.p, L.partials.p, L.ng_hv};
+      apply_hv_gl(b, qj, qprev, R, R, dtype, st, &lz, L.gl);  // qprev <- w
+      hipLaunchKernelGGL(k_alpha, dim3(R), dim3(256), 0, st, L.partials.p, L.ng_hv, R, ch, L.d_alpha.p, j, steps);
+      hipLaunchKernelGGL((k_update<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, ch, D, R, qj, qprev, L.partials.p);
+      hipLaunchKernelGGL(k_beta, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, ch, L.d_alpha.p, L.d_beta.p,
+                         L.scal.p, j, steps, L.target);
+      FTLM_HIP(hipGetLastError());
+      std::swap(qj, qprev);
+    }
+    hipLaunchKernelGGL(k_nsteps, dim3((R + 63) / 64), dim3(64), 0, st, ch, R, L.d_n.p);
+    FTLM_HIP(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_nsteps, dim3((R + 63) / 64), dim3(64), 0, st, ch.p, R, d_n.p);
-  FTLM_HIP(hipMemcpyAsync(alpha, d_alpha.p, d_alpha.bytes(), hipMemcpyDeviceToHost, st));
-  FTLM_HIP(hipMemcpyAsync(beta, d_beta.p, d_beta.bytes(), hipMemcpyDeviceToHost, st));
-  FTLM_HIP(hipMemcpyAsync(nsteps, d_n.p, R * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-  FTLM_HIP(hipStreamSynchronize(st));
-  (void)storage;
 }
 
 }  // namespace
@@ -279,18 +254,65 @@ uint64_t chain_key(uint64_t seed, int two_M, int irrep, int row, int chain) {
   return h;
 }
 
-void run_lanczos(Block& b, int R, int steps, uint64_t seed, int storage, int dist, double* alpha, double* beta,
-                 int32_t* nsteps, hipStream_t st) {
+LanczosRun::LanczosRun(const Block& b, int R_, int steps_, uint64_t seed_, int storage_, int dist_)
+    : block(&b), R(R_), steps(steps_), storage(storage_), dist(dist_), seed(seed_) {
   if (R <= 0 || R > 256) fail(FTLM_ERR_INVALID_ARG, "R must be in 1..256");
   if (steps <= 0) fail(FTLM_ERR_INVALID_ARG, "steps must be positive");
-  if (!alpha || !beta || !nsteps) fail(FTLM_ERR_INVALID_ARG, "null output");
   if (dist != FTLM_RADEMACHER && dist != FTLM_GAUSSIAN) fail(FTLM_ERR_INVALID_ARG, "bad distribution");
+  if (storage != FTLM_F64 && storage != FTLM_F32) fail(FTLM_ERR_INVALID_ARG, "storage must be FTLM_F64 or FTLM_F32");
+  const uint64_t D = b.D;
+  target = (int)std::min<uint64_t>((uint64_t)steps, D);
+  TB = R * (256 / R);
+  nb_vec = (int)blocks_for(std::max<uint64_t>(D, 1), TB / R);
+  // one lane layout for the whole run (the partial-sum buffer is sized for it)
+  gl = hv_layout_lanes(b, R, storage);
+  ng_hv = D ? hv_partial_groups(b, R, gl) : 1;
+}
+
+size_t LanczosRun::estimate_bytes(const Block& b, int R, int steps, int storage) {
+  const size_t elem = storage == FTLM_F64 ? 8 : 4;
+  return 2 * (size_t)b.D * R * elem + (size_t)8192 * R * 8 + (size_t)R * steps * 16 + (size_t)R * 128;
+}
+
+void LanczosRun::allocate() {
+  const size_t elem = storage == FTLM_F64 ? 8 : 4;
+  const uint64_t D = block->D;
+  q0.alloc(std::max<uint64_t>(D, 1) * R * elem);
+  q1.alloc(std::max<uint64_t>(D, 1) * R * elem);
+  std::vector<uint64_t> hkeys(R);
+  for (int v = 0; v < R; ++v) hkeys[v] = chain_key(seed, block->sec->two_M, block->irrep, block->row, v);
+  keys.upload(hkeys);
+  partials.alloc((size_t)std::max(nb_vec, ng_hv) * R);
+  inv_norm.alloc(R);
+  scal.alloc(2 * R);
+  d_alpha.alloc((size_t)R * steps);
+  d_beta.alloc((size_t)R * steps);
+  chain.alloc(sizeof(Chain) * R);
+  d_n.alloc(R);
+}
+
+void LanczosRun::enqueue(hipStream_t st) {
   if (storage == FTLM_F64)
-    run_typed<double>(b, R, steps, seed, dist, storage, alpha, beta, nsteps, st);
-  else if (storage == FTLM_F32)
-    run_typed<float>(b, R, steps, seed, dist, storage, alpha, beta, nsteps, st);
+    enqueue_typed<double>(*this, st);
   else
-    fail(FTLM_ERR_INVALID_ARG, "storage must be FTLM_F64 or FTLM_F32");
+    enqueue_typed<float>(*this, st);
+}
+
+void LanczosRun::download(hipStream_t st, double* alpha, double* beta, int32_t* nsteps) {
+  FTLM_HIP(hipMemcpyAsync(alpha, d_alpha.p, d_alpha.bytes(), hipMemcpyDeviceToHost, st));
+  FTLM_HIP(hipMemcpyAsync(beta, d_beta.p, d_beta.bytes(), hipMemcpyDeviceToHost, st));
+  FTLM_HIP(hipMemcpyAsync(nsteps, d_n.p, (size_t)R * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+}
+
+void run_lanczos(Block& b, int R, int steps, uint64_t seed, int storage, int dist, double* alpha, double* beta,
+                 int32_t* nsteps, hipStream_t st) {
+  if (!alpha || !beta || !nsteps) fail(FTLM_ERR_INVALID_ARG, "null output");
+  LanczosRun L(b, R, steps, seed, storage, dist);
+  AllocStreamScope scope(st ? st : tl_alloc_stream);  // stream-ordered scratch: no device-wide sync on free
+  L.allocate();
+  L.enqueue(st);
+  L.download(st, alpha, beta, nsteps);
+  FTLM_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace ftlm

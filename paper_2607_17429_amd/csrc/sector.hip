@@ -11,6 +11,7 @@
 // index(r) = base[rank(r) >> 6] + popcount of the lower bits of that word.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <unordered_map>
 
@@ -36,10 +37,10 @@ __device__ __forceinline__ const W* stage_table(const W* g_tab, uint32_t n_words
 }
 
 struct SecArgs {
-  const void* tab;
+  const void* tab;   // factored chunk tables (dev::OrbitTabs layout)
   const uint64_t* cnt;
   int cnt_stride;
-  int N, b, d, A, G;
+  int N, b, d, A, G, nH, nT;
   uint64_t D_M, n_words, n_reps;
   uint32_t tab_words;
 };
@@ -50,18 +51,34 @@ __global__ void __launch_bounds__(kThreads) k_enum(SecArgs a, uint64_t* __restri
   extern __shared__ uint64_t smem_raw[];
   const W* tab = stage_table<W, LDS>((const W*)a.tab, a.tab_words, (W*)smem_raw);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const dev::OrbitTabs<W, NCH> o = dev::orbit_tabs<W, NCH>(tab, a.nH, a.nT);
   for (uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; w < a.n_words; w += stride) {
     W x = dev::sector_unrank<W>(w * 64, a.N, a.b, a.d, a.A, a.cnt, a.cnt_stride);
     uint64_t bits = 0;
     for (int k = 0; k < 64; ++k) {
       const bool valid = w * 64 + k < a.D_M;
-      int off[NCH];
-      dev::chunk_offsets<W, NCH>(x, off);
+      int offx[NCH];
+      dev::chunk_offsets<W, NCH>(x, offx);
       bool smaller = false;
-      for (int g = 1; g < a.G; ++g) {
-        W img = dev::permute<W, NCH>(tab, g, off);
-        smaller |= img < x;
-        if ((g & 3) == 3 && __all(smaller || !valid)) break;
+      // walk g = t h; every lane runs the same trip counts, so the vote is uniform
+      int step = 0;
+      for (int hi = 0; hi < o.nH; ++hi) {
+        int off[NCH];
+        if (hi == 0) {
+#pragma unroll
+          for (int c = 0; c < NCH; ++c) off[c] = offx[c];
+        } else {
+          dev::chunk_offsets<W, NCH>(dev::permute<W, NCH>(o.H, hi, offx), off);
+        }
+        bool done = false;
+        for (int ti = hi == 0 ? 1 : 0; ti < o.nT; ++ti) {
+          smaller |= dev::permute<W, NCH>(o.T, ti, off) < x;
+          if ((++step & 3) == 0 && __all(smaller || !valid)) {
+            done = true;
+            break;
+          }
+        }
+        if (done) break;
       }
       if (valid && !smaller) bits |= 1ull << k;
       x = dev::sector_next<W>(x, a.N, a.b, a.d);
@@ -104,15 +121,31 @@ __global__ void __launch_bounds__(kThreads) k_stab_flag(SecArgs a, const uint64_
                                                        uint64_t* __restrict__ flag) {
   extern __shared__ uint64_t smem_raw[];
   const W* tab = stage_table<W, LDS>((const W*)a.tab, a.tab_words, (W*)smem_raw);
+  const dev::OrbitTabs<W, NCH> o = dev::orbit_tabs<W, NCH>(tab, a.nH, a.nT);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n_reps; i += stride) {
     const W r = (W)reps[i];
-    int off[NCH];
-    dev::chunk_offsets<W, NCH>(r, off);
+    int offr[NCH];
+    dev::chunk_offsets<W, NCH>(r, offr);
     bool fixed = false;
-    for (int g = 1; g < a.G; ++g) {
-      fixed |= dev::permute<W, NCH>(tab, g, off) == r;
-      if ((g & 3) == 3 && __all(fixed)) break;
+    int step = 0;
+    for (int hi = 0; hi < o.nH; ++hi) {
+      int off[NCH];
+      if (hi == 0) {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) off[c] = offr[c];
+      } else {
+        dev::chunk_offsets<W, NCH>(dev::permute<W, NCH>(o.H, hi, offr), off);
+      }
+      bool done = false;
+      for (int ti = hi == 0 ? 1 : 0; ti < o.nT; ++ti) {
+        fixed |= dev::permute<W, NCH>(o.T, ti, off) == r;
+        if ((++step & 3) == 0 && __all(fixed)) {
+          done = true;
+          break;
+        }
+      }
+      if (done) break;
     }
     flag[i] = fixed ? 1 : 0;
   }
@@ -126,21 +159,24 @@ __global__ void __launch_bounds__(kThreads) k_stab_mask(SecArgs a, const uint64_
                                                        uint64_t* __restrict__ masks, uint64_t* __restrict__ idx_out) {
   extern __shared__ uint64_t smem_raw[];
   const W* tab = stage_table<W, LDS>((const W*)a.tab, a.tab_words, (W*)smem_raw);
+  const dev::OrbitTabs<W, NCH> o = dev::orbit_tabs<W, NCH>(tab, a.nH, a.nT);
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n_reps; i += stride) {
     const uint64_t p = pos[i];
     if (pos[i + 1] == p) continue;
     const W r = (W)reps[i];
-    int off[NCH];
-    dev::chunk_offsets<W, NCH>(r, off);
-    for (int wq = 0; wq < mw; ++wq) {
-      uint64_t m = 0;
-      for (int t = 0; t < 64; ++t) {
-        int g = wq * 64 + t;
-        if (g >= a.G) break;
-        if (dev::permute<W, NCH>(tab, g, off) == r) m |= 1ull << t;
-      }
-      masks[p * mw + wq] = m;
+    int offr[NCH];
+    dev::chunk_offsets<W, NCH>(r, offr);
+    uint64_t* mk = masks + p * mw;
+    for (int wq = 0; wq < mw; ++wq) mk[wq] = 0;
+    for (int hi = 0; hi < o.nH; ++hi) {
+      int off[NCH];
+      dev::chunk_offsets<W, NCH>(dev::permute<W, NCH>(o.H, hi, offr), off);
+      for (int ti = 0; ti < o.nT; ++ti)
+        if (dev::permute<W, NCH>(o.T, ti, off) == r) {
+          const int g = o.gidx[ti * o.nH + hi];
+          mk[g >> 6] |= 1ull << (g & 63);   // this lane's own mask words
+        }
     }
     idx_out[p] = i;
   }
@@ -233,6 +269,7 @@ __global__ void __launch_bounds__(kThreads) k_entry_fill(SecArgs a, FlipArgs f, 
                                                         uint64_t* __restrict__ entries) {
   extern __shared__ uint64_t smem_raw[];
   const W* tab = stage_table<W, LDS>((const W*)a.tab, a.tab_words, (W*)smem_raw);
+  const dev::OrbitTabs<W, NCH> o = dev::orbit_tabs<W, NCH>(tab, a.nH, a.nT);
   const W mask = (W(1) << a.b) - 1;
   const int ncand = 2 * f.nbonds;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -247,7 +284,7 @@ __global__ void __launch_bounds__(kThreads) k_entry_fill(SecArgs a, FlipArgs f, 
       const W x = cur >= 0 ? apply_flip<W>(p, cur, f, a.b) : p;
       W r;
       int h;
-      dev::canon_min<W, NCH>(x, tab, a.G, r, h);
+      dev::canon_min<W, NCH>(x, o, r, h);
       if (cur >= 0) {
         uint64_t idx = 0;
         bool ok = lookup<W>(r, a, bits, base, idx);
@@ -268,6 +305,7 @@ __global__ void __launch_bounds__(kThreads) k_canon_labels(SecArgs a, const uint
                                                           int64_t* __restrict__ idx_out) {
   extern __shared__ uint64_t smem_raw[];
   const W* tab = stage_table<W, LDS>((const W*)a.tab, a.tab_words, (W*)smem_raw);
+  const dev::OrbitTabs<W, NCH> o = dev::orbit_tabs<W, NCH>(tab, a.nH, a.nT);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t n_iter = (n + stride - 1) / stride;
   for (int64_t it = 0; it < n_iter; ++it) {
@@ -290,7 +328,7 @@ __global__ void __launch_bounds__(kThreads) k_canon_labels(SecArgs a, const uint
     }
     W r;
     int h;
-    dev::canon_min<W, NCH>(x, tab, a.G, r, h);
+    dev::canon_min<W, NCH>(x, o, r, h);
     if (live) {
       uint64_t idx = 0;
       bool ok = in_range && lookup<W>(r, a, bits, base, idx);
@@ -378,7 +416,7 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
       s.cnt[(size_t)k * s.cnt_stride + v] = (uint64_t)c;
     }
   const int A2 = s.N * s.two_s + two_M;
-  hipStream_t st = nullptr;
+  hipStream_t st = tl_alloc_stream;  // the caller's build stream, or the null stream
   if (A2 % 2 != 0 || A2 < 0 || A2 / 2 > Amax) {
     s.A = 0;
     s.D_M = 0;
@@ -387,12 +425,22 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
     s.D_M = s.cnt[(size_t)s.N * s.cnt_stride + s.A];
   }
   s.n_words = (s.D_M + 63) / 64;
-  // permutation chunk tables
+  // permutation chunk tables of the factored group (dev::OrbitTabs layout):
+  // all |G| elements when their tables take at most 16 KiB, otherwise
+  // G = T H with |H| + |T| tables
   const int G_ = G->order;
-  const size_t tab_words = (size_t)G_ * s.nch * 16;
+  const size_t wbytes = s.wide ? 8 : 4;
   {
-    std::vector<uint64_t> tab(tab_words, 0);
-    for (int g = 0; g < G_; ++g) {
+    const int max_plain = (int)std::max<size_t>(1, 16384 / ((size_t)s.nch * 16 * wbytes));
+    const Factorization fz = factor_group(*G, max_plain);
+    s.fac_nH = (int)fz.H.size();
+    s.fac_nT = (int)fz.T.size();
+    const size_t rows = (size_t)s.fac_nH + s.fac_nT;
+    const size_t tab_bytes = rows * s.nch * 16 * wbytes + fz.gidx.size() * 2;
+    s.tab_words = (uint32_t)((tab_bytes + wbytes - 1) / wbytes);
+    std::vector<uint8_t> bytes(s.tab_words * wbytes, 0);
+    for (size_t row = 0; row < rows; ++row) {
+      const int g = row < (size_t)s.fac_nH ? fz.H[row] : fz.T[row - s.fac_nH];
       const int32_t* p = &G->perms[(size_t)g * s.N];
       for (int c = 0; c < s.nch; ++c)
         for (int v = 0; v < 16; ++v) {
@@ -404,17 +452,19 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
             int site = bit / s.bits, sub = bit % s.bits;
             img |= 1ull << (p[site] * s.bits + sub);
           }
-          tab[((size_t)g * s.nch + c) * 16 + v] = img;
+          const size_t at = ((row * s.nch + c) * 16 + v) * wbytes;
+          if (s.wide) {
+            std::memcpy(&bytes[at], &img, 8);
+          } else {
+            const uint32_t i32 = (uint32_t)img;
+            std::memcpy(&bytes[at], &i32, 4);
+          }
         }
     }
-    if (!s.wide) {
-      std::vector<uint32_t> t32(tab_words);
-      for (size_t i = 0; i < tab_words; ++i) t32[i] = (uint32_t)tab[i];
-      s.d_tab.alloc((tab_words + 1) / 2);
-      FTLM_HIP(hipMemcpy(s.d_tab.p, t32.data(), tab_words * 4, hipMemcpyHostToDevice));
-    } else {
-      s.d_tab.upload(tab);
-    }
+    std::memcpy(&bytes[rows * s.nch * 16 * wbytes], fz.gidx.data(), fz.gidx.size() * 2);
+    s.d_tab.alloc((bytes.size() + 7) / 8);
+    FTLM_HIP(hipMemcpyAsync(s.d_tab.p, bytes.data(), bytes.size(), hipMemcpyHostToDevice, st));
+    FTLM_HIP(hipStreamSynchronize(st));
   }
   s.d_cnt.upload(s.cnt);
   s.d_bonds.upload(s.bonds);
@@ -433,8 +483,7 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
       }
     s.d_fac.upload(fac);
   }
-  const size_t wbytes = s.wide ? 8 : 4;
-  const size_t tab_bytes = tab_words * wbytes;
+  const size_t tab_bytes = (size_t)s.tab_words * wbytes;
   const bool lds = tab_bytes <= (size_t)max_lds_bytes();
   SecArgs a{};
   a.tab = s.d_tab.p;
@@ -445,16 +494,19 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
   a.d = s.d;
   a.A = s.A;
   a.G = G_;
+  a.nH = s.fac_nH;
+  a.nT = s.fac_nT;
   a.D_M = s.D_M;
   a.n_words = s.n_words;
-  a.tab_words = (uint32_t)tab_words;
+  a.tab_words = s.tab_words;
   const size_t shm = lds ? tab_bytes : 0;
   FlipArgs f{s.d_bonds.p, s.d_J.p, s.nbonds};
 
   if (s.D_M == 0) {
     s.n_reps = 0;
     s.d_row_ptr.alloc(1);
-    FTLM_HIP(hipMemset(s.d_row_ptr.p, 0, sizeof(uint64_t)));
+    FTLM_HIP(hipMemsetAsync(s.d_row_ptr.p, 0, sizeof(uint64_t), st));
+    FTLM_HIP(hipStreamSynchronize(st));
     return S;
   }
   const int64_t limit = opts ? opts->hbm_limit_bytes : 0;
@@ -620,12 +672,13 @@ void sector_canonicalize(const Sector& s, const uint64_t* labels, int64_t n, uin
   a.d = s.d;
   a.A = s.A;
   a.G = s.G->order;
+  a.nH = s.fac_nH;
+  a.nT = s.fac_nT;
   a.D_M = s.D_M;
   a.n_words = s.n_words;
   a.n_reps = s.n_reps;
-  const size_t tab_words = (size_t)a.G * s.nch * 16;
-  a.tab_words = (uint32_t)tab_words;
-  const size_t tab_bytes = tab_words * (s.wide ? 8 : 4);
+  a.tab_words = s.tab_words;
+  const size_t tab_bytes = (size_t)s.tab_words * (s.wide ? 8 : 4);
   const bool lds = tab_bytes <= (size_t)max_lds_bytes();
   const uint64_t* bits = s.d_rank_bits.p;
   const uint32_t* base = s.d_rank_base.p;

@@ -25,6 +25,9 @@ CASES = [  # (cluster, 2s, 2M)
     ("ring6", 1, 0), ("ring6", 2, 0), ("ring6", 2, 2),
     ("K4", 3, 0), ("dimer", 1, 0), ("square4", 1, 4), ("icosahedron", 3, 6),
 ]
+# labels wider than 32 bits (64-bit words, 10, 12 and 16 four-bit chunks)
+WIDE = [("square6x6", 1, 30), ("square6x6", 1, 28), ("dodecahedron", 3, 54), ("ring44", 1, 40), ("ring60", 1, 56)]
+CASES += WIDE
 
 
 @pytest.mark.parametrize("name,two_s,two_M", CASES)
@@ -40,7 +43,7 @@ def test_sector_tables_bit_exact(name, two_s, two_M):
     assert [len(s) for s in sec.stab_sets] == list(ssz)
 
 
-@pytest.mark.parametrize("name,two_s,two_M", CASES[:10])
+@pytest.mark.parametrize("name,two_s,two_M", CASES[:10] + WIDE)
 def test_orbit_search_and_lookup_bit_exact(name, two_s, two_M):
     log(f"[canon] {name} 2s={two_s} 2M={two_M}")
     cl, G, _ = oracle_group(name)
@@ -90,7 +93,8 @@ def test_block_data_and_hv_fp64(name, two_s, two_M):
 
 
 @pytest.mark.parametrize("name,two_s,two_M,gi", [("dodecahedron", 1, 0, 8), ("icosahedron", 1, 0, 9),
-                                                 ("cuboctahedron", 3, 2, 7)])
+                                                 ("cuboctahedron", 3, 2, 7), ("square6x6", 1, 28, 26),
+                                                 ("ring60", 1, 56, 10)])
 def test_hv_batched_fp32_and_modes(name, two_s, two_M, gi):
     """nvec up to 70 (two vector tiles), FP32 storage, on-the-fly mode; batched == single bitwise."""
     log(f"[hv-batch] {name} 2s={two_s} 2M={two_M} irrep={gi}")
@@ -100,12 +104,20 @@ def test_hv_batched_fp32_and_modes(name, two_s, two_M, gi):
     LO = lib_block(name, two_s, two_M, gi, hv_mode=P.HV_ONTHEFLY)
     assert LO.hv_mode == P.HV_ONTHEFLY and LB.hv_mode == P.HV_ENTRIES
     rng = np.random.default_rng(5)
+    # the on-the-fly kernel keeps the irrep matrices in LDS (48 KiB for the
+    # small tables); larger ones (8x8 matrices of a group of order 288) are
+    # refused with UNSUPPORTED instead of running from global memory
+    otf_fits = LB.group_order * LB.d_gamma ** 2 * 8 <= 40 * 1024
     for nvec in (2, 24, 70):
         X = rng.standard_normal((B.D, nvec))
         Xt = torch.from_numpy(X).cuda()
         Y = LB.apply_H(Xt)
-        Yo = LO.apply_H(Xt)
-        assert torch.equal(Y, Yo)                        # same flips, same order
+        if otf_fits:
+            Yo = LO.apply_H(Xt)
+            assert torch.equal(Y, Yo)                    # same flips, same order
+        else:
+            with pytest.raises(P.FtlmError, match="UNSUPPORTED"):
+                LO.apply_H(Xt)
         assert rel_err_cols(Y.cpu().numpy(), hv.apply(B, H, X)) <= 1e-12
         # batched equals one column at a time, bitwise
         for v in (0, nvec - 1):

@@ -1,0 +1,150 @@
+"""GPU tests of the continuous-batching job server (include/ftlm_server.h).
+
+A job's Lanczos coefficients must not depend on what else runs: every job of a
+mixed batch (several clusters, M sectors, irreps, rows, R, storage types and
+start-vector distributions, admitted up to four at a time and overlapping on
+the device) is compared bit for bit with the same block run alone through
+ftlm_run.  The standalone path is itself compared with the oracle in
+test_gpu_ftlm.py; one server job is also checked against the oracle here.
+Admission by memory budget, cancellation and failing jobs are covered too.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import lib_group, lib_sector, log, oracle_block, oracle_sector
+from oracle import ftlm as oftlm
+from synth import clusters
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2607_17429_amd")
+
+# (cluster, 2M, irrep, row, R, steps, seed, storage, dist)
+MIX = [
+    ("icosahedron", 0, 0, 0, 4, 40, 11, "f64", "rad"),
+    ("icosahedron", 2, 8, 2, 6, 30, 12, "f32", "gau"),
+    ("dodecahedron", 0, 8, 1, 8, 50, 13, "f32", "rad"),
+    ("dodecahedron", 2, 3, 0, 5, 60, 14, "f64", "gau"),
+    ("cuboctahedron", 0, 9, 2, 3, 40, 15, "f64", "rad"),
+    ("cuboctahedron", 4, 4, 1, 7, 25, 16, "f32", "rad"),
+    ("square4x4", 0, 0, 0, 4, 40, 17, "f64", "rad"),
+    ("square4x4", 2, 10, 1, 9, 35, 18, "f32", "gau"),
+    ("ring12", 0, 2, 0, 2, 30, 19, "f64", "rad"),
+    ("dodecahedron", 0, 8, 4, 24, 60, 20, "f32", "gau"),
+    ("icosahedron", 0, 0, 0, 4, 40, 11, "f64", "rad"),   # repeat of the first job
+    ("dodecahedron", 4, 9, 0, 3, 45, 21, "f64", "rad"),
+]
+
+ST = {"f64": None, "f32": None}
+DI = {"rad": None, "gau": None}
+
+
+def _enums():
+    ST.update(f64=P.F64, f32=P.F32)
+    DI.update(rad=P.RADEMACHER, gau=P.GAUSSIAN)
+
+
+def _valid(job):
+    name, two_M, gi, row = job[:4]
+    dims = lib_group(name).irreps()["dims"]
+    return gi < len(dims) and row < dims[gi]
+
+
+def _standalone(job):
+    name, two_M, gi, row, R, steps, seed, st, di = job
+    B = P.Block(lib_sector(name, 1, two_M), gi, row)
+    return B.ftlm(R, steps, seed, storage=ST[st], dist=DI[di])
+
+
+def _submit(srv, job):
+    name, two_M, gi, row, R, steps, seed, st, di = job
+    cl = clusters.get(name)
+    return srv.submit(cl, cl.gens, two_M, gi, row, R, steps, seed, storage=ST[st], dist=DI[di], two_s=1)
+
+
+def test_mixed_jobs_match_standalone_bitwise():
+    _enums()
+    for job in MIX:
+        assert _valid(job), job
+    log("[server] mixed batch of %d jobs, max_active=4" % len(MIX))
+    srv = P.Server(8 << 30, max_active=4)
+    ids = [_submit(srv, job) for job in MIX]
+    results = [srv.wait(i) for i in ids]
+    srv.close()
+    for job, (res, a, b, n) in zip(MIX, results):
+        assert res["status"] == 0, (job, res)
+        assert res["submit_s"] <= res["start_s"] <= res["end_s"]
+        a0, b0, n0 = _standalone(job)
+        assert np.array_equal(n, n0), job
+        assert np.array_equal(a, a0), job
+        assert np.array_equal(b, b0), job
+    # the repeated job gives the same numbers
+    assert np.array_equal(results[0][1], results[10][1])
+
+
+def test_server_job_against_oracle():
+    _enums()
+    # a one-dimensional irrep (A_g): its matrices are its characters, so the
+    # library's block basis is the oracle's and the runs agree up to rounding
+    name, two_M, gi = "dodecahedron", 0, 0
+    assert lib_group(name).irreps()["dims"][gi] == 1
+    srv = P.Server(1 << 30, max_active=2)
+    cl = clusters.get(name)
+    jid = srv.submit(cl, cl.gens, two_M, gi, 0, 3, 40, 99, storage=P.F64, dist=P.RADEMACHER, two_s=1)
+    res, a, b, n = srv.wait(jid)
+    srv.close()
+    assert res["status"] == 0 and res["d_gamma"] == 1
+    sec, H = oracle_sector(name, 1, two_M)
+    B = oracle_block(name, 1, two_M, gi)
+    assert res["D"] == B.D
+    Hb = (B.Psi.T @ H @ B.Psi).tocsr()
+    for r in range(3):
+        v0 = oftlm.start_vector(B.D, 99, two_M, gi, 0, r, "rademacher")
+        oa, ob = oftlm.lanczos(lambda x: Hb @ x, v0, 40)
+        assert np.max(np.abs(a[r, :15] - oa[:15])) < 1e-10 * np.max(np.abs(oa))
+        assert np.max(np.abs(b[r, :15] - ob[:15])) < 1e-10 * np.max(np.abs(ob))
+
+
+def test_budget_cancel_and_failures():
+    _enums()
+    log("[server] budget / cancel / failing jobs")
+    cl = clusters.get("dodecahedron")
+    # a budget below any footprint: the job fails with OUT_OF_MEMORY, the server keeps going
+    srv = P.Server(1 << 16, max_active=2)
+    jid = srv.submit(cl, cl.gens, 0, 8, 0, 4, 20, 1, storage=P.F64, two_s=1)
+    res, a, *_ = srv.wait(jid)
+    assert res["error"] == "OUT_OF_MEMORY" and a is None
+    srv.close()
+
+    srv = P.Server(2 << 30, max_active=1)
+    bad_irrep = srv.submit(cl, cl.gens, 0, 99, 0, 4, 20, 1, two_s=1)
+    bad_row = srv.submit(cl, cl.gens, 0, 8, 7, 4, 20, 1, two_s=1)
+    big = srv.submit(cl, cl.gens, 0, 8, 0, 32, 200, 2, storage=P.F64, two_s=1)
+    queued = [srv.submit(cl, cl.gens, 2, 3, 0, 4, 30, 3 + k, two_s=1) for k in range(4)]
+    srv.cancel(queued[1])
+    out = {k: srv.wait(j) for k, j in [("bad_irrep", bad_irrep), ("bad_row", bad_row), ("big", big)]}
+    assert out["bad_irrep"][0]["error"] == "IRREP_OUT_OF_RANGE"
+    assert out["bad_row"][0]["error"] == "ROW_OUT_OF_RANGE"
+    assert out["big"][0]["status"] == 0
+    rq = [srv.wait(j) for j in queued]
+    assert rq[1][0]["error"] == "CANCELLED"
+    for k in (0, 2, 3):
+        assert rq[k][0]["status"] == 0
+        a0, b0, n0 = P.Block(lib_sector("dodecahedron", 1, 2), 3, 0).ftlm(4, 30, 3 + k, storage=P.F64)
+        assert np.array_equal(rq[k][1], a0) and np.array_equal(rq[k][2], b0)
+    st = srv.stats()
+    assert st["running"] == 0 and st["queued"] == 0
+    assert st["used_bytes"] > 0          # the cached sectors stay resident
+    with pytest.raises(P.FtlmError):
+        srv.wait(big)                    # already released
+    srv.close()
+
+
+def test_free_with_jobs_in_flight():
+    _enums()
+    cl = clusters.get("icosahedron")
+    srv = P.Server(1 << 30, max_active=2)
+    for k in range(6):
+        srv.submit(cl, cl.gens, 0, 0, 0, 4, 30, k, two_s=1)
+    srv.close()                          # cancels queued jobs, drains running ones
