@@ -115,10 +115,12 @@ def draw_jobs(rng, n, groups, clusters):
     return jobs
 
 
-def serve(P, np, n_warm, n_jobs, rate, budget_gb, max_active, seed=0x5E4E):
+def serve(P, np, n_warm, n_jobs, rate, budget_gb, max_active, seed=0x5EED0100, log_path=None, load=0.8):
     """Warm-up burst, a closed burst (capacity), then an open Poisson stream (latency).
 
-    A job's latency runs from its submission to its coefficients on the host;
+    The closed burst submits n_jobs at once; its throughput is the capacity
+    estimate, and the Poisson stream offers load x capacity (or the given rate).
+    A job's latency runs from its submission to its coefficients on the host:
     queueing, table builds on a cold cache and the Lanczos run are all inside.
     """
     from synth import clusters
@@ -126,13 +128,14 @@ def serve(P, np, n_warm, n_jobs, rate, budget_gb, max_active, seed=0x5E4E):
     rng = np.random.default_rng(seed)
     srv = P.Server(int(budget_gb * (1 << 30)), max_active=max_active)
     F = {"f64": P.F64, "f32": P.F32}
+    records = []
 
     def submit(j):
         cl = clusters.get(j["cluster"])
         return srv.submit(cl, cl.gens, j["two_M"], j["irrep"], j["row"], j["R"], j["steps"], j["seed"],
                           storage=F[j["storage"]], dist=P.RADEMACHER, two_s=1)
 
-    def run(jobs, arrivals):
+    def run(phase, jobs, arrivals):
         t0 = time.perf_counter()
         ids = []
         for j, ta in zip(jobs, arrivals):
@@ -144,25 +147,32 @@ def serve(P, np, n_warm, n_jobs, rate, budget_gb, max_active, seed=0x5E4E):
         for r, j in zip(res, jobs):
             if r[0]["status"] != 0:
                 raise RuntimeError(f"serving job failed: {j} -> {r[0]}")
+            records.append(dict(phase=phase, **j, D=int(r[0]["D"]), d_gamma=int(r[0]["d_gamma"]),
+                                submit=r[0]["submit_s"], start=r[0]["start_s"], end=r[0]["end_s"]))
         span = max(r[0]["end_s"] for r in res) - min(r[0]["submit_s"] for r in res)
         lat = np.array([r[0]["end_s"] - r[0]["submit_s"] for r in res]) * 1e3
         wait = np.array([r[0]["start_s"] - r[0]["submit_s"] for r in res]) * 1e3
         work = sum(int(r[0]["D"]) * int(r[3].sum()) for r in res)
+        print(f"[serve] {phase}: {len(jobs)} jobs in {span:.2f} s, p50 {np.percentile(lat, 50):.1f} ms, "
+              f"p99 {np.percentile(lat, 99):.1f} ms", file=sys.stderr, flush=True)
         return dict(jobs=len(jobs), span_s=span, jobs_per_s=len(jobs) / span, elem_vec_per_s=work / span,
                     p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                     max_ms=float(lat.max()), queue_p50_ms=float(np.percentile(wait, 50)),
                     queue_p99_ms=float(np.percentile(wait, 99)))
 
     t = time.perf_counter()
-    warm = draw_jobs(rng, n_warm, groups, clusters)
-    run(warm, [0.0] * n_warm)
+    run("warm", draw_jobs(rng, n_warm, groups, clusters), [0.0] * n_warm)
     warm_s = time.perf_counter() - t
-    burst = run(draw_jobs(rng, n_jobs, groups, clusters), [0.0] * n_jobs)
-    lam = rate if rate else 0.7 * burst["jobs_per_s"]
+    burst = run("burst", draw_jobs(rng, n_jobs, groups, clusters), [0.0] * n_jobs)
+    lam = rate if rate else load * burst["jobs_per_s"]
     arrivals = np.cumsum(rng.exponential(1.0 / lam, n_jobs))
-    stream = run(draw_jobs(rng, n_jobs, groups, clusters), arrivals)
+    stream = run("poisson", draw_jobs(rng, n_jobs, groups, clusters), arrivals)
     stats = srv.stats()
     srv.close()
+    if log_path:
+        with open(log_path, "w") as f:
+            for r in records:
+                f.write(json.dumps(r) + "\n")
     return dict(workload=SERVE_DESC, warmup_jobs=n_warm, warmup_s=warm_s, max_active=max_active,
                 budget_gb=budget_gb, closed_burst=burst, poisson=dict(rate_jobs_per_s=lam, **stream),
                 resident_bytes_after=stats["used_bytes"])
@@ -182,10 +192,15 @@ def main():
     ap.add_argument("--serve", action="store_true", help="run the job-server benchmark (serving mix) instead")
     ap.add_argument("--serve-jobs", type=int, default=200)
     ap.add_argument("--serve-warm", type=int, default=100)
-    ap.add_argument("--serve-rate", type=float, default=0.0, help="Poisson rate in jobs/s (0: 0.7 x burst rate)")
+    ap.add_argument("--serve-rate", type=float, default=0.0, help="Poisson rate in jobs/s (0: 0.8 x burst rate)")
     ap.add_argument("--serve-active", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-log", default=None, help="write one JSON record per job to this file")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="hardware queues per process (GPU_MAX_HW_QUEUES, read when HIP starts); 0 keeps the default")
     args = ap.parse_args()
+    if args.hw_queues:
+        os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 32))
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only "
                                    "(see DESIGN.md), so --gpus must be 1"}))
@@ -200,7 +215,7 @@ def main():
     if args.serve:
         torch.cuda.set_device(0)
         res = serve(P, np, args.serve_warm, args.serve_jobs, args.serve_rate, args.serve_budget_gb,
-                    args.serve_active)
+                    args.serve_active, log_path=args.serve_log)
         p = res["poisson"]
         print(json.dumps({"metric": "FTLM job latency under a Poisson stream (serving mix)", "value": p["p50_ms"],
                           "unit": "ms (p50)", "n_gpus": 1, "higher_is_better": False, "dtype": "f64/f32",

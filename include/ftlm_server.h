@@ -11,11 +11,16 @@
  * then holds back the queue behind it.  A job whose estimate alone exceeds
  * hbm_budget_bytes ends with FTLM_ERR_OUT_OF_MEMORY.  Sector tables are cached and shared by all
  * jobs with the same (cluster, generators, 2M); unused ones are evicted when
- * memory is needed.  Every admitted job runs on its own non-blocking HIP
- * stream with all of its Lanczos steps enqueued at admission, so work of
- * different jobs overlaps on the device; a job's result does not depend on
- * the other jobs (no shared reductions, deterministic kernels).  One worker
- * thread owns every HIP call of the server; the calls below are thread-safe.
+ * memory is needed.  Groups and sector tables are built by a builder thread
+ * of the server, one at a time, while the worker thread keeps admitting and
+ * retiring jobs whose tables are resident; a job waiting for a build holds
+ * nobody up.  Every admitted job runs on its own non-blocking HIP stream, so
+ * work of different jobs overlaps on the device; its Lanczos steps are
+ * enqueued in chunks of about 10 ms of estimated device time, so a long job
+ * holds a hardware queue shared with other streams for at most one chunk
+ * ahead of their work.  A job's result does not depend on the other jobs
+ * (no shared reductions, deterministic kernels).  The two server threads own
+ * every HIP call of the server; the calls below are thread-safe.
  */
 #ifndef FTLM_SERVER_H
 #define FTLM_SERVER_H

@@ -126,7 +126,10 @@ struct LanczosRun {
   LanczosRun(const Block& b, int R, int steps, uint64_t seed, int storage, int dist);
   static size_t estimate_bytes(const Block& b, int R, int steps, int storage);
   void allocate();                 // device buffers (stream-ordered if an allocation stream is set)
-  void enqueue(hipStream_t st);    // start vectors + all steps
+  void enqueue(hipStream_t st);    // begin + all steps + end
+  void enqueue_begin(hipStream_t st);                  // clear outputs, start vectors
+  void enqueue_steps(hipStream_t st, int j0, int j1);  // Lanczos steps j0 <= j < min(j1, target)
+  void enqueue_end(hipStream_t st);                    // per-chain step counts
   void download(hipStream_t st, double* alpha, double* beta, int32_t* nsteps);
 };
 

@@ -201,41 +201,45 @@ unsigned blocks_for(uint64_t rows, int RB) {
 }
 
 template <typename T>
-void enqueue_typed(LanczosRun& L, hipStream_t st) {
-  const Block& b = *L.block;
-  const int R = L.R, steps = L.steps;
-  const uint64_t D = b.D;
+void enqueue_begin_typed(LanczosRun& L, hipStream_t st) {
+  const int R = L.R;
+  const uint64_t D = L.block->D;
   T* q0 = (T*)L.q0.p;
-  T* q1 = (T*)L.q1.p;
   Chain* ch = (Chain*)L.chain.p;
   FTLM_HIP(hipMemsetAsync(L.d_alpha.p, 0, L.d_alpha.bytes(), st));
   FTLM_HIP(hipMemsetAsync(L.d_beta.p, 0, L.d_beta.bytes(), st));
   FTLM_HIP(hipMemsetAsync(L.d_n.p, 0, L.d_n.bytes(), st));
-  if (L.target > 0) {
-    // start vectors: norm of the FP64 draw, then the stored, normalised q_0 and its norm
-    hipLaunchKernelGGL((k_start<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, L.keys.p, L.dist, D, R, (const double*)nullptr,
-                       q0, L.partials.p);
-    hipLaunchKernelGGL(k_init_chain, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, L.inv_norm.p, ch, 0);
-    hipLaunchKernelGGL((k_start<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, L.keys.p, L.dist, D, R, L.inv_norm.p, q0,
-                       L.partials.p);
-    hipLaunchKernelGGL(k_init_chain, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, L.inv_norm.p, ch, 1);
-    FTLM_HIP(hipMemsetAsync(q1, 0, L.q1.bytes(), st));
-    hipLaunchKernelGGL(k_scal, dim3((R + 63) / 64), dim3(64), 0, st, ch, R, L.scal.p);
-    FTLM_HIP(hipGetLastError());
-    T* qj = q0;
-    T* qprev = q1;
-    const int dtype = sizeof(T) == 8 ? FTLM_F64 : FTLM_F32;
-    for (int j = 0; j < L.target; ++j) {
-      LanczosEpilogue lz{L.scal.p, L.partials.p, L.ng_hv};
-      apply_hv_gl(b, qj, qprev, R, R, dtype, st, &lz, L.gl);  // qprev <- w
-      hipLaunchKernelGGL(k_alpha, dim3(R), dim3(256), 0, st, L.partials.p, L.ng_hv, R, ch, L.d_alpha.p, j, steps);
-      hipLaunchKernelGGL((k_update<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, ch, D, R, qj, qprev, L.partials.p);
-      hipLaunchKernelGGL(k_beta, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, ch, L.d_alpha.p, L.d_beta.p,
-                         L.scal.p, j, steps, L.target);
-      FTLM_HIP(hipGetLastError());
-      std::swap(qj, qprev);
-    }
-    hipLaunchKernelGGL(k_nsteps, dim3((R + 63) / 64), dim3(64), 0, st, ch, R, L.d_n.p);
+  if (L.target == 0) return;
+  // start vectors: norm of the FP64 draw, then the stored, normalised q_0 and its norm
+  hipLaunchKernelGGL((k_start<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, L.keys.p, L.dist, D, R, (const double*)nullptr,
+                     q0, L.partials.p);
+  hipLaunchKernelGGL(k_init_chain, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, L.inv_norm.p, ch, 0);
+  hipLaunchKernelGGL((k_start<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, L.keys.p, L.dist, D, R, L.inv_norm.p, q0,
+                     L.partials.p);
+  hipLaunchKernelGGL(k_init_chain, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, L.inv_norm.p, ch, 1);
+  FTLM_HIP(hipMemsetAsync(L.q1.p, 0, L.q1.bytes(), st));
+  hipLaunchKernelGGL(k_scal, dim3((R + 63) / 64), dim3(64), 0, st, ch, R, L.scal.p);
+  FTLM_HIP(hipGetLastError());
+}
+
+// Steps j0 <= j < j1: q_j lives in q0 for even j and in q1 for odd j; the
+// other buffer holds q_{j-1} and receives w.
+template <typename T>
+void enqueue_steps_typed(LanczosRun& L, hipStream_t st, int j0, int j1) {
+  const Block& b = *L.block;
+  const int R = L.R, steps = L.steps;
+  const uint64_t D = b.D;
+  Chain* ch = (Chain*)L.chain.p;
+  const int dtype = sizeof(T) == 8 ? FTLM_F64 : FTLM_F32;
+  for (int j = j0; j < j1; ++j) {
+    T* qj = (T*)((j & 1) ? L.q1.p : L.q0.p);
+    T* qprev = (T*)((j & 1) ? L.q0.p : L.q1.p);
+    LanczosEpilogue lz{L.scal.p, L.partials.p, L.ng_hv};
+    apply_hv_gl(b, qj, qprev, R, R, dtype, st, &lz, L.gl);  // qprev <- w
+    hipLaunchKernelGGL(k_alpha, dim3(R), dim3(256), 0, st, L.partials.p, L.ng_hv, R, ch, L.d_alpha.p, j, steps);
+    hipLaunchKernelGGL((k_update<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, ch, D, R, qj, qprev, L.partials.p);
+    hipLaunchKernelGGL(k_beta, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, ch, L.d_alpha.p, L.d_beta.p,
+                       L.scal.p, j, steps, L.target);
     FTLM_HIP(hipGetLastError());
   }
 }
@@ -291,11 +295,33 @@ void LanczosRun::allocate() {
   d_n.alloc(R);
 }
 
-void LanczosRun::enqueue(hipStream_t st) {
+void LanczosRun::enqueue_begin(hipStream_t st) {
   if (storage == FTLM_F64)
-    enqueue_typed<double>(*this, st);
+    enqueue_begin_typed<double>(*this, st);
   else
-    enqueue_typed<float>(*this, st);
+    enqueue_begin_typed<float>(*this, st);
+}
+
+void LanczosRun::enqueue_steps(hipStream_t st, int j0, int j1) {
+  j0 = std::max(j0, 0);
+  j1 = std::min(j1, target);
+  if (j0 >= j1) return;
+  if (storage == FTLM_F64)
+    enqueue_steps_typed<double>(*this, st, j0, j1);
+  else
+    enqueue_steps_typed<float>(*this, st, j0, j1);
+}
+
+void LanczosRun::enqueue_end(hipStream_t st) {
+  if (target == 0) return;
+  hipLaunchKernelGGL(k_nsteps, dim3((R + 63) / 64), dim3(64), 0, st, (Chain*)chain.p, R, d_n.p);
+  FTLM_HIP(hipGetLastError());
+}
+
+void LanczosRun::enqueue(hipStream_t st) {
+  enqueue_begin(st);
+  enqueue_steps(st, 0, target);
+  enqueue_end(st);
 }
 
 void LanczosRun::download(hipStream_t st, double* alpha, double* beta, int32_t* nsteps) {

@@ -1,13 +1,18 @@
 // Continuous-batching FTLM job server (see ftlm_server.h).
 //
-// One worker thread owns all HIP work.  Each loop it (1) retires running jobs
-// whose completion event has fired, (2) admits queued jobs in FIFO order,
-// letting a later job overtake one that does not fit, while fewer than
-// max_active run and the footprint fits the budget, and (3) sleeps briefly
-// or until a submit.  Admission builds (or reuses) the group and the sector
-// tables on the server's build stream with stream-ordered allocations, builds
-// the block, then enqueues the job's whole Lanczos run and the copy of its
-// coefficients on a fresh non-blocking stream, followed by an event.
+// Two threads own all HIP work of a server.  The builder thread builds groups
+// (closure and irreps, host) and sector tables (GPU, on its own stream) one at
+// a time.  The worker thread loops: (1) take finished builds into the caches,
+// (2) retire running jobs whose completion event has fired, (3) walk the queue
+// in FIFO order: a job whose group or sector is missing asks the builder for
+// it (sector memory is reserved against the budget first) and waits without
+// holding anyone up; a job whose tables are resident is admitted when fewer
+// than max_active run and its block and Lanczos footprint fits, a later job
+// may overtake one that does not fit; (4) sleep briefly or until woken.
+// Admission builds the block on the worker's stream and enqueues the start
+// vectors on a pooled non-blocking stream; the worker then feeds the job's
+// Lanczos steps in chunks (two in flight, each followed by an event) and
+// finally the copy of its coefficients and a completion event.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -17,6 +22,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
 #include <thread>
 #include <tuple>
@@ -40,6 +46,7 @@ struct Job {
   uint64_t seed = 0;
   std::vector<int32_t> bonds, gens;
   std::vector<double> J;
+  std::string group_key, sector_key;
   // state
   bool done = false, running = false, cancel = false, holds_sector = false;
   int status = FTLM_OK;
@@ -47,7 +54,6 @@ struct Job {
   double t_submit = 0, t_start = 0, t_end = 0;
   uint64_t D = 0;
   int dg = 0;
-  std::string sector_key;
   std::unique_ptr<Block> block;
   std::unique_ptr<LanczosRun> run;
   hipStream_t stream = nullptr;
@@ -58,14 +64,52 @@ struct Job {
   double* h_beta = nullptr;
   int32_t* h_n = nullptr;
   int overtaken = 0;
+  // incremental enqueue: steps [0, next_step) are on the stream, at most two
+  // chunks of `chunk` steps are in flight, each followed by an event
+  int next_step = 0, chunk = 1;
+  bool enqueued_all = false;
+  std::deque<hipEvent_t> inflight;
   std::vector<double> alpha, beta;
   std::vector<int32_t> nsteps;
-  size_t footprint = 0;
+  int64_t footprint = 0;
 };
 
 constexpr int kMaxOvertake = 64;
+constexpr double kChunkSeconds = 0.01;
+constexpr double kHbmBytesPerSecond = 4.0e12;  // sustained gather rate assumed for chunk sizing
 
 std::string key_of(const void* p, size_t n) { return std::string((const char*)p, n); }
+
+struct BuildReq {
+  bool sector = false;  // false: group
+  std::string key;
+  std::shared_ptr<Job> job;  // source of the cluster description
+  std::shared_ptr<Group> G;  // sector builds
+};
+
+struct BuildRes {
+  bool sector = false;
+  std::string key;
+  std::shared_ptr<Group> G;
+  std::shared_ptr<Sector> S;
+  int code = FTLM_OK;
+  std::string msg;
+};
+
+// Number of labels with digit sum A2/2 (the sector dimension D_M).
+long double sector_dim(int N, int two_s, int two_M) {
+  const int d = two_s + 1, Amax = N * (d - 1);
+  std::vector<long double> c(Amax + 1, 0), n2(Amax + 1, 0);
+  c[0] = 1;
+  for (int k = 0; k < N; ++k) {
+    std::fill(n2.begin(), n2.end(), 0);
+    for (int v = 0; v <= Amax; ++v)
+      for (int a = 0; a < d && a <= v; ++a) n2[v] += c[v - a];
+    c.swap(n2);
+  }
+  const int A2 = N * two_s + two_M;
+  return (A2 % 2 || A2 < 0 || A2 / 2 > Amax) ? 0 : c[A2 / 2];
+}
 
 }  // namespace
 
@@ -82,9 +126,18 @@ struct Server {
   bool stop = false;
   int n_running = 0;
   std::atomic<int64_t> used{0};
-  std::thread worker;
+  std::thread worker, builder;
+  // builder hand-off
+  std::mutex bmu;
+  std::condition_variable bcv;
+  std::deque<BuildReq> breq;
+  std::vector<BuildRes> bdone;
+  bool bstop = false;
+  hipStream_t bstream = nullptr;  // sector tables live on it (stream-ordered frees)
   // worker-only state
   std::map<std::string, std::shared_ptr<Group>> groups;
+  std::map<std::string, std::pair<int, std::string>> group_failed;
+  std::set<std::string> group_building;
   struct SecEntry {
     std::shared_ptr<Sector> sec;
     int users = 0;
@@ -92,116 +145,212 @@ struct Server {
     int64_t bytes = 0;
   };
   std::map<std::string, SecEntry> sectors;
+  std::map<std::string, int64_t> sector_building;  // key -> reserved bytes
   uint64_t tick = 0;
   hipStream_t build = nullptr;
   std::vector<std::shared_ptr<Job>> running;
   // Streams, events and pinned result buffers are recycled: creating and
   // freeing them per job would add driver calls that can serialize the device.
   std::vector<std::pair<hipStream_t, hipEvent_t>> free_streams;
+  std::vector<hipEvent_t> free_events;
   std::multimap<size_t, void*> free_pinned;
 
   void loop();
-  bool try_admit(const std::shared_ptr<Job>& j);
+  void feed(Job& j);
+  void builder_loop();
+  void request(BuildReq r);
+  void take_builds();
+  // 1: admitted or ended, 0: waits for memory or a slot, -1: waits for a build
+  int try_admit(const std::shared_ptr<Job>& j);
+  void launch(const std::shared_ptr<Job>& j, SecEntry& se);
   void retire(const std::shared_ptr<Job>& j, int status);
-  int64_t estimate(const Job& j, const Group& G);
-  std::shared_ptr<Group> group_of(const Job& j);
-  void evict_unused(int64_t need);
+  int64_t estimate_sector(const Job& j, const Group& G) const;
+  int64_t estimate_job(const Job& j, const Group& G, const Sector& S) const;
+  void evict_unused(int64_t need, const std::string& keep);
+  void dequeue(int64_t id);
 };
 
-std::shared_ptr<Group> Server::group_of(const Job& j) {
-  const std::string gkey = key_of(j.gens.data(), j.gens.size() * 4) + key_of(&j.N, 4);
-  auto git = groups.find(gkey);
-  if (git == groups.end()) {
-    auto g = std::make_shared<Group>(build_group(j.N, j.gens.data(), j.ngens));
-    compute_irreps(*g);
-    git = groups.emplace(gkey, std::move(g)).first;
-  }
-  return git->second;
+// Upper bounds: orbits number at most D_M / |G| plus the labels with a
+// non-trivial stabilizer (the 1.2 margin and the constant cover those), and
+// every bond gives at most one admissible flip per direction.
+int64_t Server::estimate_sector(const Job& j, const Group& G) const {
+  const long double DM = sector_dim(j.N, j.two_s, j.two_M);
+  const long double reps = DM / G.order * 1.2 + 16;
+  const long double flips = (long double)j.bonds.size() / 2 * (j.two_s == 1 ? 1.0 : 2.0);
+  const long double b = DM / 8 + DM / 64 * 4 + reps * 34 + reps * flips * 8 + (1 << 20);
+  return (int64_t)std::min<long double>(b, 9.0e18);
 }
 
-// Device bytes a job will add, from the group and the sector size alone
-// (upper bounds: every representative carries a full d_Gamma block, every
-// bond a flip), plus the sector tables unless they are resident.
-int64_t Server::estimate(const Job& j, const Group& Gr) {
-  const int d = j.two_s + 1;
-  long double DM = 1;
-  {
-    // digit-sum count for this M via the same counting recursion as the sector
-    const int Amax = j.N * (d - 1);
-    std::vector<long double> c(Amax + 1, 0), n2(Amax + 1, 0);
-    c[0] = 1;
-    for (int k = 0; k < j.N; ++k) {
-      std::fill(n2.begin(), n2.end(), 0);
-      for (int v = 0; v <= Amax; ++v)
-        for (int a = 0; a < d && a <= v; ++a) n2[v] += c[v - a];
-      c.swap(n2);
-    }
-    const int A2 = j.N * j.two_s + j.two_M;
-    DM = (A2 % 2 || A2 < 0 || A2 / 2 > Amax) ? 0 : c[A2 / 2];
-  }
-  const long double G = Gr.order;
-  const int dg = (Gr.irreps_computed && j.irrep >= 0 && j.irrep < (int)Gr.irreps.size()) ? Gr.irreps[j.irrep].dim : 1;
-  // orbits of a group of order |G| number at most D_M / |G| + (labels with a
-  // nontrivial stabilizer); the 1.2 margin and the constant cover the latter
-  const long double reps = DM / G * 1.2 + 16;
-  const long double D = reps * dg;
-  long double sec = 0;
-  if (sectors.find(j.sector_key) == sectors.end()) {
-    const long double flips = j.bonds.size() / 2.0 * (j.two_s == 1 ? 1.0 : 2.0);
-    sec = DM / 8 * 1.5 + reps * 34 + reps * flips * 8;
-  }
-  const long double vec = 2 * D * j.R * (j.storage == FTLM_F64 ? 8 : 4) + reps * 16 + 8192.0 * j.R * 8;
-  return (int64_t)std::min<long double>(sec + vec + (1 << 20), 9.0e18);
+int64_t Server::estimate_job(const Job& j, const Group& G, const Sector& S) const {
+  const int dg = (G.irreps_computed && j.irrep >= 0 && j.irrep < (int)G.irreps.size()) ? G.irreps[j.irrep].dim : 1;
+  const long double D = (long double)S.n_reps * dg;  // >= the block dimension
+  const long double b = (long double)S.n_reps * 16 + 2 * D * j.R * (j.storage == FTLM_F64 ? 8 : 4) +
+                        8192.0 * j.R * 8 + (long double)j.R * j.steps * 16 + (1 << 20);
+  return (int64_t)std::min<long double>(b, 9.0e18);
 }
 
-void Server::evict_unused(int64_t need) {
+void Server::evict_unused(int64_t need, const std::string& keep) {
   while (used + need > budget) {
     auto victim = sectors.end();
     for (auto it = sectors.begin(); it != sectors.end(); ++it)
-      if (it->second.users == 0 && (victim == sectors.end() || it->second.last < victim->second.last)) victim = it;
+      if (it->second.users == 0 && it->first != keep &&
+          (victim == sectors.end() || it->second.last < victim->second.last))
+        victim = it;
     if (victim == sectors.end()) return;
     used -= victim->second.bytes;
     sectors.erase(victim);
   }
 }
 
-bool Server::try_admit(const std::shared_ptr<Job>& j) {
-  std::shared_ptr<Group> G;
-  try {
-    G = group_of(*j);
-  } catch (const Error& e) {
-    j->msg = e.what();
-    retire(j, e.code);
-    return true;
-  } catch (const std::exception& e) {
-    j->msg = e.what();
-    retire(j, FTLM_ERR_INVALID_ARG);
-    return true;
+void Server::request(BuildReq r) {
+  std::lock_guard<std::mutex> lk(bmu);
+  breq.push_back(std::move(r));
+  bcv.notify_all();
+}
+
+void Server::builder_loop() {
+  (void)hipSetDevice(device);
+  while (true) {
+    BuildReq r;
+    {
+      std::unique_lock<std::mutex> lk(bmu);
+      bcv.wait(lk, [&] { return bstop || !breq.empty(); });
+      if (bstop) break;
+      r = std::move(breq.front());
+      breq.pop_front();
+    }
+    BuildRes res;
+    res.sector = r.sector;
+    res.key = r.key;
+    try {
+      const Job& j = *r.job;
+      if (!r.sector) {
+        auto g = std::make_shared<Group>(build_group(j.N, j.gens.data(), j.ngens));
+        compute_irreps(*g);
+        res.G = std::move(g);
+      } else {
+        AllocStreamScope scope(bstream);
+        ftlm_cluster cl{j.N, j.two_s, (int32_t)(j.bonds.size() / 2), j.bonds.data(), j.J.data()};
+        ftlm_opts o{};
+        o.hv_mode = FTLM_HV_AUTO;
+        res.S = build_sector(&cl, r.G, j.two_M, &o);  // synchronizes bstream before returning
+      }
+    } catch (const Error& e) {
+      res.code = e.code;
+      res.msg = e.what();
+    } catch (const std::exception& e) {
+      res.code = FTLM_ERR_INVALID_ARG;
+      res.msg = e.what();
+    }
+    {
+      std::lock_guard<std::mutex> lk(bmu);
+      bdone.push_back(std::move(res));
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    cv_work.notify_all();
   }
-  const int64_t est = estimate(*j, *G);
+}
+
+void Server::dequeue(int64_t id) {
+  std::lock_guard<std::mutex> lk(mu);
+  for (auto it = queue.begin(); it != queue.end(); ++it)
+    if (*it == id) {
+      queue.erase(it);
+      break;
+    }
+}
+
+void Server::take_builds() {
+  std::vector<BuildRes> done;
+  {
+    std::lock_guard<std::mutex> lk(bmu);
+    done.swap(bdone);
+  }
+  for (auto& r : done) {
+    if (!r.sector) {
+      group_building.erase(r.key);
+      if (r.code == FTLM_OK)
+        groups[r.key] = r.G;
+      else
+        group_failed[r.key] = {r.code, r.msg};
+      continue;
+    }
+    auto rit = sector_building.find(r.key);
+    if (rit != sector_building.end()) {
+      used -= rit->second;
+      sector_building.erase(rit);
+    }
+    if (r.code == FTLM_OK) {
+      SecEntry& se = sectors[r.key];
+      se.sec = std::move(r.S);
+      se.bytes = se.sec->device_bytes();
+      se.last = ++tick;
+      used += se.bytes;
+      continue;
+    }
+    // the queued jobs that wait for this sector end with the build's error
+    std::vector<std::shared_ptr<Job>> failed;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      for (int64_t id : queue) {
+        auto& j = jobs[id];
+        if (j->sector_key == r.key) failed.push_back(j);
+      }
+    }
+    for (auto& j : failed) {
+      j->msg = r.msg;
+      retire(j, r.code);
+      dequeue(j->id);
+    }
+  }
+}
+
+int Server::try_admit(const std::shared_ptr<Job>& j) {
+  auto gf = group_failed.find(j->group_key);
+  if (gf != group_failed.end()) {
+    j->msg = gf->second.second;
+    retire(j, gf->second.first);
+    return 1;
+  }
+  auto git = groups.find(j->group_key);
+  if (git == groups.end()) {
+    if (group_building.insert(j->group_key).second) request(BuildReq{false, j->group_key, j, nullptr});
+    return -1;
+  }
+  const Group& G = *git->second;
+  auto sit = sectors.find(j->sector_key);
+  if (sit == sectors.end()) {
+    if (sector_building.count(j->sector_key)) return -1;
+    const int64_t est = estimate_sector(*j, G);
+    if (est > budget) {
+      j->msg = "estimated sector tables of " + std::to_string(est) + " bytes exceed the server budget";
+      retire(j, FTLM_ERR_OUT_OF_MEMORY);
+      return 1;
+    }
+    if (used + est > budget) evict_unused(est, j->sector_key);
+    if (used + est > budget) return 0;
+    used += est;
+    sector_building[j->sector_key] = est;
+    request(BuildReq{true, j->sector_key, j, git->second});
+    return -1;
+  }
+  SecEntry& se = sit->second;
+  if ((int)running.size() >= max_active) return 0;
+  const int64_t est = estimate_job(*j, G, *se.sec);
   if (est > budget) {
-    j->msg = "estimated device footprint " + std::to_string(est) + " bytes exceeds the server budget";
+    j->msg = "estimated job footprint of " + std::to_string(est) + " bytes exceeds the server budget";
     retire(j, FTLM_ERR_OUT_OF_MEMORY);
-    return true;
+    return 1;
   }
-  if (used + est > budget) evict_unused(est);
-  if (used + est > budget) return false;  // wait for memory
+  if (used + est > budget) evict_unused(est, j->sector_key);
+  if (used + est > budget) return 0;
+  launch(j, se);
+  return 1;
+}
+
+void Server::launch(const std::shared_ptr<Job>& j, SecEntry& se) {
   try {
     AllocStreamScope scope(build);
-    SecEntry& se = sectors[j->sector_key];
-    if (!se.sec) {
-      ftlm_cluster cl{j->N, j->two_s, (int32_t)(j->bonds.size() / 2), j->bonds.data(), j->J.data()};
-      ftlm_opts o{};
-      o.hv_mode = FTLM_HV_AUTO;
-      try {
-        se.sec = build_sector(&cl, G, j->two_M, &o);
-      } catch (...) {
-        sectors.erase(j->sector_key);
-        throw;
-      }
-      se.bytes = se.sec->device_bytes();
-      used += se.bytes;
-    }
     se.users++;
     se.last = ++tick;
     j->holds_sector = true;
@@ -237,10 +386,22 @@ bool Server::try_admit(const std::shared_ptr<Job>& j) {
       AllocStreamScope js(j->stream);
       j->run = std::make_unique<LanczosRun>(*j->block, j->R, j->steps, j->seed, j->storage, j->dist);
       j->run->allocate();
-      j->run->enqueue(j->stream);
-      j->run->download(j->stream, j->h_alpha, j->h_beta, j->h_n);
+      j->run->enqueue_begin(j->stream);
     }
-    FTLM_HIP(hipEventRecord(j->ev, j->stream));
+    // Steps go to the stream in chunks of about kChunkSeconds of estimated
+    // HBM time, so a long run never holds a shared hardware queue for more
+    // than one chunk ahead of other jobs' work.
+    {
+      const Sector& S = *j->block->sec;
+      const double elem = j->storage == FTLM_F64 ? 8.0 : 4.0;
+      const double rows = S.n_reps ? (double)j->D / (double)S.n_reps : 0.0;
+      const double step_bytes = (double)S.n_entries * (rows * j->R * elem + 8.0) + 6.0 * (double)j->D * j->R * elem;
+      const double step_s = step_bytes / kHbmBytesPerSecond;
+      j->chunk = (int)std::max(1.0, std::min((double)std::max(j->run->target, 1), kChunkSeconds / std::max(step_s, 1e-9)));
+    }
+    j->next_step = 0;
+    j->enqueued_all = false;
+    feed(*j);
     j->running = true;
     j->t_start = now_s(t0);
     running.push_back(j);
@@ -253,7 +414,45 @@ bool Server::try_admit(const std::shared_ptr<Job>& j) {
     j->msg = e.what();
     retire(j, FTLM_ERR_INVALID_ARG);
   }
-  return true;
+}
+
+// Keeps up to two chunks of steps in flight; after the last step enqueues the
+// step counts, the copy of the coefficients and the completion event.  A
+// cancelled running job stops receiving steps.
+void Server::feed(Job& j) {
+  while (!j.inflight.empty() && hipEventQuery(j.inflight.front()) == hipSuccess) {
+    free_events.push_back(j.inflight.front());
+    j.inflight.pop_front();
+  }
+  if (j.enqueued_all) return;
+  bool cancel;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    cancel = j.cancel;
+  }
+  const int target = j.run->target;
+  while (!cancel && j.next_step < target && j.inflight.size() < 2) {
+    const int j1 = std::min(target, j.next_step + j.chunk);
+    j.run->enqueue_steps(j.stream, j.next_step, j1);
+    j.next_step = j1;
+    hipEvent_t e;
+    if (!free_events.empty()) {
+      e = free_events.back();
+      free_events.pop_back();
+    } else {
+      FTLM_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    FTLM_HIP(hipEventRecord(e, j.stream));
+    j.inflight.push_back(e);
+  }
+  if (cancel || j.next_step >= target) {
+    if (!cancel) {
+      j.run->enqueue_end(j.stream);
+      j.run->download(j.stream, j.h_alpha, j.h_beta, j.h_n);
+    }
+    FTLM_HIP(hipEventRecord(j.ev, j.stream));
+    j.enqueued_all = true;
+  }
 }
 
 void Server::retire(const std::shared_ptr<Job>& j, int status) {
@@ -263,20 +462,22 @@ void Server::retire(const std::shared_ptr<Job>& j, int status) {
     j->beta.assign(j->h_beta, j->h_beta + (size_t)j->R * j->steps);
     j->nsteps.assign(j->h_n, j->h_n + j->R);
   }
-  j->run.reset();   // stream-ordered frees on the job's stream
+  j->run.reset();  // stream-ordered frees on the job's stream
   if (j->stream) (void)hipStreamSynchronize(j->stream);
   j->block.reset();
   if (j->h_buf) free_pinned.emplace(j->h_bytes, j->h_buf);
   j->h_buf = nullptr;
   j->h_alpha = j->h_beta = nullptr;
   j->h_n = nullptr;
+  for (hipEvent_t e : j->inflight) free_events.push_back(e);
+  j->inflight.clear();
   if (j->stream) free_streams.emplace_back(j->stream, j->ev);
   j->ev = nullptr;
   j->stream = nullptr;
   auto it = sectors.find(j->sector_key);
   if (j->holds_sector && it != sectors.end()) it->second.users--;
   j->holds_sector = false;
-  used -= (int64_t)j->footprint;
+  used -= j->footprint;
   j->footprint = 0;
   std::lock_guard<std::mutex> lk(mu);
   if (j->running) n_running--;
@@ -290,11 +491,23 @@ void Server::retire(const std::shared_ptr<Job>& j, int status) {
 void Server::loop() {
   (void)hipSetDevice(device);
   (void)hipStreamCreateWithFlags(&build, hipStreamNonBlocking);
+  (void)hipStreamCreateWithFlags(&bstream, hipStreamNonBlocking);
+  builder = std::thread([this] { builder_loop(); });
   while (true) {
+    take_builds();
     // retire finished jobs
     for (size_t i = 0; i < running.size();) {
       auto& j = running[i];
-      if (hipEventQuery(j->ev) == hipSuccess) {
+      try {
+        feed(*j);
+      } catch (const Error& e) {
+        auto jj = j;
+        running.erase(running.begin() + i);
+        jj->msg = e.what();
+        retire(jj, e.code);
+        continue;
+      }
+      if (j->enqueued_all && hipEventQuery(j->ev) == hipSuccess) {
         bool c;
         {
           std::lock_guard<std::mutex> lk(mu);
@@ -308,7 +521,7 @@ void Server::loop() {
         ++i;
       }
     }
-    // admit queued jobs
+    // walk the queue
     std::vector<std::shared_ptr<Job>> pending;
     {
       std::lock_guard<std::mutex> lk(mu);
@@ -318,53 +531,62 @@ void Server::loop() {
     bool head_blocked = false;
     std::vector<Job*> refused;
     for (auto& j : pending) {
-      if ((int)running.size() >= max_active) break;
-      // A job that has been overtaken kMaxOvertake times blocks the queue
-      // behind it until it is admitted, so large jobs are not starved.
+      // A job that has been overtaken kMaxOvertake times holds back the
+      // queue behind it until it is admitted, so large jobs are not starved.
       if (head_blocked) break;
       bool cancelled;
       {
         std::lock_guard<std::mutex> lk(mu);
         cancelled = j->cancel || stop;
       }
-      bool taken;
+      int r;
       if (cancelled) {
         j->msg = "cancelled";
         retire(j, FTLM_ERR_CANCELLED);
-        taken = true;
+        r = 1;
       } else {
-        taken = try_admit(j);
+        r = try_admit(j);
       }
-      if (!taken) {
+      if (r == 0) {
         refused.push_back(j.get());
-      } else if (j->running) {
-        for (Job* r : refused)
-          if (++r->overtaken >= kMaxOvertake) head_blocked = true;
-      }
-      if (taken) {
-        std::lock_guard<std::mutex> lk(mu);
-        for (auto it = queue.begin(); it != queue.end(); ++it)
-          if (*it == j->id) {
-            queue.erase(it);
-            break;
-          }
+      } else if (r == 1) {
+        if (j->running)
+          for (Job* q : refused)
+            if (++q->overtaken >= kMaxOvertake) head_blocked = true;
+        dequeue(j->id);
       }
     }
     std::unique_lock<std::mutex> lk(mu);
-    if (running.empty() && (queue.empty() || stop)) {
-      if (stop && queue.empty()) break;
+    if (running.empty() && queue.empty()) {
+      if (stop) break;
       cv_work.wait(lk, [&] { return stop || !queue.empty(); });
     } else {
       cv_work.wait_for(lk, std::chrono::microseconds(200));
     }
   }
+  {
+    std::lock_guard<std::mutex> lk(bmu);
+    bstop = true;
+    bcv.notify_all();
+  }
+  if (builder.joinable()) builder.join();
+  {
+    std::lock_guard<std::mutex> lk(bmu);
+    bdone.clear();
+    breq.clear();
+  }
   sectors.clear();
+  groups.clear();
+  if (bstream) (void)hipStreamSynchronize(bstream);
   if (build) (void)hipStreamSynchronize(build);
-  if (build) (void)hipStreamDestroy(build);
+  for (hipStream_t* sp : {&build, &bstream})
+    if (*sp) (void)hipStreamDestroy(*sp);
   for (auto& se : free_streams) {
     (void)hipEventDestroy(se.second);
     (void)hipStreamDestroy(se.first);
   }
+  for (hipEvent_t e : free_events) (void)hipEventDestroy(e);
+  free_events.clear();
   for (auto& pb : free_pinned) (void)hipHostFree(pb.second);
   free_streams.clear();
   free_pinned.clear();
@@ -433,6 +655,7 @@ int ftlm_server_submit(ftlm_server* h, const ftlm_job_desc* d, int64_t* job_id) 
     j->seed = d->seed;
     j->storage = d->storage;
     j->dist = d->dist;
+    j->group_key = key_of(&j->N, 4) + key_of(j->gens.data(), j->gens.size() * 4);
     j->sector_key = key_of(&j->N, 4) + key_of(&j->two_s, 4) + key_of(&j->two_M, 4) +
                     key_of(j->bonds.data(), j->bonds.size() * 4) + key_of(j->J.data(), j->J.size() * 8) +
                     key_of(j->gens.data(), j->gens.size() * 4);

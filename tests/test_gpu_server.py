@@ -148,3 +148,22 @@ def test_free_with_jobs_in_flight():
     for k in range(6):
         srv.submit(cl, cl.gens, 0, 0, 0, 4, 30, k, two_s=1)
     srv.close()                          # cancels queued jobs, drains running ones
+
+
+def test_long_job_fed_in_chunks_matches_standalone():
+    """A job whose steps are fed to the device in several chunks (the H_g block
+    of the icosidodecahedron, D = 6,465,762) next to small jobs gives the same
+    coefficients, bit for bit, as one ftlm_run call."""
+    _enums()
+    log("[server] chunked long job")
+    big = ("icosidodecahedron", 0, 8, 0, 8, 20, 31, "f32", "gau")
+    small = [("icosahedron", 0, 8, 1, 4, 40, 32 + k, "f64", "rad") for k in range(6)]
+    srv = P.Server(16 << 30, max_active=4)
+    ids = [_submit(srv, big)] + [_submit(srv, j) for j in small]
+    res = [srv.wait(i) for i in ids]
+    srv.close()
+    assert res[0][0]["D"] == 6465762
+    for job, (r, a, b, n) in zip([big] + small, res):
+        assert r["status"] == 0, (job, r)
+        a0, b0, n0 = _standalone(job)
+        assert np.array_equal(n, n0) and np.array_equal(a, a0) and np.array_equal(b, b0), job
