@@ -33,6 +33,11 @@ WORKLOADS = {
                                  desc="s=1/2 Heisenberg icosidodecahedron (N=30, 60 bonds), I_h, M=0, "
                                       "irrep H_g row 1 (D=6,465,762); R=24 Gaussian chains, 60 Lanczos steps, "
                                       "FP32 storage, FP64 reductions"),
+    "dodecahedron_s32_Hg": dict(cluster="dodecahedron", two_s=3, two_M=0, irrep=8, R=2, steps=60,
+                                dist="rademacher", storage="f32",
+                                desc="s=3/2 Heisenberg dodecahedron (N=20, 30 bonds, 40-bit labels), I_h, M=0 "
+                                     "(D_M=86,981,744,944), irrep H_g row 1 (D=3,624,380,734); R=2 Rademacher chains, "
+                                     "60 Lanczos steps, FP32 storage, FP64 reductions"),
     "dodecahedron_Hg": dict(cluster="dodecahedron", two_s=1, two_M=0, irrep=8, R=24, steps=60, dist="rademacher",
                             storage="f64",
                             desc="s=1/2 dodecahedron (N=20), I_h, M=0, irrep H_g (D=7,800); R=24 Rademacher, "
@@ -84,9 +89,13 @@ def cpu_baseline(wl, seconds):
             bits = rng.choice(cl.N, A, replace=False)
             lab = int(np.sum(2 ** bits.astype(np.int64)))
         else:
-            raise NotImplementedError
+            while True:  # a uniform state of the sector: digits with sum A, by rejection
+                dig = rng.integers(0, d, cl.N)
+                if dig.sum() == A:
+                    break
+            lab = int(sum(int(a) * d ** k for k, a in enumerate(dig)))
         p, _ = obasis.canonicalize(G, np.array([lab]), cl.N, d)
-        out = ohv.sampled_rows(G, ir, 0, cl.N, wl["two_s"], cl.bonds, cl.J, [int(p[0])], xfun, 1)
+        out = ohv.sampled_rows(G, ir, 0, cl.N, wl["two_s"], cl.bonds, cl.J, [int(p[0])], xfun, 1)  # row 0
         rows += out[0].shape[0]
         reps_done += 1
     el = time.perf_counter() - t0
@@ -309,6 +318,7 @@ def main():
     balg = algorithmic_bytes(stats, B.D, S.n_reps, wl["R"], elem)
     achieved = balg / (hv_ms * 1e-3) / 1e9
     # plain single-vector FP64 H.V for the speedup figure
+    del X, Y
     X1 = torch.randn((B.D, 1), dtype=torch.float64, device=dev)
     Y1 = torch.empty_like(X1)
     B.apply_H(X1, Y1, stream=stream)

@@ -73,15 +73,17 @@ double check_user_rho(const Group& G, const double* rho, int d) {
   return worst;
 }
 
-__global__ void k_hv_stats(const uint64_t* __restrict__ meta, const uint64_t* __restrict__ row_ptr,
-                           const uint64_t* __restrict__ entries, const uint8_t* __restrict__ n_stab, uint64_t n,
-                           unsigned long long* __restrict__ out) {
+__global__ void __launch_bounds__(256) k_hv_stats(const uint64_t* __restrict__ meta, const uint64_t* __restrict__ row_ptr,
+                                                 const uint64_t* __restrict__ entries, const uint32_t* __restrict__ eidx,
+                                                 const uint8_t* __restrict__ n_stab, uint64_t n,
+                                                 unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long red[4][256];
   unsigned long long c = 0, ca = 0, rows = 0, act = 0;
   for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (uint64_t)gridDim.x * blockDim.x) {
     if (n_stab[meta[p] >> 48] == 0) continue;
     ++act;
     for (uint64_t e = row_ptr[p]; e < row_ptr[p + 1]; ++e) {
-      const uint64_t idx = entries[e] & 0xffffffffull;
+      const uint64_t idx = eidx ? (uint64_t)eidx[e] : (entries[e] & 0xffffffffull);
       ++c;
       if (idx == 0xffffffffull) continue;
       const unsigned nr = n_stab[meta[idx] >> 48];
@@ -91,10 +93,17 @@ __global__ void k_hv_stats(const uint64_t* __restrict__ meta, const uint64_t* __
       }
     }
   }
-  atomicAdd(&out[0], act);
-  atomicAdd(&out[1], c);
-  atomicAdd(&out[2], ca);
-  atomicAdd(&out[3], rows);
+  red[0][threadIdx.x] = act;
+  red[1][threadIdx.x] = c;
+  red[2][threadIdx.x] = ca;
+  red[3][threadIdx.x] = rows;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+      for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) atomicAdd(&out[threadIdx.x], red[threadIdx.x][0]);
 }
 
 }  // namespace
@@ -111,7 +120,7 @@ void block_hv_stats(const Block& b, ftlm_hv_stats* res) {
   hipStream_t st = tl_alloc_stream;
   FTLM_HIP(hipMemsetAsync(out.p, 0, out.bytes(), st));
   hipLaunchKernelGGL(k_hv_stats, dim3(grid1(s.n_reps)), dim3(256), 0, st, b.d_meta.p, s.d_row_ptr.p,
-                     s.d_entries.p, d_n.p, s.n_reps, out.p);
+                     s.d_entries.p, s.d_eidx.p, d_n.p, s.n_reps, out.p);
   FTLM_HIP(hipGetLastError());
   unsigned long long h[4];
   FTLM_HIP(hipMemcpyAsync(h, out.p, sizeof(h), hipMemcpyDeviceToHost, st));

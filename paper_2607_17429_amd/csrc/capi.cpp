@@ -110,7 +110,7 @@ int ftlm_sector_info_get(const ftlm_sector* s, ftlm_sector_info* info) {
     const Sector& S = *s->s;
     info->D_M = S.D_M;
     info->n_reps = S.n_reps;
-    info->n_entries = S.d_entries.n;
+    info->n_entries = S.hv_mode == FTLM_HV_ENTRIES ? S.n_entries : 0;
     info->n_stab = S.n_stab;
     info->label_bits = S.bits;
     info->device_bytes = S.device_bytes();

@@ -197,6 +197,9 @@ void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
     a.reps = s.d_reps.p;
     a.row_ptr = s.d_row_ptr.p;
     a.entries = s.d_entries.p;
+    a.eidx = s.d_eidx.p;
+    a.ehc = s.d_ehc.p;
+    a.hbits = s.ent_hbits;
     a.meta = b.d_meta.p;
     a.ediag = s.d_ediag.p;
     a.rhoT = b.d_rhoT64.p;

@@ -58,7 +58,10 @@ template <typename T>
 struct HvArgs {
   const uint64_t* reps;
   const uint64_t* row_ptr;
-  const uint64_t* entries;
+  const uint64_t* entries;   // 8-byte entries, or
+  const uint32_t* eidx;      // the 6-byte split form (eidx != nullptr)
+  const uint16_t* ehc;
+  int hbits;
   const uint64_t* meta;
   const double* ediag;
   const double* rhoT;   // [g][beta][gamma], stride DG
@@ -185,7 +188,15 @@ k_hv(HvArgs<T> a) {
       // ---- one flip per lane: entry and target metadata
       uint64_t my = kInvalid;
       if constexpr (!OTF) {
-        if (e + lg < e_end) my = a.entries[e + lg];
+        if (e + lg < e_end) {
+          if (a.eidx) {
+            const uint32_t hc = a.ehc[e + lg];
+            my = (uint64_t)a.eidx[e + lg] | ((uint64_t)(hc & ((1u << a.hbits) - 1)) << 32) |
+                 ((uint64_t)(hc >> a.hbits) << 48);
+          } else {
+            my = a.entries[e + lg];
+          }
+        }
       } else {
         const int cand = (int)e + lg;
         bool ok = false;

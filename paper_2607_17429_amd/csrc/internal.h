@@ -47,7 +47,13 @@ struct Sector {
   DevBuf<uint16_t> d_stab_id;
   DevBuf<double> d_ediag;       // Eq. (16) per representative
   DevBuf<uint64_t> d_row_ptr;   // entries of representative i: [row_ptr[i], row_ptr[i+1])
-  DevBuf<uint64_t> d_entries;   // idx | h << 32 | flip << 48
+  // entries of a flip: target index, connecting element h, flip id 2*bond + sign;
+  // 8-byte form idx | h << 32 | flip << 48, or the 6-byte split form
+  // (eidx = idx, ehc = h | flip << ent_hbits) when h and flip fit 16 bits
+  DevBuf<uint64_t> d_entries;
+  DevBuf<uint32_t> d_eidx;
+  DevBuf<uint16_t> d_ehc;
+  int entry_bytes = 8, ent_hbits = 16;
   uint64_t n_entries = 0;
   DevBuf<int32_t> d_bonds;
   DevBuf<double> d_J;
@@ -55,7 +61,8 @@ struct Sector {
   int64_t device_bytes() const {
     return (int64_t)(d_tab.bytes() + d_cnt.bytes() + d_rank_bits.bytes() + d_rank_base.bytes() +
                      d_reps.bytes() + d_stab_id.bytes() + d_ediag.bytes() + d_row_ptr.bytes() +
-                     d_entries.bytes() + d_bonds.bytes() + d_J.bytes() + d_fac.bytes());
+                     d_entries.bytes() + d_eidx.bytes() + d_ehc.bytes() + d_bonds.bytes() + d_J.bytes() +
+                     d_fac.bytes());
   }
 };
 

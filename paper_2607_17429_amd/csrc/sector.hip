@@ -266,7 +266,9 @@ __global__ void __launch_bounds__(kThreads) k_entry_fill(SecArgs a, FlipArgs f, 
                                                         const uint64_t* __restrict__ row_ptr,
                                                         const uint64_t* __restrict__ bits,
                                                         const uint32_t* __restrict__ base,
-                                                        uint64_t* __restrict__ entries) {
+                                                        uint64_t* __restrict__ entries,
+                                                        uint32_t* __restrict__ eidx, uint16_t* __restrict__ ehc,
+                                                        int hbits) {
   extern __shared__ uint64_t smem_raw[];
   const W* tab = stage_table<W, LDS>((const W*)a.tab, a.tab_words, (W*)smem_raw);
   const dev::OrbitTabs<W, NCH> o = dev::orbit_tabs<W, NCH>(tab, a.nH, a.nT);
@@ -289,7 +291,13 @@ __global__ void __launch_bounds__(kThreads) k_entry_fill(SecArgs a, FlipArgs f, 
         uint64_t idx = 0;
         bool ok = lookup<W>(r, a, bits, base, idx);
         // a canonical label of the sector is always a representative
-        entries[out++] = (ok ? idx : 0xFFFFFFFFull) | ((uint64_t)h << 32) | ((uint64_t)cur << 48);
+        if (eidx) {
+          eidx[out] = ok ? (uint32_t)idx : 0xFFFFFFFFu;
+          ehc[out] = (uint16_t)(h | (cur << hbits));
+          ++out;
+        } else {
+          entries[out++] = (ok ? idx : 0xFFFFFFFFull) | ((uint64_t)h << 32) | ((uint64_t)cur << 48);
+        }
         cur = next_admissible<W>(p, cur, ncand, f, a.b, a.d, mask);
       }
     }
@@ -634,24 +642,41 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
   uint64_t n_ent = 0;
   scan_exclusive_u64(s.d_row_ptr.p, s.d_row_ptr.p, s.n_reps + 1, &n_ent, st);
   s.n_entries = n_ent;
+  // Entry format: 6 bytes (u32 target index + u16 holding h and the flip id)
+  // when both fit in 16 bits, 8 bytes (one u64) otherwise.
+  {
+    int hb = 1, cb = 1;
+    while ((1 << hb) < G_) ++hb;
+    while ((1 << cb) < 2 * s.nbonds) ++cb;
+    s.ent_hbits = hb;
+    s.entry_bytes = hb + cb <= 16 ? 6 : 8;
+  }
   int mode = opts ? opts->hv_mode : FTLM_HV_AUTO;
   if (mode == FTLM_HV_AUTO) {
+    // the table must leave a third of the free memory for blocks and vectors
     size_t free_b = 0, total_b = 0;
     FTLM_HIP(hipMemGetInfo(&free_b, &total_b));
-    mode = (n_ent * 8 < free_b / 3) ? FTLM_HV_ENTRIES : FTLM_HV_ONTHEFLY;
+    mode = ((double)n_ent * s.entry_bytes <= (double)free_b * 2.0 / 3.0) ? FTLM_HV_ENTRIES : FTLM_HV_ONTHEFLY;
   }
-  if (limit > 0 && (int64_t)(s.device_bytes() + (mode == FTLM_HV_ENTRIES ? n_ent * 8 : 0)) > limit)
+  if (limit > 0 && (int64_t)(s.device_bytes() + (mode == FTLM_HV_ENTRIES ? n_ent * s.entry_bytes : 0)) > limit)
     fail(FTLM_ERR_OUT_OF_MEMORY, "sector tables exceed the HBM limit");
   s.hv_mode = mode;
   if (mode == FTLM_HV_ENTRIES && n_ent) {
-    s.d_entries.alloc(n_ent);
+    if (s.entry_bytes == 6) {
+      s.d_eidx.alloc(n_ent);
+      s.d_ehc.alloc(n_ent);
+    } else {
+      s.d_entries.alloc(n_ent);
+    }
     FTLM_DISPATCH_NCH(s.nch, {
       if (lds)
         hipLaunchKernelGGL((k_entry_fill<W, NCH, true>), dim3(grid_for(s.n_reps)), dim3(kThreads), shm, st, a, f,
-                           s.d_reps.p, s.d_row_ptr.p, s.d_rank_bits.p, s.d_rank_base.p, s.d_entries.p);
+                           s.d_reps.p, s.d_row_ptr.p, s.d_rank_bits.p, s.d_rank_base.p, s.d_entries.p, s.d_eidx.p,
+                           s.d_ehc.p, s.ent_hbits);
       else
         hipLaunchKernelGGL((k_entry_fill<W, NCH, false>), dim3(grid_for(s.n_reps)), dim3(kThreads), 0, st, a, f,
-                           s.d_reps.p, s.d_row_ptr.p, s.d_rank_bits.p, s.d_rank_base.p, s.d_entries.p);
+                           s.d_reps.p, s.d_row_ptr.p, s.d_rank_bits.p, s.d_rank_base.p, s.d_entries.p, s.d_eidx.p,
+                           s.d_ehc.p, s.ent_hbits);
     });
     FTLM_HIP(hipGetLastError());
   }

@@ -57,3 +57,33 @@ def label_keyed_block_vector(seed: int, rep_labels, counts, nvec: int):
 def dense_uniform(seed: int, shape):
     """Plain seeded uniform [-1, 1) array (numpy PCG64)."""
     return np.random.default_rng(seed).uniform(-1.0, 1.0, size=shape)
+
+
+def _i64(c: int) -> int:
+    """An unsigned 64-bit constant as the int64 with the same bits."""
+    return c - (1 << 64) if c >= (1 << 63) else c
+
+
+def label_keyed_values_torch(seed: int, labels, k, v):
+    """``label_keyed_values`` with torch int64 tensors (any device); same values bit for bit.
+
+    uint64 arithmetic is done in int64: products wrap modulo 2^64 and a
+    logical right shift is an arithmetic shift with the sign-extended bits
+    masked off.  Returns float64 in [-1, 1).
+    """
+    import torch
+
+    def srl(x, s):
+        return (x >> s) & ((1 << (64 - s)) - 1)
+
+    def mix(z):
+        z = (z ^ srl(z, 30)) * _i64(int(_M1))
+        z = (z ^ srl(z, 27)) * _i64(int(_M2))
+        return z ^ srl(z, 31)
+
+    with np.errstate(over="ignore"):
+        h0 = int(mix64(np.uint64(seed) * _GAMMA + np.uint64(1)))
+    h = mix(torch.as_tensor(labels, dtype=torch.int64) ^ _i64(h0))
+    kv = torch.as_tensor(k, dtype=torch.int64) * (1 << 16) + torch.as_tensor(v, dtype=torch.int64) + 0x5A5A
+    h = mix(h ^ kv)
+    return srl(h, 11).to(torch.float64) * (2.0 ** -52) - 1.0
