@@ -45,18 +45,25 @@ WORKLOADS = {
 }
 
 
-def algorithmic_bytes(stats, D, n_reps, nvec, elem):
+def algorithmic_bytes(stats, D, n_reps, nvec, elem, pad=False, epilogue=False):
     """Bytes one H.V launch must move (no cache reuse credited).
 
-    per active connection: the gathered X rows (n_r * nvec * elem) + the 8-byte
-    entry + the 8-byte metadata word of the target; per connection with an
-    inactive target: the entry; per block row: read X once (diagonal) and
-    write Y; per active output representative: label, metadata, row pointer
-    and diagonal energy (32 bytes); per inactive one: its metadata word.
+    Per connection (flip of an active output representative): the stored
+    entry (stats["entry_bytes"]), and the target's 8-byte metadata word in the
+    block row layout, or in the padded layout its 2-byte stabilizer id when
+    the entry does not mark the stabilizer trivial (inactive targets never
+    have a trivial stabilizer); per active connection the gathered X rows
+    (n_Gamma(target) * nvec * elem).  Per block row: X read once (diagonal)
+    and Y written, plus the previous Lanczos vector read in the Lanczos
+    epilogue.  Per active output representative: label, metadata, row pointer
+    and diagonal energy (32 bytes); per inactive one its metadata word.
     """
-    act = stats["active_connections"]
-    inact = stats["connections"] - act
-    return (stats["gathered_rows"] * nvec * elem + 16 * act + 8 * inact + 2 * D * nvec * elem
+    conn = stats["connections"]
+    inact = conn - stats["active_connections"]
+    eb = stats.get("entry_bytes", 8)
+    target = 2 * (stats.get("nontrivial_targets", 0) + inact) if pad else 8 * conn
+    vec = (3 if epilogue else 2) * D * nvec * elem
+    return (stats["gathered_rows"] * nvec * elem + eb * conn + target + vec
             + 32 * stats["n_active"] + 8 * (n_reps - stats["n_active"]))
 
 
@@ -247,14 +254,15 @@ def main():
         S = P.Sector(cl, G, wl["two_M"], two_s=wl["two_s"])
         t1 = time.perf_counter()
         B = P.Block(S, wl["irrep"], 0)
-        a, b, n = B.ftlm(wl["R"], wl["steps"], seed, storage=storage, dist=dist, stream=stream)
+        a, b, n, info = B.ftlm(wl["R"], wl["steps"], seed, storage=storage, dist=dist, stream=stream, info=True)
         t2 = time.perf_counter()
         ths, ws = P.ritz_from_run(a, b, n)
         E, C, chi, lz = P.observables([dict(two_M=wl["two_M"], d_gamma=B.d_gamma, D=B.D, thetas=ths, weights=ws)], T)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         return dict(D=B.D, products=int(n.sum()), build=t1 - t0, lanczos=t2 - t1, thermo=t3 - t2, total=t3 - t0,
-                    E0=float(min(t.min() for t in ths)))
+                    E0=float(min(t.min() for t in ths)), hv_ms=info["hv_ms"], hv_launches=info["hv_launches"],
+                    layout=info["layout"], rows=info["rows"])
 
     if args.profile_hv:
         G0 = P.Group(cl.N, cl.gens)
@@ -265,17 +273,18 @@ def main():
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)                     # calibration: reads and writes 1 GiB
-        tdt = torch.float32 if storage == P.F32 else torch.float64
-        X = torch.randn((B0.D, wl["R"]), dtype=tdt, device=dev)
-        Y = torch.empty_like(X)
+        del src, dst
         torch.cuda.synchronize()
-        for _ in range(5):
-            B0.apply_H(X, Y, stream=stream)
+        # the H.V launches the counters see are those of 5 Lanczos steps
+        _, _, _, info = B0.ftlm(wl["R"], 5, 0x5EED0003, storage=storage, dist=dist, stream=stream, info=True)
         torch.cuda.synchronize()
         st = B0.hv_stats()
         elem = 4 if storage == P.F32 else 8
-        print(json.dumps({"copy_bytes": 1 << 30, "hv_launches": 5, "lanes_per_rep": tuned[0],
-                          "algorithmic_bytes_per_launch": algorithmic_bytes(st, B0.D, S0.n_reps, wl["R"], elem),
+        pad = info["layout"] == P.LAYOUT_PADDED
+        print(json.dumps({"copy_bytes": 1 << 30, "hv_launches": info["hv_launches"], "lanes_per_rep": tuned[0],
+                          "layout": "padded" if pad else "block",
+                          "algorithmic_bytes_per_launch": algorithmic_bytes(st, B0.D, S0.n_reps, wl["R"], elem,
+                                                                            pad=pad, epilogue=True),
                           "stats": st}), flush=True)
         return
 
@@ -315,8 +324,13 @@ def main():
     torch.cuda.synchronize()
     hv_ms = ev0.elapsed_time(ev1) / args.hv_reps
     stats = B.hv_stats()
-    balg = algorithmic_bytes(stats, B.D, S.n_reps, wl["R"], elem)
-    achieved = balg / (hv_ms * 1e-3) / 1e9
+    # roofline: the H.V launches of the timed Lanczos runs (HIP events on the run's stream)
+    pad = recs[0]["layout"] == P.LAYOUT_PADDED
+    lz_launches = sum(r["hv_launches"] for r in recs)
+    lz_hv_ms = sum(r["hv_ms"] for r in recs) / max(lz_launches, 1)
+    balg = algorithmic_bytes(stats, B.D, S.n_reps, wl["R"], elem, pad=pad, epilogue=True)
+    achieved = balg / (lz_hv_ms * 1e-3) / 1e9
+    balg_apply = algorithmic_bytes(stats, B.D, S.n_reps, wl["R"], elem)
     # plain single-vector FP64 H.V for the speedup figure
     del X, Y
     X1 = torch.randn((B.D, 1), dtype=torch.float64, device=dev)
@@ -360,12 +374,15 @@ def main():
                    "n_reps": int(S.n_reps), "group_order": B.group_order, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
-                     "kernel": "k_hv (entry-table mode)", "algorithmic_bytes_per_launch": balg,
-                     "avg_launch_ms": hv_ms, "nvec": wl["R"]},
+                     "kernel": "k_hv inside ftlm_run (entry-table mode, Lanczos epilogue, "
+                               + ("padded" if pad else "block") + " rows)",
+                     "algorithmic_bytes_per_launch": balg, "avg_launch_ms": lz_hv_ms, "launches": lz_launches,
+                     "nvec": wl["R"]},
         "cpu_baseline": cpu,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "breakdown_ms": {k: float(np.mean([r[k] for r in recs]) * 1e3) for k in ("build", "lanczos", "thermo")},
-        "hv": {"batched_elem_vec_per_s": B.D * wl["R"] / (hv_ms * 1e-3),
+        "hv": {"apply_H_ms": hv_ms, "apply_H_GBs": balg_apply / (hv_ms * 1e-3) / 1e9,
+               "batched_elem_vec_per_s": B.D * wl["R"] / (hv_ms * 1e-3),
                "single_fp64_elem_vec_per_s": B.D / (hv1_ms * 1e-3), "single_fp64_ms": hv1_ms,
                "connections": stats["connections"], "active_connections": stats["active_connections"]},
         "E0": recs[0]["E0"],

@@ -75,13 +75,31 @@ typedef struct ftlm_cluster {
 } ftlm_cluster;
 
 /* Build options (every field 0 / NULL = default). */
+/* Row layout of the Lanczos vectors that ftlm_run keeps on the device.
+ * BLOCK: the block's own rows (representative i at its offset, n_Gamma(i)
+ * rows).  PADDED: d_Gamma rows per representative (representative i at
+ * i * d_Gamma, rows k >= n_Gamma(i) held at zero), so the H.V finds a
+ * target's rows without reading its offset.  AUTO: PADDED when D >= 2^20 and
+ * the padding adds at most 2% rows, BLOCK otherwise.  The layout changes only
+ * the summation order of the FP64 reductions, not what is computed. */
+enum ftlm_layout { FTLM_LAYOUT_AUTO = 0, FTLM_LAYOUT_BLOCK = 1, FTLM_LAYOUT_PADDED = 2 };
+
+/* Storage of the sector's entry table (one entry per flip: target index,
+ * connecting element, flip id, trivial-target bit).  WIDE: 8 bytes.
+ * COMPACT: 6 bytes (u32 target + u16 rest), needs |G| and the flip count to
+ * fit 15 bits together; it saves memory but costs a second load per entry.
+ * AUTO: WIDE unless the wide table would take more than a quarter of the
+ * free device memory and COMPACT is possible. */
+enum ftlm_entry_format { FTLM_ENTRIES_AUTO = 0, FTLM_ENTRIES_WIDE = 1, FTLM_ENTRIES_COMPACT = 2 };
+
 typedef struct ftlm_opts {
   int32_t hv_mode;          /* enum ftlm_hv_mode; AUTO keeps an entry table when it fits */
-  int32_t reserved0;
+  int32_t lanczos_layout;   /* enum ftlm_layout: rows of the Lanczos vectors inside ftlm_run
+                               (block options; ignored by sector creation) */
   const double* user_rho;   /* optional irrep matrices, |G| x d x d row-major, element
                                order as above; replaces the library's own irrep */
   int32_t user_rho_dim;     /* d of user_rho (0 = none) */
-  int32_t reserved1;
+  int32_t entry_format;     /* enum ftlm_entry_format (sector creation) */
   int64_t hbm_limit_bytes;  /* 0 = no limit; builds that would exceed it fail with
                                FTLM_ERR_OUT_OF_MEMORY before allocating */
   int64_t reserved[6];
@@ -186,13 +204,18 @@ int ftlm_block_export(const ftlm_block* b, uint64_t* reps, uint16_t* stab_id, ui
 
 /* Work counts of one H.V on this block, for the algorithmic byte model:
  * connections of active output representatives (entries read), those whose
- * target representative is active in this irrep, and the rows gathered for
- * them (sum of n_Gamma(target)).  Device reduction, synchronous. */
+ * target representative is active in this irrep, the rows gathered for
+ * them (sum of n_Gamma(target)), how many of those targets have a
+ * non-trivial stabilizer, and the size of a stored entry.  Entry mode only
+ * (UNSUPPORTED otherwise).  Device reduction, synchronous. */
 typedef struct ftlm_hv_stats {
   uint64_t n_active;          /* output representatives with n_Gamma > 0 */
   uint64_t connections;       /* flips of active output representatives */
   uint64_t active_connections;
   uint64_t gathered_rows;
+  uint64_t nontrivial_targets; /* active connections whose target has a non-trivial stabilizer */
+  int32_t entry_bytes;        /* bytes per stored flip entry (6 or 8) */
+  int32_t reserved;
 } ftlm_hv_stats;
 int ftlm_block_hv_stats(const ftlm_block* b, ftlm_hv_stats* stats);
 
@@ -225,6 +248,21 @@ int ftlm_block_autotune(ftlm_block* b, int32_t nvec, int32_t dtype, void* stream
  * nsteps (R).  Synchronous.  Device scratch is allocated per call. */
 int ftlm_run(ftlm_block* b, int32_t R, int32_t steps, uint64_t seed, int32_t storage, int32_t dist,
              double* alpha, double* beta, int32_t* nsteps, void* stream);
+
+/* What one ftlm_run_ex call did: the vector layout (enum ftlm_layout, never
+ * AUTO), the rows of each stored vector, and the number and total duration
+ * of its H.V launches, measured with HIP events on the run's stream. */
+typedef struct ftlm_run_info {
+  int32_t layout;
+  int32_t hv_launches;
+  uint64_t rows;
+  double hv_ms;
+} ftlm_run_info;
+
+/* ftlm_run that also fills *info (may be NULL; then it is ftlm_run).
+ * Timing adds two event records per step. */
+int ftlm_run_ex(ftlm_block* b, int32_t R, int32_t steps, uint64_t seed, int32_t storage, int32_t dist,
+                double* alpha, double* beta, int32_t* nsteps, void* stream, ftlm_run_info* info);
 
 /* Host FP64: eigenvalues theta (ascending) and weights w_k = (first
  * eigenvector component)^2 of the n x n tridiagonal with diagonal alpha and

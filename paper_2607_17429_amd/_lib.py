@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(HERE, "libftlm.so")
 F64, F32 = 0, 1
 RADEMACHER, GAUSSIAN = 0, 1
 HV_AUTO, HV_ENTRIES, HV_ONTHEFLY = 0, 1, 2
+LAYOUT_AUTO, LAYOUT_BLOCK, LAYOUT_PADDED = 0, 1, 2
+ENTRIES_AUTO, ENTRIES_WIDE, ENTRIES_COMPACT = 0, 1, 2
 
 STATUS = {
     0: "OK", -1: "INVALID_ARG", -2: "NOT_A_PERMUTATION", -3: "GROUP_TOO_LARGE",
@@ -39,9 +41,9 @@ class Cluster(C.Structure):
 
 
 class Opts(C.Structure):
-    _fields_ = [("hv_mode", C.c_int32), ("reserved0", C.c_int32),
+    _fields_ = [("hv_mode", C.c_int32), ("lanczos_layout", C.c_int32),
                 ("user_rho", C.POINTER(C.c_double)), ("user_rho_dim", C.c_int32),
-                ("reserved1", C.c_int32), ("hbm_limit_bytes", C.c_int64),
+                ("entry_format", C.c_int32), ("hbm_limit_bytes", C.c_int64),
                 ("reserved", C.c_int64 * 6)]
 
 
@@ -59,7 +61,12 @@ class BlockInfo(C.Structure):
 
 class HvStats(C.Structure):
     _fields_ = [("n_active", C.c_uint64), ("connections", C.c_uint64), ("active_connections", C.c_uint64),
-                ("gathered_rows", C.c_uint64)]
+                ("gathered_rows", C.c_uint64), ("nontrivial_targets", C.c_uint64), ("entry_bytes", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class RunInfo(C.Structure):
+    _fields_ = [("layout", C.c_int32), ("hv_launches", C.c_int32), ("rows", C.c_uint64), ("hv_ms", C.c_double)]
 
 
 class JobDesc(C.Structure):
@@ -107,6 +114,8 @@ SIGNATURES = {
     "ftlm_apply_H": (C.c_int, [VP, VP, VP, C.c_int32, C.c_int64, C.c_int32, VP]),
     "ftlm_block_autotune": (C.c_int, [VP, C.c_int32, C.c_int32, VP, I32P, F64P, I32P, F64P, I32P]),
     "ftlm_run": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, F64P, F64P, I32P, VP]),
+    "ftlm_run_ex": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, F64P, F64P, I32P, VP,
+                              C.POINTER(RunInfo)]),
     "ftlm_tridiag_ritz": (C.c_int, [F64P, F64P, C.c_int32, F64P, F64P]),
     "ftlm_observables": (C.c_int, [C.POINTER(Ritz), C.c_int32, F64P, C.c_int32, C.c_double, F64P, F64P, F64P, F64P]),
     "ftlm_block_free": (None, [VP]),
@@ -160,9 +169,11 @@ def make_cluster(N, two_s, bonds, J=None):
     return cl
 
 
-def make_opts(hv_mode=HV_AUTO, user_rho=None, hbm_limit=0):
+def make_opts(hv_mode=HV_AUTO, user_rho=None, hbm_limit=0, layout=0, entry_format=0):
     o = Opts()
     o.hv_mode = hv_mode
+    o.entry_format = int(entry_format)
+    o.lanczos_layout = int(layout)
     o.hbm_limit_bytes = int(hbm_limit)
     if user_rho is not None:
         rho = np.ascontiguousarray(np.asarray(user_rho, dtype=np.float64))

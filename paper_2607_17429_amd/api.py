@@ -57,12 +57,12 @@ class Group:
 class Sector:
     """Irrep-independent tables of one M sector (built on the GPU)."""
 
-    def __init__(self, cluster, group: Group, two_M, hv_mode=HV_AUTO, hbm_limit=0, two_s=None):
+    def __init__(self, cluster, group: Group, two_M, hv_mode=HV_AUTO, hbm_limit=0, two_s=None, entry_format=0):
         cl = L.make_cluster(cluster.N, two_s if two_s is not None else cluster.two_s, cluster.bonds, cluster.J) \
             if not isinstance(cluster, L.Cluster) else cluster
         self._cl = cl
         self.group = group
-        opts = L.make_opts(hv_mode=hv_mode, hbm_limit=hbm_limit)
+        opts = L.make_opts(hv_mode=hv_mode, hbm_limit=hbm_limit, entry_format=entry_format)
         h = C.c_void_p()
         check(lib().ftlm_sector_create(C.byref(cl), group._h, int(two_M), C.byref(opts), C.byref(h)))
         self._h = h
@@ -103,9 +103,9 @@ class Sector:
 class Block:
     """One (M, Gamma, row) block; owns device tables, shares the sector's."""
 
-    def __init__(self, sector: Sector, irrep, row=0, user_rho=None, hbm_limit=0):
+    def __init__(self, sector: Sector, irrep, row=0, user_rho=None, hbm_limit=0, layout=0):
         self.sector = sector
-        opts = L.make_opts(user_rho=user_rho, hbm_limit=hbm_limit)
+        opts = L.make_opts(user_rho=user_rho, hbm_limit=hbm_limit, layout=layout)
         h = C.c_void_p()
         check(lib().ftlm_block_create(sector._h, int(irrep), int(row), C.byref(opts), C.byref(h)))
         self._h = h
@@ -185,14 +185,20 @@ class Block:
                                  X.stride(0), dtype, L.stream_handle(stream)))
         return Y
 
-    def ftlm(self, R, steps, seed, storage=F64, dist=RADEMACHER, stream=None):
-        """Batched Lanczos: returns alpha, beta (R x steps) and nsteps (R)."""
+    def ftlm(self, R, steps, seed, storage=F64, dist=RADEMACHER, stream=None, info=False):
+        """Batched Lanczos: returns alpha, beta (R x steps) and nsteps (R).
+
+        With info=True also a dict (layout, hv_launches, rows, hv_ms) from ftlm_run_ex."""
         alpha = np.zeros((R, steps))
         beta = np.zeros((R, steps))
         ns = np.zeros(R, np.int32)
-        check(lib().ftlm_run(self._h, int(R), int(steps), C.c_uint64(seed), int(storage), int(dist),
-                             alpha.ctypes.data_as(L.F64P), beta.ctypes.data_as(L.F64P), ns.ctypes.data_as(L.I32P),
-                             L.stream_handle(stream) if stream is not None else None))
+        ri = L.RunInfo()
+        check(lib().ftlm_run_ex(self._h, int(R), int(steps), C.c_uint64(seed), int(storage), int(dist),
+                                alpha.ctypes.data_as(L.F64P), beta.ctypes.data_as(L.F64P), ns.ctypes.data_as(L.I32P),
+                                L.stream_handle(stream) if stream is not None else None,
+                                C.byref(ri) if info else None))
+        if info:
+            return alpha, beta, ns, {f: getattr(ri, f) for f, _ in L.RunInfo._fields_}
         return alpha, beta, ns
 
 

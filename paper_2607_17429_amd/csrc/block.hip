@@ -75,10 +75,10 @@ double check_user_rho(const Group& G, const double* rho, int d) {
 
 __global__ void __launch_bounds__(256) k_hv_stats(const uint64_t* __restrict__ meta, const uint64_t* __restrict__ row_ptr,
                                                  const uint64_t* __restrict__ entries, const uint32_t* __restrict__ eidx,
-                                                 const uint8_t* __restrict__ n_stab, uint64_t n,
+                                                 const uint8_t* __restrict__ n_stab, uint64_t n, unsigned triv_sid,
                                                  unsigned long long* __restrict__ out) {
-  __shared__ unsigned long long red[4][256];
-  unsigned long long c = 0, ca = 0, rows = 0, act = 0;
+  __shared__ unsigned long long red[5][256];
+  unsigned long long c = 0, ca = 0, rows = 0, act = 0, nt = 0;
   for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (uint64_t)gridDim.x * blockDim.x) {
     if (n_stab[meta[p] >> 48] == 0) continue;
     ++act;
@@ -86,10 +86,12 @@ __global__ void __launch_bounds__(256) k_hv_stats(const uint64_t* __restrict__ m
       const uint64_t idx = eidx ? (uint64_t)eidx[e] : (entries[e] & 0xffffffffull);
       ++c;
       if (idx == 0xffffffffull) continue;
-      const unsigned nr = n_stab[meta[idx] >> 48];
+      const unsigned sr = (unsigned)(meta[idx] >> 48);
+      const unsigned nr = n_stab[sr];
       if (nr) {
         ++ca;
         rows += nr;
+        nt += sr != triv_sid ? 1 : 0;
       }
     }
   }
@@ -97,13 +99,14 @@ __global__ void __launch_bounds__(256) k_hv_stats(const uint64_t* __restrict__ m
   red[1][threadIdx.x] = c;
   red[2][threadIdx.x] = ca;
   red[3][threadIdx.x] = rows;
+  red[4][threadIdx.x] = nt;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if ((int)threadIdx.x < off)
-      for (int q = 0; q < 4; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + off];
+      for (int q = 0; q < 5; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x < 4) atomicAdd(&out[threadIdx.x], red[threadIdx.x][0]);
+  if (threadIdx.x < 5) atomicAdd(&out[threadIdx.x], red[threadIdx.x][0]);
 }
 
 }  // namespace
@@ -116,19 +119,21 @@ void block_hv_stats(const Block& b, ftlm_hv_stats* res) {
   DevBuf<uint8_t> d_n;
   d_n.upload(b.n_stab);
   DevBuf<unsigned long long> out;
-  out.alloc(4);
+  out.alloc(5);
   hipStream_t st = tl_alloc_stream;
   FTLM_HIP(hipMemsetAsync(out.p, 0, out.bytes(), st));
   hipLaunchKernelGGL(k_hv_stats, dim3(grid1(s.n_reps)), dim3(256), 0, st, b.d_meta.p, s.d_row_ptr.p,
-                     s.d_entries.p, s.d_eidx.p, d_n.p, s.n_reps, out.p);
+                     s.d_entries.p, s.d_eidx.p, d_n.p, s.n_reps, (unsigned)s.trivial_sid, out.p);
   FTLM_HIP(hipGetLastError());
-  unsigned long long h[4];
+  unsigned long long h[5];
   FTLM_HIP(hipMemcpyAsync(h, out.p, sizeof(h), hipMemcpyDeviceToHost, st));
   FTLM_HIP(hipStreamSynchronize(st));
   res->n_active = h[0];
   res->connections = h[1];
   res->active_connections = h[2];
   res->gathered_rows = h[3];
+  res->nontrivial_targets = h[4];
+  res->entry_bytes = s.entry_bytes;
 }
 
 std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int row, const ftlm_opts* opts) {
@@ -139,6 +144,11 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
   B->irrep = irrep;
   B->row = row;
   const int n = G.order;
+  if (opts) {
+    if (opts->lanczos_layout < FTLM_LAYOUT_AUTO || opts->lanczos_layout > FTLM_LAYOUT_PADDED)
+      fail(FTLM_ERR_INVALID_ARG, "lanczos_layout must be AUTO, BLOCK or PADDED");
+    B->lanczos_layout = opts->lanczos_layout;
+  }
   if (opts && opts->user_rho && opts->user_rho_dim > 0) {
     const int d = opts->user_rho_dim;
     if (d > 12) fail(FTLM_ERR_DIM_GT_12, "irrep dimension above 12");
@@ -217,6 +227,7 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
     scan_exclusive_u64(off.p, off.p, sec->n_reps + 1, &D, st);
     if (D >= (1ull << 48)) fail(FTLM_ERR_UNSUPPORTED, "block dimension above 2^48");
     B->D = D;
+    B->D_pad = sec->n_reps * (uint64_t)B->dg;
     B->d_meta.alloc(sec->n_reps);
     hipLaunchKernelGGL(k_meta, dim3(grid1(sec->n_reps)), dim3(256), 0, st, off.p, sec->d_stab_id.p, sec->n_reps,
                        B->d_meta.p);

@@ -253,6 +253,15 @@ int ftlm_run(ftlm_block* b, int32_t R, int32_t steps, uint64_t seed, int32_t sto
   });
 }
 
+int ftlm_run_ex(ftlm_block* b, int32_t R, int32_t steps, uint64_t seed, int32_t storage, int32_t dist, double* alpha,
+                double* beta, int32_t* nsteps, void* stream, ftlm_run_info* info) {
+  return guarded([&] {
+    if (!b) fail(FTLM_ERR_INVALID_ARG, "null block");
+    if (info) std::memset(info, 0, sizeof(*info));
+    run_lanczos(*b->b, R, steps, seed, storage, dist, alpha, beta, nsteps, (hipStream_t)stream, info);
+  });
+}
+
 int ftlm_tridiag_ritz(const double* alpha, const double* beta, int32_t n, double* theta, double* weight) {
   return guarded([&] {
     if (n < 0 || n > 4096) fail(FTLM_ERR_INVALID_ARG, "n must be in 0..4096");

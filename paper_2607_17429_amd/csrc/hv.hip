@@ -150,7 +150,7 @@ std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dt
 }
 
 void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t st,
-                 const LanczosEpilogue* lz, int gl) {
+                 const LanczosEpilogue* lz, int gl, bool pad) {
   const Sector& s = *b.sec;
   if (nvec <= 0 || ld < nvec) fail(FTLM_ERR_INVALID_ARG, "need 0 < nvec <= ld");
   if (b.D == 0 || s.n_reps == 0) return;
@@ -200,6 +200,10 @@ void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
     a.eidx = s.d_eidx.p;
     a.ehc = s.d_ehc.p;
     a.hbits = s.ent_hbits;
+    a.pad = pad ? 1 : 0;
+    a.dstride = b.dg;
+    a.triv_sid = s.trivial_sid;
+    a.sid = s.d_stab_id.p;
     a.meta = b.d_meta.p;
     a.ediag = s.d_ediag.p;
     a.rhoT = b.d_rhoT64.p;

@@ -62,6 +62,11 @@ struct HvArgs {
   const uint32_t* eidx;      // the 6-byte split form (eidx != nullptr)
   const uint16_t* ehc;
   int hbits;
+  // vector layout: pad == 0: block rows (representative i at meta offset);
+  // pad != 0: padded rows, representative i at i * dstride (= d_Gamma), and a
+  // target's stabilizer id comes from the entry's trivial bit or sid[]
+  int pad, dstride, triv_sid;
+  const uint16_t* sid;
   const uint64_t* meta;
   const double* ediag;
   const double* rhoT;   // [g][beta][gamma], stride DG
@@ -174,7 +179,7 @@ k_hv(HvArgs<T> a) {
     const int sp = (int)(mp >> 48);
     const int np_ = (int)stabf[4 * sp];
     if (np_ == 0) continue;
-    const uint64_t offp = mp & kOffMask;
+    const uint64_t offp = a.pad ? p * (uint64_t)a.dstride : (mp & kOffMask);
     const W plab = (W)a.reps[p];
     double acc[DG][VPL];
 #pragma unroll
@@ -192,7 +197,7 @@ k_hv(HvArgs<T> a) {
           if (a.eidx) {
             const uint32_t hc = a.ehc[e + lg];
             my = (uint64_t)a.eidx[e + lg] | ((uint64_t)(hc & ((1u << a.hbits) - 1)) << 32) |
-                 ((uint64_t)(hc >> a.hbits) << 48);
+                 ((uint64_t)((hc & 0x7fffu) >> a.hbits) << 48) | ((uint64_t)(hc >> 15) << 63);
           } else {
             my = a.entries[e + lg];
           }
@@ -217,7 +222,15 @@ k_hv(HvArgs<T> a) {
           my = idx | ((uint64_t)h << 32) | ((uint64_t)cand << 48);
       }
       const uint32_t myidx = (uint32_t)(my & 0xffffffffu);
-      const uint64_t mm = myidx != kInvalid ? a.meta[myidx] : 0;
+      uint64_t mm = 0;
+      if (myidx != kInvalid) {
+        if (a.pad) {
+          const uint64_t sr = (my >> 63) ? (uint64_t)a.triv_sid : (uint64_t)a.sid[myidx];
+          mm = (uint64_t)myidx * (uint64_t)a.dstride | (sr << 48);
+        } else {
+          mm = a.meta[myidx];
+        }
+      }
       const int cnt = (int)min((uint64_t)GL, e_end - e);
 
 #pragma unroll 1
@@ -244,7 +257,7 @@ k_hv(HvArgs<T> a) {
             xv[q][j] = use ? val : T(0);
           }
         const int h = (int)((ent >> 32) & 0xffff);
-        const int cand = (int)(ent >> 48);
+        const int cand = (int)((ent >> 48) & 0x7fff);
         const int bond = cand >> 1;
         const int ai = dev::digit(plab, bonds[2 * bond], a.b, lmask);
         const int aj = dev::digit(plab, bonds[2 * bond + 1], a.b, lmask);

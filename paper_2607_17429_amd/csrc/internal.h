@@ -47,13 +47,15 @@ struct Sector {
   DevBuf<uint16_t> d_stab_id;
   DevBuf<double> d_ediag;       // Eq. (16) per representative
   DevBuf<uint64_t> d_row_ptr;   // entries of representative i: [row_ptr[i], row_ptr[i+1])
-  // entries of a flip: target index, connecting element h, flip id 2*bond + sign;
-  // 8-byte form idx | h << 32 | flip << 48, or the 6-byte split form
-  // (eidx = idx, ehc = h | flip << ent_hbits) when h and flip fit 16 bits
+  // entries of a flip: target index, connecting element h, flip id 2*bond + sign,
+  // and a bit set when the target's stabilizer is trivial; 8-byte form
+  // idx | h << 32 | flip << 48 | trivial << 63, or the 6-byte split form
+  // (eidx = idx, ehc = h | flip << ent_hbits | trivial << 15) when h and flip fit 15 bits
   DevBuf<uint64_t> d_entries;
   DevBuf<uint32_t> d_eidx;
   DevBuf<uint16_t> d_ehc;
   int entry_bytes = 8, ent_hbits = 16;
+  int trivial_sid = 0;          // stabilizer id of the trivial stabilizer {e}
   uint64_t n_entries = 0;
   DevBuf<int32_t> d_bonds;
   DevBuf<double> d_J;
@@ -72,6 +74,8 @@ struct Block {
   int irrep = 0, row = 0, dg = 0;
   int dgp = 0;                  // kernel dimension bucket (tables zero-padded to it)
   uint64_t D = 0, n_active = 0;
+  uint64_t D_pad = 0;           // n_reps * dg: rows of the padded vector layout
+  int lanczos_layout = FTLM_LAYOUT_AUTO;
   std::vector<double> rho;      // |G| x d x d (the irrep used)
   std::vector<uint8_t> n_stab;  // n_Gamma per stabilizer id
   std::vector<double> V_stab;   // per stabilizer: d x d (columns k < n valid, rest 0)
@@ -111,8 +115,9 @@ void apply_hv(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int 
 // or default), the partial-sum groups of that layout, and H.V with it fixed.
 int hv_layout_lanes(const Block& b, int nvec, int dtype);
 int hv_partial_groups(const Block& b, int nvec, int gl);
+// pad: X and Y use the padded row layout (representative i at i * d_Gamma).
 void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t stream,
-                 const LanczosEpilogue* lz, int gl);
+                 const LanczosEpilogue* lz, int gl, bool pad = false);
 // Times every lane layout for (nvec, dtype) on this block, caches the fastest
 // process-wide and returns (lanes per representative, ms per launch) pairs.
 std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dtype, hipStream_t st, int reps);
@@ -126,6 +131,11 @@ struct LanczosRun {
   int R, steps, storage, dist;
   uint64_t seed;
   int target = 0, TB = 0, nb_vec = 0, gl = 0, ng_hv = 0;
+  bool pad = false;              // padded vector rows (FTLM_LAYOUT_PADDED)
+  uint64_t rows = 0;             // rows of each stored vector
+  // optional timing of the H.V launches (two events per step)
+  std::vector<hipEvent_t> hv_events;
+  bool timed = false;
   DevBuf<uint8_t> q0, q1, chain;
   DevBuf<uint64_t> keys;
   DevBuf<double> partials, inv_norm, scal, d_alpha, d_beta;
@@ -137,11 +147,14 @@ struct LanczosRun {
   void enqueue_begin(hipStream_t st);                  // clear outputs, start vectors
   void enqueue_steps(hipStream_t st, int j0, int j1);  // Lanczos steps j0 <= j < min(j1, target)
   void enqueue_end(hipStream_t st);                    // per-chain step counts
+  void enable_timing();
+  double hv_ms() const;          // after the stream has finished
+  ~LanczosRun();
   void download(hipStream_t st, double* alpha, double* beta, int32_t* nsteps);
 };
 
 void run_lanczos(Block& b, int R, int steps, uint64_t seed, int storage, int dist, double* alpha,
-                 double* beta, int32_t* nsteps, hipStream_t stream);
+                 double* beta, int32_t* nsteps, hipStream_t stream, ftlm_run_info* info = nullptr);
 
 void tridiag_ritz(const double* alpha, const double* beta, int n, double* theta, double* weight);
 void observables(const ftlm_ritz* blocks, int nb, const double* T, int nT, double g, double* E, double* C,

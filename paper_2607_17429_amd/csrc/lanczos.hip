@@ -51,16 +51,28 @@ __device__ __forceinline__ double start_value(uint64_t key, uint64_t j, int dist
 // threads per block, so each thread's elements belong to one chain and the
 // per-chain block sums are reduced in a fixed order.
 template <typename T>
+// Padded layout (meta != nullptr): stored row i * dstride + k is block row
+// offset(i) + k for k < n_Gamma(i) and zero otherwise; D counts stored rows.
 __global__ void __launch_bounds__(256) k_start(const uint64_t* __restrict__ keys, int dist, uint64_t D, int R,
                                               const double* __restrict__ inv_norm, T* __restrict__ Q,
-                                              double* __restrict__ partials) {
+                                              double* __restrict__ partials, const uint64_t* __restrict__ meta,
+                                              const double* __restrict__ stabf, int dstride) {
   __shared__ double red[256];
   const int t = threadIdx.x;
   const int RB = blockDim.x / R;
   const int v = t % R, r0 = t / R;
   double acc = 0.0;
   for (uint64_t row = (uint64_t)blockIdx.x * RB + r0; row < D; row += (uint64_t)gridDim.x * RB) {
-    const double x = start_value(keys[v], row, dist);
+    uint64_t brow = row;
+    bool live = true;
+    if (meta) {
+      const uint64_t i = row / (uint64_t)dstride;
+      const int k = (int)(row - i * (uint64_t)dstride);
+      const uint64_t m = meta[i];
+      live = k < (int)stabf[4 * (m >> 48)];
+      brow = (m & ((1ull << 48) - 1)) + (uint64_t)k;
+    }
+    const double x = live ? start_value(keys[v], brow, dist) : 0.0;
     if (inv_norm) {
       const T q = (T)(x * inv_norm[v]);
       Q[row * R + v] = q;
@@ -203,7 +215,7 @@ unsigned blocks_for(uint64_t rows, int RB) {
 template <typename T>
 void enqueue_begin_typed(LanczosRun& L, hipStream_t st) {
   const int R = L.R;
-  const uint64_t D = L.block->D;
+  const uint64_t D = L.rows;
   T* q0 = (T*)L.q0.p;
   Chain* ch = (Chain*)L.chain.p;
   FTLM_HIP(hipMemsetAsync(L.d_alpha.p, 0, L.d_alpha.bytes(), st));
@@ -211,11 +223,14 @@ void enqueue_begin_typed(LanczosRun& L, hipStream_t st) {
   FTLM_HIP(hipMemsetAsync(L.d_n.p, 0, L.d_n.bytes(), st));
   if (L.target == 0) return;
   // start vectors: norm of the FP64 draw, then the stored, normalised q_0 and its norm
+  const uint64_t* meta = L.pad ? L.block->d_meta.p : nullptr;
+  const double* stabf = L.block->d_stabf64.p;
+  const int dstride = L.block->dg;
   hipLaunchKernelGGL((k_start<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, L.keys.p, L.dist, D, R, (const double*)nullptr,
-                     q0, L.partials.p);
+                     q0, L.partials.p, meta, stabf, dstride);
   hipLaunchKernelGGL(k_init_chain, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, L.inv_norm.p, ch, 0);
   hipLaunchKernelGGL((k_start<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, L.keys.p, L.dist, D, R, L.inv_norm.p, q0,
-                     L.partials.p);
+                     L.partials.p, meta, stabf, dstride);
   hipLaunchKernelGGL(k_init_chain, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, L.inv_norm.p, ch, 1);
   FTLM_HIP(hipMemsetAsync(L.q1.p, 0, L.q1.bytes(), st));
   hipLaunchKernelGGL(k_scal, dim3((R + 63) / 64), dim3(64), 0, st, ch, R, L.scal.p);
@@ -228,14 +243,16 @@ template <typename T>
 void enqueue_steps_typed(LanczosRun& L, hipStream_t st, int j0, int j1) {
   const Block& b = *L.block;
   const int R = L.R, steps = L.steps;
-  const uint64_t D = b.D;
+  const uint64_t D = L.rows;
   Chain* ch = (Chain*)L.chain.p;
   const int dtype = sizeof(T) == 8 ? FTLM_F64 : FTLM_F32;
   for (int j = j0; j < j1; ++j) {
     T* qj = (T*)((j & 1) ? L.q1.p : L.q0.p);
     T* qprev = (T*)((j & 1) ? L.q0.p : L.q1.p);
     LanczosEpilogue lz{L.scal.p, L.partials.p, L.ng_hv};
-    apply_hv_gl(b, qj, qprev, R, R, dtype, st, &lz, L.gl);  // qprev <- w
+    if (L.timed) FTLM_HIP(hipEventRecord(L.hv_events[2 * j], st));
+    apply_hv_gl(b, qj, qprev, R, R, dtype, st, &lz, L.gl, L.pad);  // qprev <- w
+    if (L.timed) FTLM_HIP(hipEventRecord(L.hv_events[2 * j + 1], st));
     hipLaunchKernelGGL(k_alpha, dim3(R), dim3(256), 0, st, L.partials.p, L.ng_hv, R, ch, L.d_alpha.p, j, steps);
     hipLaunchKernelGGL((k_update<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, ch, D, R, qj, qprev, L.partials.p);
     hipLaunchKernelGGL(k_beta, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, ch, L.d_alpha.p, L.d_beta.p,
@@ -266,8 +283,14 @@ LanczosRun::LanczosRun(const Block& b, int R_, int steps_, uint64_t seed_, int s
   if (storage != FTLM_F64 && storage != FTLM_F32) fail(FTLM_ERR_INVALID_ARG, "storage must be FTLM_F64 or FTLM_F32");
   const uint64_t D = b.D;
   target = (int)std::min<uint64_t>((uint64_t)steps, D);
+  if (b.lanczos_layout == FTLM_LAYOUT_PADDED)
+    pad = true;
+  else if (b.lanczos_layout == FTLM_LAYOUT_AUTO)
+    pad = D >= (1ull << 20) && (double)b.D_pad <= 1.02 * (double)D;
+  if (pad && b.D_pad >= (1ull << 48)) fail(FTLM_ERR_UNSUPPORTED, "padded rows above 2^48");
+  rows = pad ? b.D_pad : D;
   TB = R * (256 / R);
-  nb_vec = (int)blocks_for(std::max<uint64_t>(D, 1), TB / R);
+  nb_vec = (int)blocks_for(std::max<uint64_t>(rows, 1), TB / R);
   // one lane layout for the whole run (the partial-sum buffer is sized for it)
   gl = hv_layout_lanes(b, R, storage);
   ng_hv = D ? hv_partial_groups(b, R, gl) : 1;
@@ -275,14 +298,35 @@ LanczosRun::LanczosRun(const Block& b, int R_, int steps_, uint64_t seed_, int s
 
 size_t LanczosRun::estimate_bytes(const Block& b, int R, int steps, int storage) {
   const size_t elem = storage == FTLM_F64 ? 8 : 4;
-  return 2 * (size_t)b.D * R * elem + (size_t)8192 * R * 8 + (size_t)R * steps * 16 + (size_t)R * 128;
+  const uint64_t rows = std::max(b.D, b.lanczos_layout == FTLM_LAYOUT_BLOCK ? b.D : b.D_pad);
+  return 2 * (size_t)rows * R * elem + (size_t)8192 * R * 8 + (size_t)R * steps * 16 + (size_t)R * 128;
+}
+
+void LanczosRun::enable_timing() {
+  timed = true;
+  hv_events.assign(2 * (size_t)std::max(target, 0), nullptr);
+  for (auto& e : hv_events) FTLM_HIP(hipEventCreate(&e));
+}
+
+double LanczosRun::hv_ms() const {
+  double t = 0.0;
+  for (size_t j = 0; j + 1 < hv_events.size(); j += 2) {
+    float ms = 0.f;
+    FTLM_HIP(hipEventElapsedTime(&ms, hv_events[j], hv_events[j + 1]));
+    t += ms;
+  }
+  return t;
+}
+
+LanczosRun::~LanczosRun() {
+  for (auto& e : hv_events)
+    if (e) (void)hipEventDestroy(e);
 }
 
 void LanczosRun::allocate() {
   const size_t elem = storage == FTLM_F64 ? 8 : 4;
-  const uint64_t D = block->D;
-  q0.alloc(std::max<uint64_t>(D, 1) * R * elem);
-  q1.alloc(std::max<uint64_t>(D, 1) * R * elem);
+  q0.alloc(std::max<uint64_t>(rows, 1) * R * elem);
+  q1.alloc(std::max<uint64_t>(rows, 1) * R * elem);
   std::vector<uint64_t> hkeys(R);
   for (int v = 0; v < R; ++v) hkeys[v] = chain_key(seed, block->sec->two_M, block->irrep, block->row, v);
   keys.upload(hkeys);
@@ -331,14 +375,21 @@ void LanczosRun::download(hipStream_t st, double* alpha, double* beta, int32_t* 
 }
 
 void run_lanczos(Block& b, int R, int steps, uint64_t seed, int storage, int dist, double* alpha, double* beta,
-                 int32_t* nsteps, hipStream_t st) {
+                 int32_t* nsteps, hipStream_t st, ftlm_run_info* info) {
   if (!alpha || !beta || !nsteps) fail(FTLM_ERR_INVALID_ARG, "null output");
   LanczosRun L(b, R, steps, seed, storage, dist);
   AllocStreamScope scope(st ? st : tl_alloc_stream);  // stream-ordered scratch: no device-wide sync on free
+  if (info) L.enable_timing();
   L.allocate();
   L.enqueue(st);
   L.download(st, alpha, beta, nsteps);
   FTLM_HIP(hipStreamSynchronize(st));
+  if (info) {
+    info->layout = L.pad ? FTLM_LAYOUT_PADDED : FTLM_LAYOUT_BLOCK;
+    info->rows = L.rows;
+    info->hv_launches = L.target;
+    info->hv_ms = L.hv_ms();
+  }
 }
 
 }  // namespace ftlm

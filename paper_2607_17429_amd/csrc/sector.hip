@@ -182,9 +182,22 @@ __global__ void __launch_bounds__(kThreads) k_stab_mask(SecArgs a, const uint64_
   }
 }
 
-__global__ void k_first_trivial(const uint64_t* __restrict__ pos, uint64_t n, unsigned long long* out) {
+__global__ void __launch_bounds__(kThreads) k_first_trivial(const uint64_t* __restrict__ pos, uint64_t n,
+                                                           unsigned long long* out) {
+  __shared__ unsigned long long red[kThreads];
+  unsigned long long best = ~0ull;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
-    if (pos[i + 1] == pos[i]) atomicMin(out, (unsigned long long)i);
+    if (pos[i + 1] == pos[i]) {
+      best = i;
+      break;  // later i of this lane are larger
+    }
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] = min(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] != ~0ull) atomicMin(out, red[0]);
 }
 
 __global__ void k_assign_stab(const uint64_t* __restrict__ pos, uint64_t n, const uint16_t* __restrict__ ids_nt,
@@ -268,7 +281,8 @@ __global__ void __launch_bounds__(kThreads) k_entry_fill(SecArgs a, FlipArgs f, 
                                                         const uint32_t* __restrict__ base,
                                                         uint64_t* __restrict__ entries,
                                                         uint32_t* __restrict__ eidx, uint16_t* __restrict__ ehc,
-                                                        int hbits) {
+                                                        int hbits, const uint16_t* __restrict__ stab_id,
+                                                        uint16_t triv_sid) {
   extern __shared__ uint64_t smem_raw[];
   const W* tab = stage_table<W, LDS>((const W*)a.tab, a.tab_words, (W*)smem_raw);
   const dev::OrbitTabs<W, NCH> o = dev::orbit_tabs<W, NCH>(tab, a.nH, a.nT);
@@ -291,12 +305,16 @@ __global__ void __launch_bounds__(kThreads) k_entry_fill(SecArgs a, FlipArgs f, 
         uint64_t idx = 0;
         bool ok = lookup<W>(r, a, bits, base, idx);
         // a canonical label of the sector is always a representative
+        // top bit: the target's stabilizer is trivial (its n_Gamma, L and V
+        // are then known without reading its stabilizer id)
+        const bool triv = ok && stab_id[idx] == triv_sid;
         if (eidx) {
           eidx[out] = ok ? (uint32_t)idx : 0xFFFFFFFFu;
-          ehc[out] = (uint16_t)(h | (cur << hbits));
+          ehc[out] = (uint16_t)(h | (cur << hbits) | (triv ? 0x8000 : 0));
           ++out;
         } else {
-          entries[out++] = (ok ? idx : 0xFFFFFFFFull) | ((uint64_t)h << 32) | ((uint64_t)cur << 48);
+          entries[out++] = (ok ? idx : 0xFFFFFFFFull) | ((uint64_t)h << 32) | ((uint64_t)cur << 48) |
+                           (triv ? (1ull << 63) : 0ull);
         }
         cur = next_admissible<W>(p, cur, ncand, f, a.b, a.d, mask);
       }
@@ -620,6 +638,7 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
       ids_nt[q] = intern(m);
     }
     if (!trivial_done) trivial_id = intern(trivial_mask);
+    s.trivial_sid = trivial_id;
     s.n_stab = (int32_t)ids.size();
     DevBuf<uint16_t> d_ids;
     d_ids.upload(ids_nt);
@@ -642,14 +661,25 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
   uint64_t n_ent = 0;
   scan_exclusive_u64(s.d_row_ptr.p, s.d_row_ptr.p, s.n_reps + 1, &n_ent, st);
   s.n_entries = n_ent;
-  // Entry format: 6 bytes (u32 target index + u16 holding h and the flip id)
-  // when both fit in 16 bits, 8 bytes (one u64) otherwise.
+  // Entry format: 6 bytes (u32 target index + u16 holding h, the flip id and
+  // the trivial-target bit) when they fit in 16 bits, 8 bytes (one u64:
+  // idx | h << 32 | flip << 48 | trivial << 63) otherwise.
   {
     int hb = 1, cb = 1;
     while ((1 << hb) < G_) ++hb;
     while ((1 << cb) < 2 * s.nbonds) ++cb;
     s.ent_hbits = hb;
-    s.entry_bytes = hb + cb <= 16 ? 6 : 8;
+    const bool compact_ok = hb + cb <= 15;
+    const int fmt = opts ? opts->entry_format : FTLM_ENTRIES_AUTO;
+    if (fmt < FTLM_ENTRIES_AUTO || fmt > FTLM_ENTRIES_COMPACT) fail(FTLM_ERR_INVALID_ARG, "bad entry_format");
+    if (fmt == FTLM_ENTRIES_COMPACT && !compact_ok)
+      fail(FTLM_ERR_UNSUPPORTED, "compact entries need |G| and the flip count to fit 15 bits");
+    size_t free_b = 0, total_b = 0;
+    FTLM_HIP(hipMemGetInfo(&free_b, &total_b));
+    if (fmt == FTLM_ENTRIES_AUTO)
+      s.entry_bytes = (compact_ok && (double)n_ent * 8.0 > (double)free_b / 4.0) ? 6 : 8;
+    else
+      s.entry_bytes = fmt == FTLM_ENTRIES_COMPACT ? 6 : 8;
   }
   int mode = opts ? opts->hv_mode : FTLM_HV_AUTO;
   if (mode == FTLM_HV_AUTO) {
@@ -672,11 +702,11 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
       if (lds)
         hipLaunchKernelGGL((k_entry_fill<W, NCH, true>), dim3(grid_for(s.n_reps)), dim3(kThreads), shm, st, a, f,
                            s.d_reps.p, s.d_row_ptr.p, s.d_rank_bits.p, s.d_rank_base.p, s.d_entries.p, s.d_eidx.p,
-                           s.d_ehc.p, s.ent_hbits);
+                           s.d_ehc.p, s.ent_hbits, s.d_stab_id.p, (uint16_t)s.trivial_sid);
       else
         hipLaunchKernelGGL((k_entry_fill<W, NCH, false>), dim3(grid_for(s.n_reps)), dim3(kThreads), 0, st, a, f,
                            s.d_reps.p, s.d_row_ptr.p, s.d_rank_bits.p, s.d_rank_base.p, s.d_entries.p, s.d_eidx.p,
-                           s.d_ehc.p, s.ent_hbits);
+                           s.d_ehc.p, s.ent_hbits, s.d_stab_id.p, (uint16_t)s.trivial_sid);
     });
     FTLM_HIP(hipGetLastError());
   }

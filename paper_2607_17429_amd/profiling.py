@@ -21,7 +21,9 @@ import json
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-HV_SOURCES = ("csrc/hv_kernel.h", "csrc/hv.hip")
+# sources that decide what the H.V kernel reads: the kernel, its launch, the
+# entry table format and the Lanczos driver that calls it
+HV_SOURCES = ("csrc/hv_kernel.h", "csrc/hv.hip", "csrc/sector.hip", "csrc/lanczos.hip")
 
 
 def hv_source_sha() -> str:
@@ -43,6 +45,25 @@ def kernel_stats_markdown(stats_csv: str, top: int = 14) -> str:
         out.append(f"| `{name}` | {r['Calls']} | {float(r['AverageNs']) / 1e6:.3f} | "
                    f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.2f} |")
     return "\n".join(out)
+
+
+def lanczos_hv(trace_csv: str):
+    """(count, avg ms, kernel name) of the H.V dispatches made by ftlm_run: those
+    that the Lanczos alpha reduction follows on the same queue."""
+    rows = list(csv.DictReader(open(trace_csv)))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    by_q = {}
+    for r in rows:
+        by_q.setdefault(r["Queue_Id"], []).append(r)
+    picked = []
+    for q in by_q.values():
+        for a, b in zip(q, q[1:]):
+            if "k_hv<" in a["Kernel_Name"] and "k_alpha" in b["Kernel_Name"]:
+                picked.append(a)
+    if not picked:
+        return 0, None, None
+    ms = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in picked) / len(picked) / 1e6
+    return len(picked), ms, picked[0]["Kernel_Name"]
 
 
 def _dispatches(path):
@@ -79,6 +100,7 @@ def main():
     ap.add_argument("--out", default="profiles")
     ap.add_argument("--cmd", default="")
     ap.add_argument("--bench-json", default=None, help="bench.py output line, for the algorithmic bytes")
+    ap.add_argument("--trace", default=None, help="kernel_trace.csv of the trace run (H.V launches inside ftlm_run)")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     tr = counter_traffic(args.fetch, args.write)
@@ -94,8 +116,14 @@ def main():
     md = [f"# k_hv on {args.workload}: rocprofv3 summary", "",
           "Commands (from the repository root of the GPU box):", "", "```", args.cmd, "```", "",
           "## Kernel trace statistics (one bench step, `bench.py --steps 1 --warmup 0 --no-cpu-baseline`)", "",
-          kernel_stats_markdown(args.stats), "",
-          "## HBM traffic of one H.V launch (`bench.py --profile-hv`)", "",
+          kernel_stats_markdown(args.stats), ""]
+    if args.trace:
+        n, ms, name = lanczos_hv(args.trace)
+        if n:
+            md += [f"H.V launches inside `ftlm_run` (each followed by `k_alpha` on its queue): {n}, "
+                   f"average {ms:.3f} ms (`{name[:90]}`).", ""]
+    md += [
+          "## HBM traffic of one H.V launch inside `ftlm_run` (`bench.py --profile-hv`)", "",
           "| counter | raw KiB / launch | calibration (1 GiB copy) raw KiB | scale | bytes / launch |",
           "|---|---:|---:|---:|---:|"]
     for k in ("FETCH_SIZE", "WRITE_SIZE"):

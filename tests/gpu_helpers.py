@@ -48,19 +48,20 @@ def lib_group(name):
     return _lib_groups[name]
 
 
-def lib_sector(name, two_s, two_M, hv_mode=0):
+def lib_sector(name, two_s, two_M, hv_mode=0, entry_format=0):
     import paper_2607_17429_amd as P
-    key = (name, two_s, two_M, hv_mode)
+    key = (name, two_s, two_M, hv_mode, entry_format)
     if key not in _lib_sectors:
         cl = clusters.get(name)
-        _lib_sectors[key] = P.Sector(cl, lib_group(name), two_M, hv_mode=hv_mode, two_s=two_s)
+        _lib_sectors[key] = P.Sector(cl, lib_group(name), two_M, hv_mode=hv_mode, two_s=two_s,
+                                     entry_format=entry_format)
     return _lib_sectors[key]
 
 
-def lib_block(name, two_s, two_M, gi, row=0, hv_mode=0):
+def lib_block(name, two_s, two_M, gi, row=0, hv_mode=0, entry_format=0):
     import paper_2607_17429_amd as P
     _, _, irs = oracle_group(name)
-    return P.Block(lib_sector(name, two_s, two_M, hv_mode), gi, row, user_rho=irs[gi].rho)
+    return P.Block(lib_sector(name, two_s, two_M, hv_mode, entry_format), gi, row, user_rho=irs[gi].rho)
 
 
 def rel_err_cols(Y, Yref):

@@ -12,6 +12,7 @@ import pytest
 from gpu_helpers import lib_block, log, oracle_block, oracle_group, oracle_sector
 from oracle import ftlm as oftlm
 from oracle import hv
+from synth import clusters
 
 pytestmark = pytest.mark.gpu
 
@@ -96,3 +97,54 @@ def test_observables_icosahedron_all_sectors(storage, tol):
     E2, C2, chi2, lz2 = P.observables(lib_blocks, np.array([1e9]))
     assert abs(np.exp(lz2[0]) / 2 ** 12 - 1) < 1e-6
     assert abs(1e9 * chi2[0] / (12 * 0.75 / 3) - 1) < 1e-6
+
+
+def test_padded_layout_against_oracle_and_block_layout():
+    """The padded vector layout (d_Gamma rows per representative, read without
+    the target's row offset) gives the oracle's coefficients; forced on a
+    block where it adds padding rows, with FP64 and FP32 storage."""
+    name, two_s, two_M, gi = "dodecahedron", 1, 0, 8
+    log("[lanczos] padded layout")
+    sec, H = oracle_sector(name, two_s, two_M)
+    B = oracle_block(name, two_s, two_M, gi)
+    Hb = (B.Psi.T @ H @ B.Psi).tocsr()
+    _, _, irs = oracle_group(name)
+    S = lib_block(name, two_s, two_M, gi).sector
+    LP = P.Block(S, gi, 0, user_rho=irs[gi].rho, layout=P.LAYOUT_PADDED)
+    LB = P.Block(S, gi, 0, user_rho=irs[gi].rho, layout=P.LAYOUT_BLOCK)
+    assert S.n_reps * 5 > LP.D          # the padded layout has zero rows here
+    a, b, n, info = LP.ftlm(3, 40, 99, storage=P.F64, info=True)
+    assert info["layout"] == P.LAYOUT_PADDED and info["rows"] == S.n_reps * 5 and info["hv_launches"] == 40
+    assert info["hv_ms"] > 0
+    for r in range(3):
+        v0 = oftlm.start_vector(B.D, 99, two_M, gi, 0, r, "rademacher")
+        oa, ob = oftlm.lanczos(lambda x: Hb @ x, v0, 40)
+        assert np.max(np.abs(a[r, :15] - oa[:15])) < 1e-10 * np.max(np.abs(oa))
+        assert np.max(np.abs(b[r, :15] - ob[:15])) < 1e-10 * np.max(np.abs(ob))
+    a1, b1, n1, info1 = LB.ftlm(3, 40, 99, storage=P.F64, info=True)
+    assert info1["layout"] == P.LAYOUT_BLOCK and info1["rows"] == LB.D
+    assert np.max(np.abs(a[:, :15] - a1[:, :15])) < 1e-12 * np.max(np.abs(a1))
+    # FP32 storage: the stored rows are the same numbers, only FP64 reduction order differs
+    a32, b32, _ = LP.ftlm(3, 30, 7, storage=P.F32)
+    a32b, b32b, _ = LB.ftlm(3, 30, 7, storage=P.F32)
+    assert np.max(np.abs(a32[:, :15] - a32b[:, :15])) < 1e-6 * np.max(np.abs(a32b))
+    assert np.max(np.abs(b32[:, :15] - b32b[:, :15])) < 1e-6 * np.max(np.abs(b32b))
+
+
+@pytest.mark.timeout(600)
+def test_auto_layout_at_scale_matches_block_layout():
+    """On the icosidodecahedron H_g block (D = 6,465,762) AUTO picks the padded
+    layout (0.16% extra rows); its FP64 coefficients agree with the block
+    layout's over the first steps."""
+    log("[lanczos] auto layout at scale")
+    cl = clusters.get("icosidodecahedron")
+    G = P.Group(cl.N, cl.gens)
+    S = P.Sector(cl, G, 0, two_s=1)
+    BA = P.Block(S, 8, 0)
+    BB = P.Block(S, 8, 0, layout=P.LAYOUT_BLOCK)
+    a, b, n, info = BA.ftlm(4, 20, 3, storage=P.F64, info=True)
+    assert info["layout"] == P.LAYOUT_PADDED and info["rows"] == 1295266 * 5
+    a1, b1, n1, info1 = BB.ftlm(4, 20, 3, storage=P.F64, info=True)
+    assert info1["layout"] == P.LAYOUT_BLOCK and info1["rows"] == 6465762
+    assert np.max(np.abs(a - a1)) < 1e-11 * np.max(np.abs(a1))
+    assert np.max(np.abs(b - b1)) < 1e-11 * np.max(np.abs(b1))

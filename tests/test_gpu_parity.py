@@ -103,6 +103,14 @@ def test_hv_batched_fp32_and_modes(name, two_s, two_M, gi):
     LB = lib_block(name, two_s, two_M, gi)
     LO = lib_block(name, two_s, two_M, gi, hv_mode=P.HV_ONTHEFLY)
     assert LO.hv_mode == P.HV_ONTHEFLY and LB.hv_mode == P.HV_ENTRIES
+    assert LB.hv_stats()["entry_bytes"] == 8
+    # compact 6-byte entries (when |G| and the flip ids fit 15 bits): same flips, same order
+    try:
+        LC = lib_block(name, two_s, two_M, gi, entry_format=P.ENTRIES_COMPACT)
+        assert LC.hv_stats()["entry_bytes"] == 6
+    except P.FtlmError as e:
+        assert e.name == "UNSUPPORTED" and name == "square6x6", e
+        LC = None
     rng = np.random.default_rng(5)
     # the on-the-fly kernel keeps the irrep matrices in LDS (48 KiB for the
     # small tables); larger ones (8x8 matrices of a group of order 288) are
@@ -112,6 +120,8 @@ def test_hv_batched_fp32_and_modes(name, two_s, two_M, gi):
         X = rng.standard_normal((B.D, nvec))
         Xt = torch.from_numpy(X).cuda()
         Y = LB.apply_H(Xt)
+        if LC is not None:
+            assert torch.equal(LC.apply_H(Xt), Y)
         if otf_fits:
             Yo = LO.apply_H(Xt)
             assert torch.equal(Y, Yo)                    # same flips, same order
