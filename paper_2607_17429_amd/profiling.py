@@ -134,7 +134,7 @@ def main():
     if balg:
         md += ["", f"Algorithmic bytes per launch (byte model): {balg / 1e9:.3f} GB; "
                    f"measured / algorithmic = {total / balg:.3f}."]
-    md += ["", f"Kernel source hash (hv_kernel.h + hv.hip): `{rec['source_sha']}`", ""]
+    md += ["", f"Kernel source hash ({' + '.join(os.path.basename(p) for p in HV_SOURCES)}): `{rec['source_sha']}`", ""]
     with open(os.path.join(args.out, f"k_hv_{args.workload}.md"), "w") as f:
         f.write("\n".join(md))
     print(json.dumps({"traffic_bytes_per_launch": total, "algorithmic": balg}))
