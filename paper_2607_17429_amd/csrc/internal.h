@@ -136,6 +136,10 @@ struct LanczosRun {
   // optional timing of the H.V launches (two events per step)
   std::vector<hipEvent_t> hv_events;
   bool timed = false;
+  // replayable graph of an even and an odd step (captured on first use)
+  bool use_graphs = true;
+  hipGraph_t pair_graph = nullptr;
+  hipGraphExec_t pair_exec = nullptr;
   DevBuf<uint8_t> q0, q1, chain;
   DevBuf<uint64_t> keys;
   DevBuf<double> partials, inv_norm, scal, d_alpha, d_beta;

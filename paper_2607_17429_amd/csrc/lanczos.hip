@@ -33,6 +33,8 @@ struct Chain {
   double ca;      // alpha_j * s_j (update coefficient)
   int n;          // products done
   int done;
+  int step;       // index j of the next step (the kernels of a step read it
+                  // here, so one captured graph serves every step)
 };
 
 __device__ __forceinline__ double start_value(uint64_t key, uint64_t j, int dist) {
@@ -145,6 +147,7 @@ __global__ void __launch_bounds__(256) k_init_chain(const double* __restrict__ p
       c.ca = 0.0;
       c.n = 0;
       c.done = 0;
+      c.step = 0;
       ch[v] = c;
     }
   }
@@ -159,11 +162,12 @@ __global__ void k_scal(const Chain* __restrict__ ch, int R, double* __restrict__
 }
 
 __global__ void __launch_bounds__(256) k_alpha(const double* __restrict__ partials, int ngroups, int R, Chain* __restrict__ ch,
-                                              double* __restrict__ alpha, int j, int steps) {
+                                              double* __restrict__ alpha, int steps) {
   const int v = blockIdx.x;
   const double s = block_sum(partials, ngroups, R, v);
   if (threadIdx.x == 0) {
     Chain c = ch[v];
+    const int j = c.step;
     const double a = c.s * s;
     c.ca = a * c.s;
     if (!c.done) alpha[(size_t)v * steps + j] = a;
@@ -173,11 +177,13 @@ __global__ void __launch_bounds__(256) k_alpha(const double* __restrict__ partia
 
 __global__ void __launch_bounds__(256) k_beta(const double* __restrict__ partials, int ngroups, int R, Chain* __restrict__ ch,
                                              const double* __restrict__ alpha, double* __restrict__ beta,
-                                             double* __restrict__ scal, int j, int steps, int target) {
+                                             double* __restrict__ scal, int steps, int target) {
   const int v = blockIdx.x;
   const double s2 = block_sum(partials, ngroups, R, v);
   if (threadIdx.x == 0) {
     Chain c = ch[v];
+    const int j = c.step;
+    c.step = j + 1;
     if (!c.done) {
       const double b = sqrt(s2);
       beta[(size_t)v * steps + j] = b;
@@ -237,28 +243,57 @@ void enqueue_begin_typed(LanczosRun& L, hipStream_t st) {
   FTLM_HIP(hipGetLastError());
 }
 
-// Steps j0 <= j < j1: q_j lives in q0 for even j and in q1 for odd j; the
-// other buffer holds q_{j-1} and receives w.
+// One Lanczos step j: q_j lives in q0 for even j and in q1 for odd j; the
+// other buffer holds q_{j-1} and receives w.  The kernels take j from the
+// chain state, so the enqueue depends only on the parity of j.
 template <typename T>
-void enqueue_steps_typed(LanczosRun& L, hipStream_t st, int j0, int j1) {
+void enqueue_one_step(LanczosRun& L, hipStream_t st, bool odd, int timed_j) {
   const Block& b = *L.block;
   const int R = L.R, steps = L.steps;
   const uint64_t D = L.rows;
   Chain* ch = (Chain*)L.chain.p;
   const int dtype = sizeof(T) == 8 ? FTLM_F64 : FTLM_F32;
-  for (int j = j0; j < j1; ++j) {
-    T* qj = (T*)((j & 1) ? L.q1.p : L.q0.p);
-    T* qprev = (T*)((j & 1) ? L.q0.p : L.q1.p);
-    LanczosEpilogue lz{L.scal.p, L.partials.p, L.ng_hv};
-    if (L.timed) FTLM_HIP(hipEventRecord(L.hv_events[2 * j], st));
-    apply_hv_gl(b, qj, qprev, R, R, dtype, st, &lz, L.gl, L.pad);  // qprev <- w
-    if (L.timed) FTLM_HIP(hipEventRecord(L.hv_events[2 * j + 1], st));
-    hipLaunchKernelGGL(k_alpha, dim3(R), dim3(256), 0, st, L.partials.p, L.ng_hv, R, ch, L.d_alpha.p, j, steps);
-    hipLaunchKernelGGL((k_update<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, ch, D, R, qj, qprev, L.partials.p);
-    hipLaunchKernelGGL(k_beta, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, ch, L.d_alpha.p, L.d_beta.p,
-                       L.scal.p, j, steps, L.target);
-    FTLM_HIP(hipGetLastError());
+  T* qj = (T*)(odd ? L.q1.p : L.q0.p);
+  T* qprev = (T*)(odd ? L.q0.p : L.q1.p);
+  LanczosEpilogue lz{L.scal.p, L.partials.p, L.ng_hv};
+  if (timed_j >= 0) FTLM_HIP(hipEventRecord(L.hv_events[2 * timed_j], st));
+  apply_hv_gl(b, qj, qprev, R, R, dtype, st, &lz, L.gl, L.pad);  // qprev <- w
+  if (timed_j >= 0) FTLM_HIP(hipEventRecord(L.hv_events[2 * timed_j + 1], st));
+  hipLaunchKernelGGL(k_alpha, dim3(R), dim3(256), 0, st, L.partials.p, L.ng_hv, R, ch, L.d_alpha.p, steps);
+  hipLaunchKernelGGL((k_update<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, ch, D, R, qj, qprev, L.partials.p);
+  hipLaunchKernelGGL(k_beta, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, ch, L.d_alpha.p, L.d_beta.p,
+                     L.scal.p, steps, L.target);
+  FTLM_HIP(hipGetLastError());
+}
+
+// Steps j0 <= j < j1.  On a capturable stream, pairs of steps starting at an
+// even j replay one captured graph of an even and an odd step; otherwise (the
+// null stream, timing requested, or a lone step) the kernels are enqueued
+// directly.  Both orders are the same kernels with the same arguments.
+template <typename T>
+void enqueue_steps_typed(LanczosRun& L, hipStream_t st, int j0, int j1) {
+  int j = j0;
+  const bool graphs = L.use_graphs && st != nullptr && !L.timed;
+  if (j < j1 && (j & 1)) enqueue_one_step<T>(L, st, true, L.timed ? j : -1), ++j;
+  if (graphs && j + 1 < j1) {
+    if (!L.pair_exec) {
+      hipGraph_t g = nullptr;
+      FTLM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      try {
+        enqueue_one_step<T>(L, st, false, -1);
+        enqueue_one_step<T>(L, st, true, -1);
+      } catch (...) {
+        (void)hipStreamEndCapture(st, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      FTLM_HIP(hipStreamEndCapture(st, &g));
+      L.pair_graph = g;
+      FTLM_HIP(hipGraphInstantiate(&L.pair_exec, g, nullptr, nullptr, 0));
+    }
+    for (; j + 1 < j1; j += 2) FTLM_HIP(hipGraphLaunch(L.pair_exec, st));
   }
+  for (; j < j1; ++j) enqueue_one_step<T>(L, st, (j & 1) != 0, L.timed ? j : -1);
 }
 
 }  // namespace
@@ -321,6 +356,8 @@ double LanczosRun::hv_ms() const {
 LanczosRun::~LanczosRun() {
   for (auto& e : hv_events)
     if (e) (void)hipEventDestroy(e);
+  if (pair_exec) (void)hipGraphExecDestroy(pair_exec);
+  if (pair_graph) (void)hipGraphDestroy(pair_graph);
 }
 
 void LanczosRun::allocate() {

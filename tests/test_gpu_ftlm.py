@@ -148,3 +148,25 @@ def test_auto_layout_at_scale_matches_block_layout():
     assert info1["layout"] == P.LAYOUT_BLOCK and info1["rows"] == 6465762
     assert np.max(np.abs(a - a1)) < 1e-11 * np.max(np.abs(a1))
     assert np.max(np.abs(b - b1)) < 1e-11 * np.max(np.abs(b1))
+
+
+def test_graph_replayed_steps_equal_direct_launches():
+    """On a non-default stream the Lanczos steps run as replays of one captured
+    two-step graph; on the default stream (and when timing is requested) the
+    kernels are launched directly.  Every graph run, with other device work and
+    synchronizations between them, gives the direct run's coefficients bit for bit."""
+    log("[lanczos] graph replays")
+    s = torch.cuda.Stream()
+    for name, two_s, two_M, gi, R, steps, st in (("dodecahedron", 1, 0, 8, 5, 41, P.F64),
+                                                 ("icosahedron", 1, 0, 8, 3, 30, P.F32),
+                                                 ("cuboctahedron", 3, 2, 7, 4, 37, P.F32)):
+        LB = lib_block(name, two_s, two_M, gi)
+        a0, b0, n0 = LB.ftlm(R, steps, 123, storage=st)                      # default stream: direct
+        a1, b1, n1, info = LB.ftlm(R, steps, 123, storage=st, stream=s, info=True)  # timed: direct
+        assert np.array_equal(a0, a1) and np.array_equal(b0, b1)
+        for rep in range(3):
+            a2, b2, n2 = LB.ftlm(R, steps, 123, storage=st, stream=s)          # graph replays
+            assert np.array_equal(n0, n2) and np.array_equal(a0, a2) and np.array_equal(b0, b2), (name, rep)
+            X = torch.randn((LB.D, 3), dtype=torch.float64, device="cuda")
+            LB.apply_H(X)                                                    # other work in between
+            torch.cuda.synchronize()
