@@ -164,6 +164,8 @@ k_hv(HvArgs<T> a) {
   bool vok[VPL];
 #pragma unroll
   for (int j = 0; j < VPL; ++j) vok[j] = vbase + j * GL < a.nvec;
+  // uniform: the whole launch may gather without clamps (see the gather below)
+  const bool dense = a.pad && a.dstride == DG && a.nvec == a.tile_w * (int)gridDim.y && a.tile_w == GL * VPL;
   const int slots_per_wave = 64 >> a.log2GL;
   const int waves = blockDim.x >> 6;
   const uint64_t slot = ((uint64_t)blockIdx.x * waves + (threadIdx.x >> 6)) * slots_per_wave + (lane >> a.log2GL);
@@ -247,15 +249,25 @@ k_hv(HvArgs<T> a) {
         // and a select zeroes those values, so all loads of the flip are in
         // flight together instead of each waiting inside its own branch.
         T xv[DG][VPL];
+        if (dense) {
+          // padded rows with d_Gamma == DG and every column in range: rows
+          // k >= n_r of a target are stored zeros, so no clamp or select
+          const T* xr = a.X + offr * (uint64_t)a.ld + vbase;
 #pragma unroll
-        for (int q = 0; q < DG; ++q)
+          for (int q = 0; q < DG; ++q)
 #pragma unroll
-          for (int j = 0; j < VPL; ++j) {
-            const bool use = vok[j] && q < nr;
-            const uint64_t at = (offr + (q < nr ? q : 0)) * a.ld + (vok[j] ? vbase + j * GL : 0);
-            const T val = a.X[at];
-            xv[q][j] = use ? val : T(0);
-          }
+            for (int j = 0; j < VPL; ++j) xv[q][j] = xr[q * a.ld + j * GL];
+        } else {
+#pragma unroll
+          for (int q = 0; q < DG; ++q)
+#pragma unroll
+            for (int j = 0; j < VPL; ++j) {
+              const bool use = vok[j] && q < nr;
+              const uint64_t at = (offr + (q < nr ? q : 0)) * a.ld + (vok[j] ? vbase + j * GL : 0);
+              const T val = a.X[at];
+              xv[q][j] = use ? val : T(0);
+            }
+        }
         const int h = (int)((ent >> 32) & 0xffff);
         const int cand = (int)((ent >> 48) & 0x7fff);
         const int bond = cand >> 1;
