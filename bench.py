@@ -38,6 +38,16 @@ WORKLOADS = {
                                 desc="s=3/2 Heisenberg dodecahedron (N=20, 30 bonds, 40-bit labels), I_h, M=0 "
                                      "(D_M=86,981,744,944), irrep H_g row 1 (D=3,624,380,734); R=2 Rademacher chains, "
                                      "60 Lanczos steps, FP32 storage, FP64 reductions"),
+    "icosidodecahedron_Hg_f16": dict(cluster="icosidodecahedron", two_s=1, two_M=0, irrep=8, R=24, steps=60,
+                                     dist="gaussian", storage="f16",
+                                     desc="s=1/2 Heisenberg icosidodecahedron (N=30, 60 bonds), I_h, M=0, irrep H_g "
+                                          "row 1 (D=6,465,762); R=24 Gaussian chains, 60 Lanczos steps, FP16 storage "
+                                          "with a per-chain power-of-two scale, FP64 arithmetic and reductions"),
+    "dodecahedron_s32_Hg_f16": dict(cluster="dodecahedron", two_s=3, two_M=0, irrep=8, R=2, steps=60,
+                                    dist="rademacher", storage="f16",
+                                    desc="s=3/2 Heisenberg dodecahedron (N=20, 30 bonds, 40-bit labels), I_h, M=0, "
+                                         "irrep H_g row 1 (D=3,624,380,734); R=2 Rademacher chains, 60 Lanczos steps, "
+                                         "FP16 storage with a per-chain power-of-two scale, FP64 arithmetic"),
     "dodecahedron_Hg": dict(cluster="dodecahedron", two_s=1, two_M=0, irrep=8, R=24, steps=60, dist="rademacher",
                             storage="f64",
                             desc="s=1/2 dodecahedron (N=20), I_h, M=0, irrep H_g (D=7,800); R=24 Rademacher, "
@@ -241,7 +251,7 @@ def main():
 
     wl = WORKLOADS[args.workload]
     cl = clusters.get(wl["cluster"])
-    storage = P.F32 if wl["storage"] == "f32" else P.F64
+    storage = {"f64": P.F64, "f32": P.F32, "f16": P.F16}[wl["storage"]]
     dist = P.GAUSSIAN if wl["dist"] == "gaussian" else P.RADEMACHER
     T = np.geomspace(0.05, 10, 50)
     dev = torch.device("cuda:0")
@@ -279,7 +289,7 @@ def main():
         _, _, _, info = B0.ftlm(wl["R"], 5, 0x5EED0003, storage=storage, dist=dist, stream=stream, info=True)
         torch.cuda.synchronize()
         st = B0.hv_stats()
-        elem = 4 if storage == P.F32 else 8
+        elem = {P.F64: 8, P.F32: 4, P.F16: 2}[storage]
         pad = info["layout"] == P.LAYOUT_PADDED
         print(json.dumps({"copy_bytes": 1 << 30, "hv_launches": info["hv_launches"], "lanes_per_rep": tuned[0],
                           "layout": "padded" if pad else "block",
@@ -310,8 +320,8 @@ def main():
     G = P.Group(cl.N, cl.gens)
     S = P.Sector(cl, G, wl["two_M"], two_s=wl["two_s"])
     B = P.Block(S, wl["irrep"], 0)
-    tdt = torch.float32 if storage == P.F32 else torch.float64
-    elem = 4 if storage == P.F32 else 8
+    tdt = {P.F64: torch.float64, P.F32: torch.float32, P.F16: torch.float16}[storage]
+    elem = {P.F64: 8, P.F32: 4, P.F16: 2}[storage]
     X = torch.randn((B.D, wl["R"]), dtype=tdt, device=dev)
     Y = torch.empty_like(X)
     for _ in range(3):

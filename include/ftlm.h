@@ -60,7 +60,11 @@ enum ftlm_status {
   FTLM_ERR_QUEUE_FULL = -15
 };
 
-enum ftlm_dtype { FTLM_F64 = 0, FTLM_F32 = 1 };
+/* Storage type of vectors.  Arithmetic is FP64 for every storage type: F32
+ * and F16 values are widened when read and rounded once when stored.  In
+ * ftlm_run, F16 vectors carry a per-chain power-of-two scale that keeps their
+ * elements of order one (FP16 normals start at 6.1e-5). */
+enum ftlm_dtype { FTLM_F64 = 0, FTLM_F32 = 1, FTLM_F16 = 2 };
 enum ftlm_dist { FTLM_RADEMACHER = 0, FTLM_GAUSSIAN = 1 };
 enum ftlm_hv_mode { FTLM_HV_AUTO = 0, FTLM_HV_ENTRIES = 1, FTLM_HV_ONTHEFLY = 2 };
 

@@ -13,7 +13,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libftlm.so")
 
-F64, F32 = 0, 1
+F64, F32, F16 = 0, 1, 2
 RADEMACHER, GAUSSIAN = 0, 1
 HV_AUTO, HV_ENTRIES, HV_ONTHEFLY = 0, 1, 2
 LAYOUT_AUTO, LAYOUT_BLOCK, LAYOUT_PADDED = 0, 1, 2

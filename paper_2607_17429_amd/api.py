@@ -10,7 +10,7 @@ import ctypes as C
 import numpy as np
 
 from . import _lib as L
-from ._lib import F32, F64, GAUSSIAN, HV_AUTO, HV_ENTRIES, HV_ONTHEFLY, RADEMACHER, FtlmError, check, lib
+from ._lib import F16, F32, F64, GAUSSIAN, HV_AUTO, HV_ENTRIES, HV_ONTHEFLY, RADEMACHER, FtlmError, check, lib
 
 
 class Group:
@@ -171,15 +171,15 @@ class Block:
         return best.value, best_ms.value, dict(zip(tried[: n.value].tolist(), tried_ms[: n.value].tolist()))
 
     def apply_H(self, X, Y=None, stream=None):
-        """Y = H X for a (D, nvec) torch CUDA tensor (float64 or float32)."""
+        """Y = H X for a (D, nvec) torch CUDA tensor (float64, float32 or float16 storage)."""
         import torch
         if X.dim() == 1:
             X = X[:, None]
         assert X.shape[0] == self.D and X.is_cuda
         if Y is None:
             Y = torch.empty_like(X)
-        dtype = F64 if X.dtype == torch.float64 else F32
-        assert X.dtype in (torch.float64, torch.float32) and Y.dtype == X.dtype
+        dtype = {torch.float64: F64, torch.float32: F32, torch.float16: F16}[X.dtype]
+        assert Y.dtype == X.dtype
         assert X.stride(1) == 1 and Y.stride(1) == 1 and X.stride(0) == Y.stride(0)
         check(lib().ftlm_apply_H(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), X.shape[1],
                                  X.stride(0), dtype, L.stream_handle(stream)))

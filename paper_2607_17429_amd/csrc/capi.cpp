@@ -229,7 +229,7 @@ int ftlm_block_autotune(ftlm_block* b, int32_t nvec, int32_t dtype, void* stream
   return guarded([&] {
     if (!b) fail(FTLM_ERR_INVALID_ARG, "null block");
     if (nvec <= 0 || nvec > 4096) fail(FTLM_ERR_INVALID_ARG, "nvec must be in 1..4096");
-    if (dtype != FTLM_F64 && dtype != FTLM_F32) fail(FTLM_ERR_INVALID_ARG, "bad dtype");
+    if (dtype != FTLM_F64 && dtype != FTLM_F32 && dtype != FTLM_F16) fail(FTLM_ERR_INVALID_ARG, "bad dtype");
     auto res = autotune_hv(*b->b, nvec, dtype, (hipStream_t)stream, 5);
     int bi = -1;
     for (size_t i = 0; i < res.size(); ++i)

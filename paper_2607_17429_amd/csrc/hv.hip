@@ -114,7 +114,7 @@ void apply_hv(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int 
 std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dtype, hipStream_t st, int reps) {
   std::vector<std::pair<int, double>> out;
   if (b.D == 0 || b.sec->n_reps == 0) return out;
-  const size_t elem = dtype == FTLM_F64 ? 8 : 4;
+  const size_t elem = dtype == FTLM_F64 ? 8 : dtype == FTLM_F32 ? 4 : 2;
   DevBuf<uint8_t> X, Y;
   X.alloc((size_t)b.D * nvec * elem);
   Y.alloc((size_t)b.D * nvec * elem);
@@ -246,8 +246,10 @@ void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
   };
   HvArgs<double> a64{};
   HvArgs<float> a32{};
+  HvArgs<_Float16> a16{};
   const HvArgs<double>* p64 = nullptr;
   const HvArgs<float>* p32 = nullptr;
+  const HvArgs<_Float16>* p16 = nullptr;
   if (dtype == FTLM_F64) {
     fill(a64);
     a64.X = (const double*)X;
@@ -258,18 +260,23 @@ void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
     a32.X = (const float*)X;
     a32.Y = (float*)Y;
     p32 = &a32;
+  } else if (dtype == FTLM_F16) {
+    fill(a16);
+    a16.X = (const _Float16*)X;
+    a16.Y = (_Float16*)Y;
+    p16 = &a16;
   } else {
-    fail(FTLM_ERR_INVALID_ARG, "dtype must be FTLM_F64 or FTLM_F32");
+    fail(FTLM_ERR_INVALID_ARG, "dtype must be FTLM_F64, FTLM_F32 or FTLM_F16");
   }
   switch (b.dgp) {
-    case 1: launch_dg<1>(p64, p32, c, st); break;
-    case 2: launch_dg<2>(p64, p32, c, st); break;
-    case 3: launch_dg<3>(p64, p32, c, st); break;
-    case 4: launch_dg<4>(p64, p32, c, st); break;
-    case 5: launch_dg<5>(p64, p32, c, st); break;
-    case 6: launch_dg<6>(p64, p32, c, st); break;
-    case 8: launch_dg<8>(p64, p32, c, st); break;
-    case 12: launch_dg<12>(p64, p32, c, st); break;
+    case 1: launch_dg<1>(p64, p32, p16, c, st); break;
+    case 2: launch_dg<2>(p64, p32, p16, c, st); break;
+    case 3: launch_dg<3>(p64, p32, p16, c, st); break;
+    case 4: launch_dg<4>(p64, p32, p16, c, st); break;
+    case 5: launch_dg<5>(p64, p32, p16, c, st); break;
+    case 6: launch_dg<6>(p64, p32, p16, c, st); break;
+    case 8: launch_dg<8>(p64, p32, p16, c, st); break;
+    case 12: launch_dg<12>(p64, p32, p16, c, st); break;
     default: fail(FTLM_ERR_DIM_GT_12, "irrep dimension above 12");
   }
   FTLM_HIP(hipGetLastError());

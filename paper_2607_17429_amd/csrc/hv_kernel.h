@@ -21,7 +21,7 @@
 // fetched with one load per lane and exchanged by lane shuffles, then each
 // flip's n_r rows of X[r] are gathered for all VPL vectors.  rho^T, V_S, the
 // stabilizer data and the bond coefficients sit in LDS when they fit.
-// Arithmetic is FP64; FP32 storage rounds once on the store.
+// Arithmetic is FP64; FP32 and FP16 storage round once on the store.
 //
 // Flips come from the sector's entry table (target index, h, flip id; built
 // once per sector and shared by all irreps) or are found on the fly (flip,
@@ -416,16 +416,19 @@ void launch_t(const HvArgs<T>& a, const LaunchCfg& c, hipStream_t st) {
 
 // one instantiation unit per irrep dimension bucket
 template <int DG>
-void launch_dg(const HvArgs<double>* a64, const HvArgs<float>* a32, const LaunchCfg& c, hipStream_t st);
+void launch_dg(const HvArgs<double>* a64, const HvArgs<float>* a32, const HvArgs<_Float16>* a16,
+               const LaunchCfg& c, hipStream_t st);
 
 #define FTLM_HV_INSTANTIATE(DGV)                                                                     \
   template <>                                                                                       \
-  void launch_dg<DGV>(const HvArgs<double>* a64, const HvArgs<float>* a32, const LaunchCfg& c,    \
-                      hipStream_t st) {                                                             \
+  void launch_dg<DGV>(const HvArgs<double>* a64, const HvArgs<float>* a32,                         \
+                      const HvArgs<_Float16>* a16, const LaunchCfg& c, hipStream_t st) {            \
     if (a64)                                                                                        \
       launch_t<double, DGV>(*a64, c, st);                                                           \
-    else                                                                                            \
+    else if (a32)                                                                                   \
       launch_t<float, DGV>(*a32, c, st);                                                            \
+    else                                                                                            \
+      launch_t<_Float16, DGV>(*a16, c, st);                                                         \
   }
 
 }  // namespace hvk

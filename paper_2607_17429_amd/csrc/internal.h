@@ -132,6 +132,7 @@ struct LanczosRun {
   uint64_t seed;
   int target = 0, TB = 0, nb_vec = 0, gl = 0, ng_hv = 0;
   bool pad = false;              // padded vector rows (FTLM_LAYOUT_PADDED)
+  double sigma = 1.0;            // power-of-two storage scale of the vectors (FP16)
   uint64_t rows = 0;             // rows of each stored vector
   // optional timing of the H.V launches (two events per step)
   std::vector<hipEvent_t> hv_events;

@@ -8,6 +8,11 @@
 //   alpha_j = s_j <q_j, w>                         (FP64 partials from the same pass)
 //   w      -= alpha_j s_j q_j ;  beta_{j+1} = |w|  (one update pass, FP64 partials)
 //   q_{j+1} = w, s_{j+1} = 1 / beta_{j+1}
+// FP16 storage keeps every stored vector multiplied by a per-chain power of
+// two sigma (~ sqrt(rows)), so its elements are of order one: q_0 is stored
+// with norm sigma, the epilogue and update use sigma-scaled coefficients and
+// alpha, beta divide it out.  For FP32 and FP64 sigma = 1 and every formula
+// reduces exactly to the one above.
 // Reductions over workgroup partials run in a fixed order (deterministic).
 // Start vectors: SplitMix64 (Steele, Lea, Flood 2014) stream per chain keyed by
 // (seed, 2M, irrep, row, chain); element j uses the (j+1)-th output
@@ -35,6 +40,7 @@ struct Chain {
   int done;
   int step;       // index j of the next step (the kernels of a step read it
                   // here, so one captured graph serves every step)
+  double sigma;   // power-of-two storage scale (1 unless FP16)
 };
 
 __device__ __forceinline__ double start_value(uint64_t key, uint64_t j, int dist) {
@@ -132,14 +138,16 @@ __device__ __forceinline__ double block_sum(const double* __restrict__ partials,
 
 // one block per chain
 __global__ void __launch_bounds__(256) k_init_chain(const double* __restrict__ partials, int ngroups, int R,
-                                                   double* __restrict__ inv_norm, Chain* __restrict__ ch, int phase) {
+                                                   double* __restrict__ inv_norm, Chain* __restrict__ ch, int phase,
+                                                   double sigma) {
   const int v = blockIdx.x;
   const double s = block_sum(partials, ngroups, R, v);
   if (threadIdx.x == 0) {
     if (phase == 0) {
-      inv_norm[v] = s > 0 ? 1.0 / sqrt(s) : 0.0;
+      inv_norm[v] = s > 0 ? sigma / sqrt(s) : 0.0;  // stored q_0 has norm sigma
     } else {
       Chain c{};
+      c.sigma = sigma;
       c.s = s > 0 ? 1.0 / sqrt(s) : 0.0;
       c.bs = 0.0;
       c.beta = 0.0;
@@ -156,8 +164,8 @@ __global__ void __launch_bounds__(256) k_init_chain(const double* __restrict__ p
 __global__ void k_scal(const Chain* __restrict__ ch, int R, double* __restrict__ scal) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v < R) {
-    scal[2 * v] = ch[v].s;
-    scal[2 * v + 1] = ch[v].bs;
+    scal[2 * v] = ch[v].s * ch[v].sigma;
+    scal[2 * v + 1] = ch[v].bs * ch[v].sigma;
   }
 }
 
@@ -168,8 +176,8 @@ __global__ void __launch_bounds__(256) k_alpha(const double* __restrict__ partia
   if (threadIdx.x == 0) {
     Chain c = ch[v];
     const int j = c.step;
-    const double a = c.s * s;
-    c.ca = a * c.s;
+    const double a = c.s * s / c.sigma;
+    c.ca = a * c.s * c.sigma;
     if (!c.done) alpha[(size_t)v * steps + j] = a;
     ch[v] = c;
   }
@@ -185,7 +193,7 @@ __global__ void __launch_bounds__(256) k_beta(const double* __restrict__ partial
     const int j = c.step;
     c.step = j + 1;
     if (!c.done) {
-      const double b = sqrt(s2);
+      const double b = sqrt(s2) / c.sigma;
       beta[(size_t)v * steps + j] = b;
       const double a = alpha[(size_t)v * steps + j];
       c.scale = fmax(c.scale, fabs(a) + c.beta + b);
@@ -194,7 +202,7 @@ __global__ void __launch_bounds__(256) k_beta(const double* __restrict__ partial
         c.done = 1;
       } else {
         c.bs = b * c.s;
-        c.s = 1.0 / b;
+        c.s = 1.0 / (b * c.sigma);
         c.beta = b;
       }
     }
@@ -203,8 +211,8 @@ __global__ void __launch_bounds__(256) k_beta(const double* __restrict__ partial
       c.bs = 0.0;
     }
     ch[v] = c;
-    scal[2 * v] = c.s;
-    scal[2 * v + 1] = c.bs;
+    scal[2 * v] = c.s * c.sigma;
+    scal[2 * v + 1] = c.bs * c.sigma;
   }
 }
 
@@ -234,10 +242,12 @@ void enqueue_begin_typed(LanczosRun& L, hipStream_t st) {
   const int dstride = L.block->dg;
   hipLaunchKernelGGL((k_start<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, L.keys.p, L.dist, D, R, (const double*)nullptr,
                      q0, L.partials.p, meta, stabf, dstride);
-  hipLaunchKernelGGL(k_init_chain, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, L.inv_norm.p, ch, 0);
+  hipLaunchKernelGGL(k_init_chain, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, L.inv_norm.p, ch, 0,
+                     L.sigma);
   hipLaunchKernelGGL((k_start<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, L.keys.p, L.dist, D, R, L.inv_norm.p, q0,
                      L.partials.p, meta, stabf, dstride);
-  hipLaunchKernelGGL(k_init_chain, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, L.inv_norm.p, ch, 1);
+  hipLaunchKernelGGL(k_init_chain, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, L.inv_norm.p, ch, 1,
+                     L.sigma);
   FTLM_HIP(hipMemsetAsync(L.q1.p, 0, L.q1.bytes(), st));
   hipLaunchKernelGGL(k_scal, dim3((R + 63) / 64), dim3(64), 0, st, ch, R, L.scal.p);
   FTLM_HIP(hipGetLastError());
@@ -252,7 +262,7 @@ void enqueue_one_step(LanczosRun& L, hipStream_t st, bool odd, int timed_j) {
   const int R = L.R, steps = L.steps;
   const uint64_t D = L.rows;
   Chain* ch = (Chain*)L.chain.p;
-  const int dtype = sizeof(T) == 8 ? FTLM_F64 : FTLM_F32;
+  const int dtype = sizeof(T) == 8 ? FTLM_F64 : sizeof(T) == 4 ? FTLM_F32 : FTLM_F16;
   T* qj = (T*)(odd ? L.q1.p : L.q0.p);
   T* qprev = (T*)(odd ? L.q0.p : L.q1.p);
   LanczosEpilogue lz{L.scal.p, L.partials.p, L.ng_hv};
@@ -315,7 +325,8 @@ LanczosRun::LanczosRun(const Block& b, int R_, int steps_, uint64_t seed_, int s
   if (R <= 0 || R > 256) fail(FTLM_ERR_INVALID_ARG, "R must be in 1..256");
   if (steps <= 0) fail(FTLM_ERR_INVALID_ARG, "steps must be positive");
   if (dist != FTLM_RADEMACHER && dist != FTLM_GAUSSIAN) fail(FTLM_ERR_INVALID_ARG, "bad distribution");
-  if (storage != FTLM_F64 && storage != FTLM_F32) fail(FTLM_ERR_INVALID_ARG, "storage must be FTLM_F64 or FTLM_F32");
+  if (storage != FTLM_F64 && storage != FTLM_F32 && storage != FTLM_F16)
+    fail(FTLM_ERR_INVALID_ARG, "storage must be FTLM_F64, FTLM_F32 or FTLM_F16");
   const uint64_t D = b.D;
   target = (int)std::min<uint64_t>((uint64_t)steps, D);
   if (b.lanczos_layout == FTLM_LAYOUT_PADDED)
@@ -324,6 +335,9 @@ LanczosRun::LanczosRun(const Block& b, int R_, int steps_, uint64_t seed_, int s
     pad = D >= (1ull << 20) && (double)b.D_pad <= 1.02 * (double)D;
   if (pad && b.D_pad >= (1ull << 48)) fail(FTLM_ERR_UNSUPPORTED, "padded rows above 2^48");
   rows = pad ? b.D_pad : D;
+  // FP16: elements of a unit vector are ~ 1/sqrt(rows); scale them to ~1
+  sigma = 1.0;
+  if (storage == FTLM_F16 && rows > 1) sigma = std::ldexp(1.0, (int)std::floor(0.5 * std::log2((double)rows)));
   TB = R * (256 / R);
   nb_vec = (int)blocks_for(std::max<uint64_t>(rows, 1), TB / R);
   // one lane layout for the whole run (the partial-sum buffer is sized for it)
@@ -332,7 +346,7 @@ LanczosRun::LanczosRun(const Block& b, int R_, int steps_, uint64_t seed_, int s
 }
 
 size_t LanczosRun::estimate_bytes(const Block& b, int R, int steps, int storage) {
-  const size_t elem = storage == FTLM_F64 ? 8 : 4;
+  const size_t elem = storage == FTLM_F64 ? 8 : storage == FTLM_F32 ? 4 : 2;
   const uint64_t rows = std::max(b.D, b.lanczos_layout == FTLM_LAYOUT_BLOCK ? b.D : b.D_pad);
   return 2 * (size_t)rows * R * elem + (size_t)8192 * R * 8 + (size_t)R * steps * 16 + (size_t)R * 128;
 }
@@ -361,7 +375,7 @@ LanczosRun::~LanczosRun() {
 }
 
 void LanczosRun::allocate() {
-  const size_t elem = storage == FTLM_F64 ? 8 : 4;
+  const size_t elem = storage == FTLM_F64 ? 8 : storage == FTLM_F32 ? 4 : 2;
   q0.alloc(std::max<uint64_t>(rows, 1) * R * elem);
   q1.alloc(std::max<uint64_t>(rows, 1) * R * elem);
   std::vector<uint64_t> hkeys(R);
@@ -379,8 +393,10 @@ void LanczosRun::allocate() {
 void LanczosRun::enqueue_begin(hipStream_t st) {
   if (storage == FTLM_F64)
     enqueue_begin_typed<double>(*this, st);
-  else
+  else if (storage == FTLM_F32)
     enqueue_begin_typed<float>(*this, st);
+  else
+    enqueue_begin_typed<_Float16>(*this, st);
 }
 
 void LanczosRun::enqueue_steps(hipStream_t st, int j0, int j1) {
@@ -389,8 +405,10 @@ void LanczosRun::enqueue_steps(hipStream_t st, int j0, int j1) {
   if (j0 >= j1) return;
   if (storage == FTLM_F64)
     enqueue_steps_typed<double>(*this, st, j0, j1);
-  else
+  else if (storage == FTLM_F32)
     enqueue_steps_typed<float>(*this, st, j0, j1);
+  else
+    enqueue_steps_typed<_Float16>(*this, st, j0, j1);
 }
 
 void LanczosRun::enqueue_end(hipStream_t st) {

@@ -184,7 +184,7 @@ int64_t Server::estimate_sector(const Job& j, const Group& G) const {
 int64_t Server::estimate_job(const Job& j, const Group& G, const Sector& S) const {
   const int dg = (G.irreps_computed && j.irrep >= 0 && j.irrep < (int)G.irreps.size()) ? G.irreps[j.irrep].dim : 1;
   const long double D = (long double)S.n_reps * dg;  // >= the block dimension
-  const long double b = (long double)S.n_reps * 16 + 2 * D * j.R * (j.storage == FTLM_F64 ? 8 : 4) +
+  const long double b = (long double)S.n_reps * 16 + 2 * D * j.R * (j.storage == FTLM_F64 ? 8 : j.storage == FTLM_F32 ? 4 : 2) +
                         8192.0 * j.R * 8 + (long double)j.R * j.steps * 16 + (1 << 20);
   return (int64_t)std::min<long double>(b, 9.0e18);
 }
@@ -393,7 +393,7 @@ void Server::launch(const std::shared_ptr<Job>& j, SecEntry& se) {
     // than one chunk ahead of other jobs' work.
     {
       const Sector& S = *j->block->sec;
-      const double elem = j->storage == FTLM_F64 ? 8.0 : 4.0;
+      const double elem = j->storage == FTLM_F64 ? 8.0 : j->storage == FTLM_F32 ? 4.0 : 2.0;
       const double rows = S.n_reps ? (double)j->D / (double)S.n_reps : 0.0;
       const double step_bytes = (double)S.n_entries * (rows * j->R * elem + 8.0) + 6.0 * (double)j->D * j->R * elem;
       const double step_s = step_bytes / kHbmBytesPerSecond;

@@ -99,6 +99,28 @@ def test_observables_icosahedron_all_sectors(storage, tol):
     assert abs(1e9 * chi2[0] / (12 * 0.75 / 3) - 1) < 1e-6
 
 
+def test_observables_icosahedron_fp16_storage():
+    """FP16 vector storage (FP64 arithmetic, per-chain power-of-two scale): the
+    error of E, C, chi against the FP64 oracle, per temperature."""
+    log("[ftlm] icosahedron storage=f16")
+    lib_blocks, ora_blocks = _ftlm_all_blocks("icosahedron", 1, 4, 30, 0x5EED0001, P.F16, P.RADEMACHER)
+    E, C, chi, lz = P.observables(lib_blocks, T_GRID)
+    Eo, Co, chio, lzo = oftlm.observables(ora_blocks, T_GRID, with_logZ=True)
+    eE, eC, eX = _rel(E, Eo), _rel(C, Co), _rel(chi, chio)
+    for k in range(0, len(T_GRID), 7):
+        log(f"  T={T_GRID[k]:.3f} rel err E {eE[k]:.2e} C {eC[k]:.2e} chi {eX[k]:.2e}")
+    log(f"  max rel err E {eE.max():.2e} C {eC.max():.2e} chi {eX.max():.2e}")
+    # Bound from the arithmetic: each stored element carries a relative error of
+    # at most u = 2^-11, which moves Ritz values by ~ u W (W = spectral width);
+    # E moves by that much, and the Boltzmann weights of C and chi by a relative
+    # u W / T.
+    u = 2.0 ** -11
+    th = np.concatenate([np.concatenate(b.thetas) for b in ora_blocks])
+    W = th.max() - th.min()
+    assert np.all(np.abs(E - Eo) <= u * W)
+    assert np.all(eC <= u * W / T_GRID) and np.all(eX <= u * W / T_GRID)
+
+
 def test_padded_layout_against_oracle_and_block_layout():
     """The padded vector layout (d_Gamma rows per representative, read without
     the target's row offset) gives the oracle's coefficients; forced on a

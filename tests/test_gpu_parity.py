@@ -136,6 +136,12 @@ def test_hv_batched_fp32_and_modes(name, two_s, two_M, gi):
         X32 = X.astype(np.float32)
         Y32 = LB.apply_H(torch.from_numpy(X32).cuda()).cpu().numpy()
         assert rel_err_cols(Y32, hv.apply(B, H, X32.astype(np.float64))) <= 2e-7
+        # FP16 storage: one rounding of the FP64 result, |err| <= (2^-11 + 2^-24) |y|
+        X16 = X.astype(np.float16)
+        Y16 = LB.apply_H(torch.from_numpy(X16).cuda())
+        assert rel_err_cols(Y16.cpu().numpy(), hv.apply(B, H, X16.astype(np.float64))) <= 2.0 ** -11 + 2.0 ** -24
+        if otf_fits:
+            assert torch.equal(LO.apply_H(torch.from_numpy(X16).cuda()), Y16)
     # repeated launches are bitwise identical
     X = torch.from_numpy(rng.standard_normal((B.D, 24))).cuda()
     Y1 = LB.apply_H(X)
