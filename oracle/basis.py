@@ -30,7 +30,13 @@ from .sector import digits, enumerate_sector
 
 
 def apply_all(G: Group, labels, N: int, d: int) -> np.ndarray:
-    """(len(labels), |G|) array of the labels of U(g)|n>."""
+    """(len(labels), |G|) array of the labels of U(g)|n>.
+
+    For G x Z2 (``spinflip.FlipGroup``) the columns |G|..2|G|-1 are U(g) F|n>."""
+    if getattr(G, "flip", False):
+        from .spinflip import flip_labels
+        labels = np.asarray(labels, dtype=np.int64)
+        return np.hstack([apply_all(G.base, labels, N, d), apply_all(G.base, flip_labels(labels, N, d), N, d)])
     dig = digits(labels, N, d)
     pw = (d ** G.perms).T            # (N, |G|): weight of site k under g is d^{perm_g[k]}
     return dig @ pw

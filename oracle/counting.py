@@ -57,7 +57,18 @@ def fixed_count(perm, two_s: int, two_M: int) -> int:
 
 
 def block_dims_by_characters(G: Group, irreps, two_s: int, two_M: int):
-    F = np.array([fixed_count(p, two_s, two_M) for p in G.perms], dtype=np.float64)
+    """D_{M,Gamma} = (1/|G|) sum_g chi(g)^* F_M(g), F_M(g) = states of sector M fixed by U(g).
+
+    For G x Z2 (M = 0 only) the elements U(g) F fix the states counted by
+    ``spinflip.flip_fixed_count``."""
+    if getattr(G, "flip", False):
+        from .spinflip import flip_fixed_count
+        if two_M != 0:
+            raise ValueError("the spin flip maps sector M to -M; G x Z2 needs M = 0")
+        F = np.array([fixed_count(p, two_s, 0) for p in G.base.perms] +
+                     [flip_fixed_count(p, two_s) for p in G.base.perms], dtype=np.float64)
+    else:
+        F = np.array([fixed_count(p, two_s, two_M) for p in G.perms], dtype=np.float64)
     dims = []
     for ir in irreps:
         val = np.sum(np.conj(ir.chars) * F) / G.order
