@@ -106,7 +106,15 @@ typedef struct ftlm_opts {
   int32_t entry_format;     /* enum ftlm_entry_format (sector creation) */
   int64_t hbm_limit_bytes;  /* 0 = no limit; builds that would exceed it fail with
                                FTLM_ERR_OUT_OF_MEMORY before allocating */
-  int64_t reserved[6];
+  int32_t spin_flip;        /* sector creation: 1 = resolve the M = 0 sector by the global
+                               spin flip F (every digit a -> d-1-a) as well, i.e. by
+                               G x Z2.  Its element (g, f) acts as U(g) F^f and has index
+                               f|G| + g (connecting elements h reach 2|G| - 1); the irreps
+                               of its blocks are Gamma_i^+ and Gamma_i^- at indices 2i and
+                               2i + 1, rho'(g, f) = (+-1)^f rho_i(g) (user_rho then gives
+                               rho_i on G).  INVALID_ARG unless 2M = 0. */
+  int32_t reserved2;
+  int64_t reserved[5];
 } ftlm_opts;
 
 typedef struct ftlm_group ftlm_group;

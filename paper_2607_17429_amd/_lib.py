@@ -44,7 +44,7 @@ class Opts(C.Structure):
     _fields_ = [("hv_mode", C.c_int32), ("lanczos_layout", C.c_int32),
                 ("user_rho", C.POINTER(C.c_double)), ("user_rho_dim", C.c_int32),
                 ("entry_format", C.c_int32), ("hbm_limit_bytes", C.c_int64),
-                ("reserved", C.c_int64 * 6)]
+                ("spin_flip", C.c_int32), ("reserved2", C.c_int32), ("reserved", C.c_int64 * 5)]
 
 
 class SectorInfo(C.Structure):
@@ -169,8 +169,9 @@ def make_cluster(N, two_s, bonds, J=None):
     return cl
 
 
-def make_opts(hv_mode=HV_AUTO, user_rho=None, hbm_limit=0, layout=0, entry_format=0):
+def make_opts(hv_mode=HV_AUTO, user_rho=None, hbm_limit=0, layout=0, entry_format=0, spin_flip=False):
     o = Opts()
+    o.spin_flip = 1 if spin_flip else 0
     o.hv_mode = hv_mode
     o.entry_format = int(entry_format)
     o.lanczos_layout = int(layout)

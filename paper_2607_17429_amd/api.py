@@ -57,12 +57,13 @@ class Group:
 class Sector:
     """Irrep-independent tables of one M sector (built on the GPU)."""
 
-    def __init__(self, cluster, group: Group, two_M, hv_mode=HV_AUTO, hbm_limit=0, two_s=None, entry_format=0):
+    def __init__(self, cluster, group: Group, two_M, hv_mode=HV_AUTO, hbm_limit=0, two_s=None, entry_format=0,
+                 spin_flip=False):
         cl = L.make_cluster(cluster.N, two_s if two_s is not None else cluster.two_s, cluster.bonds, cluster.J) \
             if not isinstance(cluster, L.Cluster) else cluster
         self._cl = cl
         self.group = group
-        opts = L.make_opts(hv_mode=hv_mode, hbm_limit=hbm_limit, entry_format=entry_format)
+        opts = L.make_opts(hv_mode=hv_mode, hbm_limit=hbm_limit, entry_format=entry_format, spin_flip=spin_flip)
         h = C.c_void_p()
         check(lib().ftlm_sector_create(C.byref(cl), group._h, int(two_M), C.byref(opts), C.byref(h)))
         self._h = h

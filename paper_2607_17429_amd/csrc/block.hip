@@ -143,7 +143,12 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
   B->sec = sec;
   B->irrep = irrep;
   B->row = row;
-  const int n = G.order;
+  const int n = G.order;          // |G|
+  const int ng = sec->gorder;      // |G|, or 2|G| with the spin flip
+  // with the spin flip, irrep 2i + q is Gamma_i with flip parity (-1)^q
+  const int base_irrep = sec->zflip ? irrep >> 1 : irrep;
+  const double parity = (sec->zflip && (irrep & 1)) ? -1.0 : 1.0;
+  if (irrep < 0) fail(FTLM_ERR_IRREP_OUT_OF_RANGE, "irrep index out of range");
   if (opts) {
     if (opts->lanczos_layout < FTLM_LAYOUT_AUTO || opts->lanczos_layout > FTLM_LAYOUT_PADDED)
       fail(FTLM_ERR_INVALID_ARG, "lanczos_layout must be AUTO, BLOCK or PADDED");
@@ -159,14 +164,19 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
   } else {
     if (!G.irreps_computed) fail(FTLM_ERR_UNSUPPORTED, "group irreps not available (|G| > 1024); pass user_rho");
     if (!G.all_real) fail(FTLM_ERR_COMPLEX_IRREP_UNSUPPORTED, "group has irreps that are not of real type");
-    if (irrep < 0 || irrep >= (int)G.irreps.size()) fail(FTLM_ERR_IRREP_OUT_OF_RANGE, "irrep index out of range");
-    const Irrep& ir = G.irreps[irrep];
+    if (base_irrep >= (int)G.irreps.size()) fail(FTLM_ERR_IRREP_OUT_OF_RANGE, "irrep index out of range");
+    const Irrep& ir = G.irreps[base_irrep];
     if (ir.dim > 12) fail(FTLM_ERR_DIM_GT_12, "irrep dimension above 12");
     B->dg = ir.dim;
     B->rho = ir.rho;
   }
   const int d = B->dg;
   if (row < 0 || row >= d) fail(FTLM_ERR_ROW_OUT_OF_RANGE, "row must be in 0..d-1");
+  if (sec->zflip) {
+    // rho'(g, f) = parity^f rho(g): the flipped half follows the G half
+    B->rho.resize((size_t)ng * d * d);
+    for (size_t q = 0; q < (size_t)n * d * d; ++q) B->rho[(size_t)n * d * d + q] = parity * B->rho[q];
+  }
   B->dgp = irrep_dim_bucket(d);
   // per stabilizer data
   const int ns = sec->n_stab;
@@ -206,7 +216,7 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
     B->n_stab[s] = (uint8_t)nG;
     for (int k = 0; k < nG; ++k)
       for (int i = 0; i < d; ++i) B->V_stab[((size_t)s * d + i) * d + k] = cols[k][i];
-    B->L_stab[s] = (double)n / (double)S.size();
+    B->L_stab[s] = (double)ng / (double)S.size();
     B->trivial[s] = (S.size() == 1) ? 1 : 0;
   }
   hipStream_t st = tl_alloc_stream;  // the caller's build stream, or the null stream
@@ -239,8 +249,8 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
   }
   // rho^T[g][beta][gamma] = rho(g)[gamma][beta], zero-padded to the kernel's dimension bucket
   const int dp = B->dgp;
-  std::vector<double> rt((size_t)n * dp * dp, 0.0);
-  for (int g = 0; g < n; ++g)
+  std::vector<double> rt((size_t)ng * dp * dp, 0.0);
+  for (int g = 0; g < ng; ++g)
     for (int be = 0; be < d; ++be)
       for (int ga = 0; ga < d; ++ga) rt[((size_t)g * dp + be) * dp + ga] = B->rho[((size_t)g * d + ga) * d + be];
   B->d_rhoT64.upload(rt);

@@ -176,7 +176,7 @@ int ftlm_block_info_get(const ftlm_block* b, ftlm_block_info* info) {
     info->n_active = B.n_active;
     info->D = B.D;
     info->d_gamma = B.dg;
-    info->group_order = B.sec->G->order;
+    info->group_order = B.sec->gorder;
     info->two_M = B.sec->two_M;
     info->irrep = B.irrep;
     info->row = B.row;

@@ -167,6 +167,55 @@ __device__ __forceinline__ void canon_min(W a, const OrbitTabs<W, NCH>& o, W& be
   }
 }
 
+// Orbit minimum over G x Z2 (spin flip F, which reverses label order: F x =
+// full - x for packed labels).  The images of the flipped elements (g, 1) are
+// F(U(g) a), whose minimum is F of the G-orbit maximum, so one walk keeps the
+// minimum and the maximum, each with the smallest index reaching it.  Index
+// of (g, f) is f |G| + g, and ties on the label go to the smaller index, so a
+// G-element wins a tie with a flipped one.  zf = 0 gives canon_min.
+template <typename W, int NCH>
+__device__ __forceinline__ void canon_min_z(W a, const OrbitTabs<W, NCH>& o, bool zf, W full, int G, W& best,
+                                            int& bestg) {
+  if (!zf) {
+    canon_min<W, NCH>(a, o, best, bestg);
+    return;
+  }
+  int offa[NCH];
+  chunk_offsets<W, NCH>(a, offa);
+  best = a;
+  bestg = 0;
+  W top = a;
+  int topg = 0;
+  for (int hi = 0; hi < o.nH; ++hi) {
+    int off[NCH];
+    if (hi == 0) {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) off[c] = offa[c];
+    } else {
+      chunk_offsets<W, NCH>(permute<W, NCH>(o.H, hi, offa), off);
+    }
+    for (int ti = hi == 0 ? 1 : 0; ti < o.nT; ++ti) {
+      const W img = permute<W, NCH>(o.T, ti, off);
+      if (img <= best || img >= top) {
+        const int g = o.gidx[ti * o.nH + hi];
+        if (img < best || (img == best && g < bestg)) {
+          best = img;
+          bestg = g;
+        }
+        if (img > top || (img == top && g < topg)) {
+          top = img;
+          topg = g;
+        }
+      }
+    }
+  }
+  const W ftop = full - top;
+  if (ftop < best) {
+    best = ftop;
+    bestg = G + topg;
+  }
+}
+
 __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;

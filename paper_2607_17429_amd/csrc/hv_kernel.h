@@ -91,6 +91,8 @@ struct HvArgs {
   const uint64_t* rank_bits;
   const uint32_t* rank_base;
   int cnt_stride, N, A_tot;
+  int Gbase, zf;        // |G| and the spin flip of the on-the-fly search
+  uint64_t full;
   uint64_t D_M;
   uint32_t tab_words;
   // Lanczos epilogue
@@ -218,7 +220,7 @@ k_hv(HvArgs<T> a) {
         }
         W r;
         int h;
-        dev::canon_min<W, NCH>(x, otabs, r, h);
+        dev::canon_min_z<W, NCH>(x, otabs, a.zf != 0, (W)a.full, a.Gbase, r, h);
         uint64_t idx = 0;
         if (ok && lookup_rep<W>(r, a.N, a.b, a.dloc, a.A_tot, a.cnt, a.cnt_stride, a.D_M, a.rank_bits, a.rank_base, idx))
           my = idx | ((uint64_t)h << 32) | ((uint64_t)cand << 48);

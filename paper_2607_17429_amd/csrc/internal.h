@@ -26,6 +26,9 @@ struct Sector {
   int nbonds = 0;
   bool wide = false;            // labels need 64 bits (N * bits > 32)
   int nch = 0;                  // 4-bit chunks of a packed label
+  bool zflip = false;           // M = 0 resolved by G x Z2 (global spin flip)
+  uint64_t full = 0;            // packed label with every digit d - 1
+  int gorder = 0;               // |G|, or 2|G| with the spin flip (element (g, f) = f|G| + g)
   uint64_t D_M = 0, n_reps = 0, n_words = 0;
   int hv_mode = FTLM_HV_ENTRIES;
   // host copies of small tables

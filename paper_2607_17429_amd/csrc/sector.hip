@@ -41,6 +41,8 @@ struct SecArgs {
   const uint64_t* cnt;
   int cnt_stride;
   int N, b, d, A, G, nH, nT;
+  int zf;          // resolve by the spin flip too (G x Z2)
+  uint64_t full;   // packed label with every digit d - 1 (F x = full - x)
   uint64_t D_M, n_words, n_reps;
   uint32_t tab_words;
 };
@@ -59,7 +61,8 @@ __global__ void __launch_bounds__(kThreads) k_enum(SecArgs a, uint64_t* __restri
       const bool valid = w * 64 + k < a.D_M;
       int offx[NCH];
       dev::chunk_offsets<W, NCH>(x, offx);
-      bool smaller = false;
+      const W fx = (W)a.full - x;
+      bool smaller = a.zf && fx < x;  // (e, F)
       // walk g = t h; every lane runs the same trip counts, so the vote is uniform
       int step = 0;
       for (int hi = 0; hi < o.nH; ++hi) {
@@ -72,7 +75,8 @@ __global__ void __launch_bounds__(kThreads) k_enum(SecArgs a, uint64_t* __restri
         }
         bool done = false;
         for (int ti = hi == 0 ? 1 : 0; ti < o.nT; ++ti) {
-          smaller |= dev::permute<W, NCH>(o.T, ti, off) < x;
+          const W img = dev::permute<W, NCH>(o.T, ti, off);
+          smaller |= img < x || (a.zf && img > fx);  // F(img) < x
           if ((++step & 3) == 0 && __all(smaller || !valid)) {
             done = true;
             break;
@@ -127,7 +131,8 @@ __global__ void __launch_bounds__(kThreads) k_stab_flag(SecArgs a, const uint64_
     const W r = (W)reps[i];
     int offr[NCH];
     dev::chunk_offsets<W, NCH>(r, offr);
-    bool fixed = false;
+    const W fr = (W)a.full - r;
+    bool fixed = a.zf && fr == r;  // (e, F)
     int step = 0;
     for (int hi = 0; hi < o.nH; ++hi) {
       int off[NCH];
@@ -139,7 +144,8 @@ __global__ void __launch_bounds__(kThreads) k_stab_flag(SecArgs a, const uint64_
       }
       bool done = false;
       for (int ti = hi == 0 ? 1 : 0; ti < o.nT; ++ti) {
-        fixed |= dev::permute<W, NCH>(o.T, ti, off) == r;
+        const W img = dev::permute<W, NCH>(o.T, ti, off);
+        fixed |= img == r || (a.zf && img == fr);
         if ((++step & 3) == 0 && __all(fixed)) {
           done = true;
           break;
@@ -165,6 +171,7 @@ __global__ void __launch_bounds__(kThreads) k_stab_mask(SecArgs a, const uint64_
     const uint64_t p = pos[i];
     if (pos[i + 1] == p) continue;
     const W r = (W)reps[i];
+    const W fr = (W)a.full - r;
     int offr[NCH];
     dev::chunk_offsets<W, NCH>(r, offr);
     uint64_t* mk = masks + p * mw;
@@ -172,11 +179,15 @@ __global__ void __launch_bounds__(kThreads) k_stab_mask(SecArgs a, const uint64_
     for (int hi = 0; hi < o.nH; ++hi) {
       int off[NCH];
       dev::chunk_offsets<W, NCH>(dev::permute<W, NCH>(o.H, hi, offr), off);
-      for (int ti = 0; ti < o.nT; ++ti)
-        if (dev::permute<W, NCH>(o.T, ti, off) == r) {
-          const int g = o.gidx[ti * o.nH + hi];
-          mk[g >> 6] |= 1ull << (g & 63);   // this lane's own mask words
+      for (int ti = 0; ti < o.nT; ++ti) {
+        const W img = dev::permute<W, NCH>(o.T, ti, off);
+        const int g = o.gidx[ti * o.nH + hi];
+        if (img == r) mk[g >> 6] |= 1ull << (g & 63);   // this lane's own mask words
+        if (a.zf && img == fr) {
+          const int gf = a.G + g;                       // (g, F)
+          mk[gf >> 6] |= 1ull << (gf & 63);
         }
+      }
     }
     idx_out[p] = i;
   }
@@ -300,7 +311,7 @@ __global__ void __launch_bounds__(kThreads) k_entry_fill(SecArgs a, FlipArgs f, 
       const W x = cur >= 0 ? apply_flip<W>(p, cur, f, a.b) : p;
       W r;
       int h;
-      dev::canon_min<W, NCH>(x, o, r, h);
+      dev::canon_min_z<W, NCH>(x, o, a.zf, (W)a.full, a.G, r, h);
       if (cur >= 0) {
         uint64_t idx = 0;
         bool ok = lookup<W>(r, a, bits, base, idx);
@@ -354,7 +365,7 @@ __global__ void __launch_bounds__(kThreads) k_canon_labels(SecArgs a, const uint
     }
     W r;
     int h;
-    dev::canon_min<W, NCH>(x, o, r, h);
+    dev::canon_min_z<W, NCH>(x, o, a.zf, (W)a.full, a.G, r, h);
     if (live) {
       uint64_t idx = 0;
       bool ok = in_range && lookup<W>(r, a, bits, base, idx);
@@ -408,6 +419,12 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
   if (s.N * s.bits > 64) fail(FTLM_ERR_UNSUPPORTED, "packed labels need more than 64 bits");
   s.wide = s.N * s.bits > 32;
   s.nch = nch_bucket((s.N * s.bits + 3) / 4);
+  // spin flip (G x Z2) at M = 0
+  s.zflip = opts && opts->spin_flip;
+  if (s.zflip && two_M != 0) fail(FTLM_ERR_INVALID_ARG, "the spin flip resolves only the M = 0 sector");
+  s.full = 0;
+  for (int k = 0; k < s.N; ++k) s.full |= (uint64_t)(s.d - 1) << (k * s.bits);
+  s.gorder = G->order * (s.zflip ? 2 : 1);
   if (cl->nbonds < 0 || (cl->nbonds > 0 && !cl->bonds)) fail(FTLM_ERR_INVALID_ARG, "bad bond list");
   if (cl->nbonds > 16000) fail(FTLM_ERR_INVALID_ARG, "too many bonds");
   s.nbonds = cl->nbonds;
@@ -520,6 +537,8 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
   a.d = s.d;
   a.A = s.A;
   a.G = G_;
+  a.zf = s.zflip ? 1 : 0;
+  a.full = s.full;
   a.nH = s.fac_nH;
   a.nT = s.fac_nT;
   a.D_M = s.D_M;
@@ -580,7 +599,7 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
     FTLM_HIP(hipGetLastError());
     uint64_t n_nt = 0;
     scan_exclusive_u64(pos.p, pos.p, s.n_reps + 1, &n_nt, st);
-    const int mw = (G_ + 63) / 64;
+    const int mw = (s.gorder + 63) / 64;
     DevBuf<uint64_t> masks, idx;
     masks.alloc(std::max<uint64_t>(n_nt, 1) * mw);
     idx.alloc(std::max<uint64_t>(n_nt, 1));
@@ -620,7 +639,7 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
       uint16_t id = (uint16_t)ids.size();
       ids.emplace(m, id);
       std::vector<int32_t> el;
-      for (int g = 0; g < G_; ++g)
+      for (int g = 0; g < s.gorder; ++g)
         if ((m[g / 64] >> (g % 64)) & 1) el.push_back(g);
       s.stab_elems.push_back(el);
       s.stab_size.push_back((uint16_t)el.size());
@@ -666,7 +685,7 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
   // idx | h << 32 | flip << 48 | trivial << 63) otherwise.
   {
     int hb = 1, cb = 1;
-    while ((1 << hb) < G_) ++hb;
+    while ((1 << hb) < s.gorder) ++hb;
     while ((1 << cb) < 2 * s.nbonds) ++cb;
     s.ent_hbits = hb;
     const bool compact_ok = hb + cb <= 15;
@@ -727,6 +746,8 @@ void sector_canonicalize(const Sector& s, const uint64_t* labels, int64_t n, uin
   a.d = s.d;
   a.A = s.A;
   a.G = s.G->order;
+  a.zf = s.zflip ? 1 : 0;
+  a.full = s.full;
   a.nH = s.fac_nH;
   a.nT = s.fac_nT;
   a.D_M = s.D_M;
