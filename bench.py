@@ -48,6 +48,11 @@ WORKLOADS = {
                                     desc="s=3/2 Heisenberg dodecahedron (N=20, 30 bonds, 40-bit labels), I_h, M=0, "
                                          "irrep H_g row 1 (D=3,624,380,734); R=2 Rademacher chains, 60 Lanczos steps, "
                                          "FP16 storage with a per-chain power-of-two scale, FP64 arithmetic"),
+    "dodecahedron_s32_Hg_flip": dict(cluster="dodecahedron", two_s=3, two_M=0, irrep=16, R=2, steps=60,
+                                     dist="rademacher", storage="f32", flip=True,
+                                     desc="s=3/2 Heisenberg dodecahedron, M=0 resolved by G x Z2 (I_h x spin "
+                                          "flip), irrep H_g^+ row 1 (D=1,812,277,727); R=2 Rademacher chains, 60 "
+                                          "Lanczos steps, FP32 storage, FP64 reductions"),
     "dodecahedron_Hg": dict(cluster="dodecahedron", two_s=1, two_M=0, irrep=8, R=24, steps=60, dist="rademacher",
                             storage="f64",
                             desc="s=1/2 dodecahedron (N=20), I_h, M=0, irrep H_g (D=7,800); R=24 Rademacher, "
@@ -90,7 +95,11 @@ def cpu_baseline(wl, seconds):
 
     cl = clusters.get(wl["cluster"])
     G = ogroup.close(cl.gens, cl.N)
-    ir = oirreps.compute_irreps(G)[wl["irrep"]]
+    irs = oirreps.compute_irreps(G)
+    if wl.get("flip"):
+        from oracle import spinflip
+        G, irs = spinflip.FlipGroup(G), spinflip.flip_irreps(irs)
+    ir = irs[wl["irrep"]]
     d = wl["two_s"] + 1
     rng = np.random.default_rng(17)
     A = (cl.N * wl["two_s"] + wl["two_M"]) // 2
@@ -261,7 +270,7 @@ def main():
     def job(seed):
         t0 = time.perf_counter()
         G = P.Group(cl.N, cl.gens)
-        S = P.Sector(cl, G, wl["two_M"], two_s=wl["two_s"])
+        S = P.Sector(cl, G, wl["two_M"], two_s=wl["two_s"], spin_flip=wl.get("flip", False))
         t1 = time.perf_counter()
         B = P.Block(S, wl["irrep"], 0)
         a, b, n, info = B.ftlm(wl["R"], wl["steps"], seed, storage=storage, dist=dist, stream=stream, info=True)
@@ -276,7 +285,7 @@ def main():
 
     if args.profile_hv:
         G0 = P.Group(cl.N, cl.gens)
-        S0 = P.Sector(cl, G0, wl["two_M"], two_s=wl["two_s"])
+        S0 = P.Sector(cl, G0, wl["two_M"], two_s=wl["two_s"], spin_flip=wl.get("flip", False))
         B0 = P.Block(S0, wl["irrep"], 0)
         tuned = B0.autotune(wl["R"], storage, stream=stream)
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
@@ -300,7 +309,7 @@ def main():
 
     # autotune the H.V lane layout once for this kernel shape (cached process-wide)
     G0 = P.Group(cl.N, cl.gens)
-    S0 = P.Sector(cl, G0, wl["two_M"], two_s=wl["two_s"])
+    S0 = P.Sector(cl, G0, wl["two_M"], two_s=wl["two_s"], spin_flip=wl.get("flip", False))
     B0 = P.Block(S0, wl["irrep"], 0)
     tuned = B0.autotune(wl["R"], storage, stream=stream)
     del B0, S0, G0
@@ -318,7 +327,7 @@ def main():
 
     # ---- H.V kernel alone: same block, nvec = R, storage dtype, HIP events on the launch stream
     G = P.Group(cl.N, cl.gens)
-    S = P.Sector(cl, G, wl["two_M"], two_s=wl["two_s"])
+    S = P.Sector(cl, G, wl["two_M"], two_s=wl["two_s"], spin_flip=wl.get("flip", False))
     B = P.Block(S, wl["irrep"], 0)
     tdt = {P.F64: torch.float64, P.F32: torch.float32, P.F16: torch.float16}[storage]
     elem = {P.F64: 8, P.F32: 4, P.F16: 2}[storage]

@@ -249,8 +249,11 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
   }
   // rho^T[g][beta][gamma] = rho(g)[gamma][beta], zero-padded to the kernel's dimension bucket
   const int dp = B->dgp;
-  std::vector<double> rt((size_t)ng * dp * dp, 0.0);
-  for (int g = 0; g < ng; ++g)
+  // only the |G| matrices of G: the flipped half is parity * rho(g), applied
+  // by the kernel as a sign on the coefficient
+  B->fpar = parity;
+  std::vector<double> rt((size_t)n * dp * dp, 0.0);
+  for (int g = 0; g < n; ++g)
     for (int be = 0; be < d; ++be)
       for (int ga = 0; ga < d; ++ga) rt[((size_t)g * dp + be) * dp + ga] = B->rho[((size_t)g * d + ga) * d + be];
   B->d_rhoT64.upload(rt);

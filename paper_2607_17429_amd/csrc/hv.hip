@@ -170,7 +170,7 @@ void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
   // small tables first priority; the permutation table joins them in LDS when
   // both fit, otherwise it is read through the caches
   uint64_t small = 0;
-  small = align16(small + (uint64_t)s.gorder * (uint64_t)b.dgp * b.dgp * 8);
+  small = align16(small + (uint64_t)s.G->order * (uint64_t)b.dgp * b.dgp * 8);
   small = align16(small + (uint64_t)std::max(s.n_stab, 1) * b.dgp * b.dgp * 8);
   small = align16(small + (uint64_t)std::max(s.n_stab, 1) * 4 * 8);
   small = align16(small + (uint64_t)s.nbonds * 8);
@@ -180,7 +180,7 @@ void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
   const uint32_t base = c.lds_tab ? align16(tab_bytes) : 0;
   uint64_t o = base;
   const uint32_t o_rho = (uint32_t)o;
-  o = align16(o + (uint64_t)s.gorder * DG * DG * 8);
+  o = align16(o + (uint64_t)s.G->order * DG * DG * 8);
   const uint32_t o_V = (uint32_t)o;
   o = align16(o + ns * DG * DG * 8);
   const uint32_t o_stab = (uint32_t)o;
@@ -215,8 +215,9 @@ void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
     a.b = s.bits;
     a.dloc = s.d;
     a.nbonds = s.nbonds;
-    a.G = s.gorder;  // rho^T tables: one per element of G (x Z2)
+    a.G = s.G->order;  // rho^T tables: one per element of G
     a.Gbase = s.G->order;
+    a.fpar = b.fpar;
     a.zf = s.zflip ? 1 : 0;
     a.full = s.full;
     a.nH = s.fac_nH;

@@ -93,6 +93,7 @@ struct HvArgs {
   int cnt_stride, N, A_tot;
   int Gbase, zf;        // |G| and the spin flip of the on-the-fly search
   uint64_t full;
+  double fpar;          // flip parity: element (g, F) acts as fpar * rho(g)
   uint64_t D_M;
   uint32_t tab_words;
   // Lanczos epilogue
@@ -270,12 +271,16 @@ k_hv(HvArgs<T> a) {
               xv[q][j] = use ? val : T(0);
             }
         }
-        const int h = (int)((ent >> 32) & 0xffff);
+        int h = (int)((ent >> 32) & 0xffff);
         const int cand = (int)((ent >> 48) & 0x7fff);
         const int bond = cand >> 1;
         const int ai = dev::digit(plab, bonds[2 * bond], a.b, lmask);
         const int aj = dev::digit(plab, bonds[2 * bond + 1], a.b, lmask);
-        const double c = Jb[bond] * fac[((cand & 1) * a.dloc + ai) * a.dloc + aj] * stabf[4 * sr + 2];
+        double c = Jb[bond] * fac[((cand & 1) * a.dloc + ai) * a.dloc + aj] * stabf[4 * sr + 2];
+        // G x Z2: (g, F) has index |G| + g and matrix fpar * rho(g)
+        const bool flipped = h >= a.Gbase;
+        h = flipped ? h - a.Gbase : h;
+        c = flipped ? c * a.fpar : c;
         const double* R = rhoT + (size_t)h * DG * DG;
         if (stabf[4 * sr + 3] != 0.0) {
 #pragma unroll

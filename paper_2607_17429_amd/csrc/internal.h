@@ -78,6 +78,7 @@ struct Block {
   int dgp = 0;                  // kernel dimension bucket (tables zero-padded to it)
   uint64_t D = 0, n_active = 0;
   uint64_t D_pad = 0;           // n_reps * dg: rows of the padded vector layout
+  double fpar = 1.0;            // spin-flip parity of the irrep (G x Z2 sectors)
   int lanczos_layout = FTLM_LAYOUT_AUTO;
   std::vector<double> rho;      // |G| x d x d (the irrep used)
   std::vector<uint8_t> n_stab;  // n_Gamma per stabilizer id

@@ -12,6 +12,8 @@ input whose values depend only on (representative label, k, column); it is
 generated on the device with the torch form of the seeded generator, and
 sampled output rows are compared with the oracle's row-by-row evaluation.
 """
+import gc
+
 import numpy as np
 import pytest
 
@@ -31,6 +33,8 @@ NVEC = 2
 
 @pytest.fixture(scope="module")
 def dodeca32():
+    gc.collect()
+    torch.cuda.empty_cache()     # device memory cached by earlier modules
     cl = clusters.get("dodecahedron")
     G = group.close(cl.gens, cl.N)
     irs = irreps.compute_irreps(G)
@@ -112,3 +116,4 @@ def test_hg_block_sampled_rows_s32(dodeca32):
         got = Y[o:o + counts[i]].double().cpu().numpy()
         assert np.max(np.abs(got - yref)) <= 2e-7 * scale, (i, np.max(np.abs(got - yref)) / scale)
     del Y
+
