@@ -53,6 +53,16 @@ WORKLOADS = {
                                      desc="s=3/2 Heisenberg dodecahedron, M=0 resolved by G x Z2 (I_h x spin "
                                           "flip), irrep H_g^+ row 1 (D=1,812,277,727); R=2 Rademacher chains, 60 "
                                           "Lanczos steps, FP32 storage, FP64 reductions"),
+    "icosahedron_all": dict(cluster="icosahedron", two_s=1, R=4, steps=30, dist="rademacher", storage="f64",
+                            campaign=True, chains_per_run=1,
+                            desc="s=1/2 Heisenberg icosahedron (N=12), I_h, all M >= 0 sectors, all 10 irreps, row 1; "
+                                 "R=4 Rademacher chains run one at a time (plain single-vector FP64 path), 30 "
+                                 "Lanczos steps; E, C, chi at 50 T in [0.05, 10]"),
+    "dodecahedron_all": dict(cluster="dodecahedron", two_s=1, R=24, steps=60, dist="rademacher", storage="f64",
+                             campaign=True, chains_per_run=0,
+                             desc="s=1/2 Heisenberg dodecahedron (N=20), I_h, all M >= 0 sectors, all irreps, row 1; "
+                                  "R=24 Rademacher chains batched in one H.V launch per step, 60 Lanczos steps, "
+                                  "FP64; E, C, chi at 50 T"),
     "dodecahedron_Hg": dict(cluster="dodecahedron", two_s=1, two_M=0, irrep=8, R=24, steps=60, dist="rademacher",
                             storage="f64",
                             desc="s=1/2 dodecahedron (N=20), I_h, M=0, irrep H_g (D=7,800); R=24 Rademacher, "
@@ -213,6 +223,91 @@ def serve(P, np, n_warm, n_jobs, rate, budget_gb, max_active, seed=0x5EED0100, l
                 resident_bytes_after=stats["used_bytes"])
 
 
+def oracle_campaign_rate(wl, seconds):
+    """FP64 oracle FTLM over the cluster's blocks (explicit basis, SciPy Lanczos), block by block
+    until the time budget is spent: basis elements x products per second."""
+    import numpy as np
+
+    from oracle import basis as obasis
+    from oracle import ftlm as oftlm
+    from oracle import group as ogroup
+    from oracle import hv as ohv
+    from oracle import irreps as oirreps
+    from oracle import sector as osector
+    from synth import clusters
+
+    cl = clusters.get(wl["cluster"])
+    G = ogroup.close(cl.gens, cl.N)
+    irs = oirreps.compute_irreps(G)
+    two_s = wl["two_s"]
+    work, blocks = 0, 0
+    t0 = time.perf_counter()
+    for two_M in range((cl.N * two_s) % 2, cl.N * two_s + 1, 2):
+        sec = obasis.sector_reps(G, cl.N, two_s, two_M)
+        H = osector.hamiltonian(sec.labels, cl.N, two_s, cl.bonds, cl.J)
+        for gi, ir in enumerate(irs):
+            B = obasis.build_block(G, ir, sec)
+            if B.D == 0:
+                continue
+            Hb = ohv.block_matrix(B, H)
+            for r in range(wl["R"]):
+                v0 = oftlm.start_vector(B.D, 1, two_M, gi, 0, r, "rademacher")
+                a, b = oftlm.lanczos(lambda x: Hb @ x, v0, wl["steps"])
+                work += B.D * len(a)
+            blocks += 1
+            if time.perf_counter() - t0 > seconds:
+                break
+        if time.perf_counter() - t0 > seconds:
+            break
+    el = time.perf_counter() - t0
+    return dict(value=work / el, unit="basis-elems*vecs/s", cores=1, kind="oracle",
+                sample=f"{blocks} blocks of the campaign (explicit basis, dense block matrix, one chain at a time), "
+                       f"{el:.1f} s single-threaded Python/NumPy")
+
+
+def bench_campaign(P, np, wl, cl, args):
+    """Whole-cluster FTLM: every M >= 0 sector and irrep block, thermal sums."""
+    T = np.geomspace(0.05, 10, 50)
+    storage = {"f64": P.F64, "f32": P.F32, "f16": P.F16}[wl["storage"]]
+    dist = P.GAUSSIAN if wl["dist"] == "gaussian" else P.RADEMACHER
+
+    def run(seed, cpr):
+        return P.campaign(cl, cl.gens, wl["two_s"], wl["R"], wl["steps"], seed, T, storage=storage, dist=dist,
+                          chains_per_run=cpr)
+
+    for w in range(args.warmup):
+        run(0x5EED0001 + 100 + w, wl["chains_per_run"])
+    t0 = time.perf_counter()
+    recs = [run(0x5EED0001 + k, wl["chains_per_run"]) for k in range(args.steps)]
+    wall = time.perf_counter() - t0
+    work = sum(r["stats"]["work"] for r in recs)
+    other = 1 if wl["chains_per_run"] == 0 else 0          # the other path, for the speedup figure
+    t1 = time.perf_counter()
+    alt = run(0x5EED0001, other)
+    alt_s = time.perf_counter() - t1
+    st = recs[0]["stats"]
+    cpu = None if args.no_cpu_baseline else oracle_campaign_rate(wl, args.cpu_seconds)
+    return {
+        "metric": "FTLM campaign basis-elems x vecs/s (all M >= 0 sectors and irreps, thermal sums)",
+        "value": work / wall, "unit": "basis-elems*vecs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": wl["storage"],
+        "data": "synthetic (cluster geometry + seeded SplitMix64 start vectors)",
+        "config": {"workload": wl["desc"], "sectors": st["sectors"], "blocks": st["blocks"], "rows": st["rows"],
+                   "R": wl["R"], "lanczos_steps": wl["steps"], "parallelism": "single GPU"},
+        "roofline": None,
+        "roofline_note": "every block is cache-resident (largest few MB), so an HBM roofline does not bound it",
+        "cpu_baseline": cpu,
+        "breakdown_s": {k: st[k] for k in ("seconds_build", "seconds_lanczos", "seconds_thermo", "seconds_total")},
+        "single_vs_batched": {"this_path": "single-vector" if wl["chains_per_run"] == 1 else "batched",
+                              "other_path_elem_vec_per_s": alt["stats"]["work"] / alt_s,
+                              "speedup_batched_over_single":
+                                  (work / wall) / (alt["stats"]["work"] / alt_s) if other == 1
+                                  else (alt["stats"]["work"] / alt_s) / (work / wall)},
+        "E_T0.05": float(recs[0]["E"][0]), "E_T10": float(recs[0]["E"][-1]),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,6 +355,10 @@ def main():
 
     wl = WORKLOADS[args.workload]
     cl = clusters.get(wl["cluster"])
+    if wl.get("campaign"):
+        torch.cuda.set_device(0)
+        print(json.dumps(bench_campaign(P, np, wl, cl, args)), flush=True)
+        return
     storage = {"f64": P.F64, "f32": P.F32, "f16": P.F16}[wl["storage"]]
     dist = P.GAUSSIAN if wl["dist"] == "gaussian" else P.RADEMACHER
     T = np.geomspace(0.05, 10, 50)

@@ -301,6 +301,41 @@ typedef struct ftlm_ritz {
 int ftlm_observables(const ftlm_ritz* blocks, int32_t nblocks, const double* T, int32_t nT, double g,
                      double* E, double* C, double* chi, double* logZ);
 
+/* ------------------------------------------------------------- campaign ---
+ * The whole method on one cluster (Sections 2.2, 3, 4): every M >= 0 sector
+ * (or one), every irrep block of it (row 0; with spin_flip, G x Z2 at M = 0),
+ * R chains per block, Ritz data per chain, and E, C, chi, ln Z on T[0..nT) by
+ * ftlm_observables over all blocks.  Uses the library's own irreps (real type
+ * required).  Chain r of block (2M, irrep) has the key of ftlm_run, so a
+ * block's coefficients equal those of ftlm_run on that block with the same
+ * chains per run.  Blocks run one after another on a stream of the library;
+ * the sector tables of one M are freed before the next.  Synchronous. */
+typedef struct ftlm_campaign_opts {
+  int32_t R;               /* chains per block */
+  int32_t steps;           /* Lanczos steps per chain */
+  uint64_t seed;
+  int32_t storage;         /* enum ftlm_dtype */
+  int32_t dist;            /* enum ftlm_dist */
+  int32_t all_M;           /* 1: all 2M = (2Ns mod 2) .. 2Ns; 0: only two_M */
+  int32_t two_M;
+  int32_t spin_flip;       /* resolve M = 0 by G x Z2 */
+  int32_t chains_per_run;  /* 0: all R chains share one H.V launch per step; k: runs of k chains
+                              (1 = the plain single-vector path) */
+  double g;                /* g factor of chi */
+} ftlm_campaign_opts;
+
+typedef struct ftlm_campaign_stats {
+  int32_t sectors, blocks, empty_blocks, reserved;
+  uint64_t rows;           /* sum of block dimensions */
+  uint64_t products;       /* H.v products over all chains */
+  uint64_t work;           /* sum over chains of D x products: basis elements x vectors */
+  double seconds_build, seconds_lanczos, seconds_thermo, seconds_total;
+} ftlm_campaign_stats;
+
+int ftlm_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, const ftlm_campaign_opts* opts,
+                  const double* T, int32_t nT, double* E, double* C, double* chi, double* logZ,
+                  ftlm_campaign_stats* stats);
+
 void ftlm_block_free(ftlm_block* b);
 const char* ftlm_last_error(void);
 

@@ -65,6 +65,19 @@ class HvStats(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class CampaignOpts(C.Structure):
+    _fields_ = [("R", C.c_int32), ("steps", C.c_int32), ("seed", C.c_uint64), ("storage", C.c_int32),
+                ("dist", C.c_int32), ("all_M", C.c_int32), ("two_M", C.c_int32), ("spin_flip", C.c_int32),
+                ("chains_per_run", C.c_int32), ("g", C.c_double)]
+
+
+class CampaignStats(C.Structure):
+    _fields_ = [("sectors", C.c_int32), ("blocks", C.c_int32), ("empty_blocks", C.c_int32), ("reserved", C.c_int32),
+                ("rows", C.c_uint64), ("products", C.c_uint64), ("work", C.c_uint64),
+                ("seconds_build", C.c_double), ("seconds_lanczos", C.c_double), ("seconds_thermo", C.c_double),
+                ("seconds_total", C.c_double)]
+
+
 class RunInfo(C.Structure):
     _fields_ = [("layout", C.c_int32), ("hv_launches", C.c_int32), ("rows", C.c_uint64), ("hv_ms", C.c_double)]
 
@@ -117,6 +130,8 @@ SIGNATURES = {
     "ftlm_run_ex": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, F64P, F64P, I32P, VP,
                               C.POINTER(RunInfo)]),
     "ftlm_tridiag_ritz": (C.c_int, [F64P, F64P, C.c_int32, F64P, F64P]),
+    "ftlm_campaign": (C.c_int, [C.POINTER(Cluster), I32P, C.c_int32, C.POINTER(CampaignOpts), F64P, C.c_int32,
+                                F64P, F64P, F64P, F64P, C.POINTER(CampaignStats)]),
     "ftlm_observables": (C.c_int, [C.POINTER(Ritz), C.c_int32, F64P, C.c_int32, C.c_double, F64P, F64P, F64P, F64P]),
     "ftlm_block_free": (None, [VP]),
     # include/ftlm_server.h

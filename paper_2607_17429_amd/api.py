@@ -252,3 +252,20 @@ def observables(blocks, T, g=1.0):
 
 __all__ = ["Group", "Sector", "Block", "tridiag_ritz", "ritz_from_run", "observables", "FtlmError",
            "F32", "F64", "RADEMACHER", "GAUSSIAN", "HV_AUTO", "HV_ENTRIES", "HV_ONTHEFLY"]
+
+
+def campaign(cluster, gens, two_s, R, steps, seed, T, storage=F64, dist=RADEMACHER, all_M=True, two_M=0,
+             spin_flip=False, chains_per_run=0, g=1.0):
+    """Whole-cluster FTLM (ftlm_campaign): E, C, chi, logZ on T and the run statistics."""
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    cl = L.make_cluster(cluster.N, two_s, cluster.bonds, cluster.J)
+    gens = np.ascontiguousarray(np.asarray(gens, dtype=np.int32).reshape(-1, cluster.N))
+    o = L.CampaignOpts(int(R), int(steps), C.c_uint64(seed), int(storage), int(dist), 1 if all_M else 0,
+                       int(two_M), 1 if spin_flip else 0, int(chains_per_run), float(g))
+    out = [np.empty(len(T)) for _ in range(4)]
+    st = L.CampaignStats()
+    check(lib().ftlm_campaign(C.byref(cl), gens.ctypes.data_as(L.I32P), len(gens), C.byref(o),
+                              T.ctypes.data_as(L.F64P), len(T), *[x.ctypes.data_as(L.F64P) for x in out],
+                              C.byref(st)))
+    E, Cv, chi, logZ = out
+    return dict(E=E, C=Cv, chi=chi, logZ=logZ, stats={f: getattr(st, f) for f, _ in L.CampaignStats._fields_})

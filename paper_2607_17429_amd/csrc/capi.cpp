@@ -262,6 +262,12 @@ int ftlm_run_ex(ftlm_block* b, int32_t R, int32_t steps, uint64_t seed, int32_t 
   });
 }
 
+int ftlm_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, const ftlm_campaign_opts* opts,
+                  const double* T, int32_t nT, double* E, double* C, double* chi, double* logZ,
+                  ftlm_campaign_stats* stats) {
+  return guarded([&] { run_campaign(cl, gens, ngens, opts, T, nT, E, C, chi, logZ, stats); });
+}
+
 int ftlm_tridiag_ritz(const double* alpha, const double* beta, int32_t n, double* theta, double* weight) {
   return guarded([&] {
     if (n < 0 || n > 4096) fail(FTLM_ERR_INVALID_ARG, "n must be in 0..4096");

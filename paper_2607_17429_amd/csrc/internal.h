@@ -135,6 +135,7 @@ struct LanczosRun {
   int R, steps, storage, dist;
   uint64_t seed;
   int target = 0, TB = 0, nb_vec = 0, gl = 0, ng_hv = 0;
+  int first_chain = 0;           // chain keys start at this chain index
   bool pad = false;              // padded vector rows (FTLM_LAYOUT_PADDED)
   double sigma = 1.0;            // power-of-two storage scale of the vectors (FP16)
   uint64_t rows = 0;             // rows of each stored vector
@@ -170,6 +171,10 @@ void observables(const ftlm_ritz* blocks, int nb, const double* T, int nT, doubl
                  double* chi, double* logZ);
 
 uint64_t chain_key(uint64_t seed, int two_M, int irrep, int row, int chain);
+
+void run_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, const ftlm_campaign_opts* o,
+                  const double* T, int nT, double* E, double* C, double* chi, double* logZ,
+                  ftlm_campaign_stats* st);
 
 // exclusive prefix sum over n values of a device array (uint64 in/out, in-place allowed)
 void scan_exclusive_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t* total, hipStream_t s);

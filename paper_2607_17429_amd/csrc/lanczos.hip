@@ -379,7 +379,8 @@ void LanczosRun::allocate() {
   q0.alloc(std::max<uint64_t>(rows, 1) * R * elem);
   q1.alloc(std::max<uint64_t>(rows, 1) * R * elem);
   std::vector<uint64_t> hkeys(R);
-  for (int v = 0; v < R; ++v) hkeys[v] = chain_key(seed, block->sec->two_M, block->irrep, block->row, v);
+  for (int v = 0; v < R; ++v)
+    hkeys[v] = chain_key(seed, block->sec->two_M, block->irrep, block->row, first_chain + v);
   keys.upload(hkeys);
   partials.alloc((size_t)std::max(nb_vec, ng_hv) * R);
   inv_norm.alloc(R);
