@@ -271,9 +271,11 @@ def bench_campaign(P, np, wl, cl, args):
     storage = {"f64": P.F64, "f32": P.F32, "f16": P.F16}[wl["storage"]]
     dist = P.GAUSSIAN if wl["dist"] == "gaussian" else P.RADEMACHER
 
-    def run(seed, cpr):
+    engine = {"auto": P.ENGINE_AUTO, "steps": P.ENGINE_STEPS, "fused": P.ENGINE_FUSED}[args.engine]
+
+    def run(seed, cpr, eng=engine):
         return P.campaign(cl, cl.gens, wl["two_s"], wl["R"], wl["steps"], seed, T, storage=storage, dist=dist,
-                          chains_per_run=cpr)
+                          chains_per_run=cpr, engine=eng)
 
     for w in range(args.warmup):
         run(0x5EED0001 + 100 + w, wl["chains_per_run"])
@@ -286,6 +288,11 @@ def bench_campaign(P, np, wl, cl, args):
     alt = run(0x5EED0001, other)
     alt_s = time.perf_counter() - t1
     st = recs[0]["stats"]
+    # the same campaign with the per-step kernels only (no fused small-block kernel)
+    run(0x5EED0001, wl["chains_per_run"], P.ENGINE_STEPS)
+    t2 = time.perf_counter()
+    per_step = run(0x5EED0001, wl["chains_per_run"], P.ENGINE_STEPS)
+    per_step_s = time.perf_counter() - t2
     cpu = None if args.no_cpu_baseline else oracle_campaign_rate(wl, args.cpu_seconds)
     return {
         "metric": "FTLM campaign basis-elems x vecs/s (all M >= 0 sectors and irreps, thermal sums)",
@@ -299,6 +306,9 @@ def bench_campaign(P, np, wl, cl, args):
         "roofline_note": "every block is cache-resident (largest few MB), so an HBM roofline does not bound it",
         "cpu_baseline": cpu,
         "breakdown_s": {k: st[k] for k in ("seconds_build", "seconds_lanczos", "seconds_thermo", "seconds_total")},
+        "engine": {"name": args.engine, "fused_blocks": st["fused_blocks"],
+                   "per_step_engine_elem_vec_per_s": per_step["stats"]["work"] / per_step_s,
+                   "speedup_over_per_step_engine": (work / wall) / (per_step["stats"]["work"] / per_step_s)},
         "single_vs_batched": {"this_path": "single-vector" if wl["chains_per_run"] == 1 else "batched",
                               "other_path_elem_vec_per_s": alt["stats"]["work"] / alt_s,
                               "speedup_batched_over_single":
@@ -317,6 +327,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hv-reps", type=int, default=20)
+    ap.add_argument("--engine", default="auto", choices=["auto", "steps", "fused"],
+                    help="campaign workloads: Lanczos engine (fused small-block kernel, per-step kernels, or automatic)")
     ap.add_argument("--profile-hv", action="store_true",
                     help="counter run: one 1 GiB copy (calibration) and 5 H.V launches, then exit")
     ap.add_argument("--serve", action="store_true", help="run the job-server benchmark (serving mix) instead")

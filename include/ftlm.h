@@ -276,6 +276,38 @@ typedef struct ftlm_run_info {
 int ftlm_run_ex(ftlm_block* b, int32_t R, int32_t steps, uint64_t seed, int32_t storage, int32_t dist,
                 double* alpha, double* beta, int32_t* nsteps, void* stream, ftlm_run_info* info);
 
+/* One job of ftlm_run_fused: R chains of `steps` Lanczos steps on a block. */
+typedef struct ftlm_fused_job {
+  ftlm_block* block;
+  int32_t R;               /* 1..32 */
+  int32_t steps;
+  uint64_t seed;
+  int32_t storage;         /* FTLM_F64 or FTLM_F32 */
+  int32_t dist;            /* enum ftlm_dist */
+  int32_t first_chain;     /* chain r of the job has the key of chain first_chain + r of
+                              ftlm_run on the same block (0: the keys of ftlm_run) */
+  int32_t reserved;
+  double* alpha;           /* host outputs as in ftlm_run: R x steps */
+  double* beta;            /* R x steps */
+  int32_t* nsteps;         /* R */
+} ftlm_fused_job;
+
+/* Fused small-block Lanczos (Sections 2.2 and 3; the persistent form of the
+ * batched recurrence for many small blocks): one workgroup of the device runs
+ * every step of one job, i.e. the start vectors, the H.V with the Lanczos
+ * epilogue, alpha, the update and beta, with workgroup barriers between the
+ * phases, and one launch per kernel shape covers all n jobs.  The recurrence,
+ * the keys of the start vectors and the stopping rule are those of ftlm_run;
+ * the FP64 sums run over one workgroup in a fixed order (deterministic, equal
+ * to ftlm_run's results up to rounding).  Each job's block must use the entry
+ * table (FTLM_HV_ENTRIES or AUTO resolved to it), have its irrep tables fit in
+ * LDS and not force the padded layout; otherwise FTLM_ERR_INVALID_ARG.  A job
+ * works through all of its block's representatives with one workgroup, so it
+ * pays only for blocks of up to a few thousand representatives: larger ones
+ * belong to ftlm_run.  Blocks may repeat across jobs.  Device scratch
+ * (2 D R vectors per job) is allocated per call.  Synchronous. */
+int ftlm_run_fused(const ftlm_fused_job* jobs, int32_t n, void* stream);
+
 /* Host FP64: eigenvalues theta (ascending) and weights w_k = (first
  * eigenvector component)^2 of the n x n tridiagonal with diagonal alpha and
  * off-diagonal beta[0..n-2] (Section 2.2).  n <= 4096. */
@@ -308,8 +340,23 @@ int ftlm_observables(const ftlm_ritz* blocks, int32_t nblocks, const double* T, 
  * ftlm_observables over all blocks.  Uses the library's own irreps (real type
  * required).  Chain r of block (2M, irrep) has the key of ftlm_run, so a
  * block's coefficients equal those of ftlm_run on that block with the same
- * chains per run.  Blocks run one after another on a stream of the library;
- * the sector tables of one M are freed before the next.  Synchronous. */
+ * chains per run (to rounding where the fused engine runs the block: its
+ * reductions sum in another fixed order).
+ *
+ * Engines: sectors with few representatives (at most fused_max_rounds
+ * representatives per lane group of one workgroup; 0 = the library default
+ * of 8) run in the fused small-block kernel: one workgroup does every
+ * Lanczos step of one block job (R chains, or chains_per_run of them), and
+ * all such jobs of the campaign go out as one batch on a second stream of
+ * the library.  The blocks of larger sectors run one after another with the
+ * per-step kernels (the steps replay a captured graph), overlapping the
+ * batch.  FTLM_ENGINE_STEPS forces the per-step kernels everywhere,
+ * FTLM_ENGINE_FUSED the fused kernel wherever it applies (FP64 or FP32
+ * storage, entry-table H.V, irrep tables within LDS, at most 32 chains per
+ * job).  The sector tables of a large M are freed before the next M.
+ * Synchronous. */
+enum ftlm_engine { FTLM_ENGINE_AUTO = 0, FTLM_ENGINE_STEPS = 1, FTLM_ENGINE_FUSED = 2 };
+
 typedef struct ftlm_campaign_opts {
   int32_t R;               /* chains per block */
   int32_t steps;           /* Lanczos steps per chain */
@@ -322,10 +369,13 @@ typedef struct ftlm_campaign_opts {
   int32_t chains_per_run;  /* 0: all R chains share one H.V launch per step; k: runs of k chains
                               (1 = the plain single-vector path) */
   double g;                /* g factor of chi */
+  int32_t engine;          /* enum ftlm_engine */
+  int32_t fused_max_rounds;/* automatic engine choice (0: default) */
 } ftlm_campaign_opts;
 
 typedef struct ftlm_campaign_stats {
-  int32_t sectors, blocks, empty_blocks, reserved;
+  int32_t sectors, blocks, empty_blocks;
+  int32_t fused_blocks;    /* blocks run by the fused small-block kernel */
   uint64_t rows;           /* sum of block dimensions */
   uint64_t products;       /* H.v products over all chains */
   uint64_t work;           /* sum over chains of D x products: basis elements x vectors */

@@ -18,6 +18,7 @@ RADEMACHER, GAUSSIAN = 0, 1
 HV_AUTO, HV_ENTRIES, HV_ONTHEFLY = 0, 1, 2
 LAYOUT_AUTO, LAYOUT_BLOCK, LAYOUT_PADDED = 0, 1, 2
 ENTRIES_AUTO, ENTRIES_WIDE, ENTRIES_COMPACT = 0, 1, 2
+ENGINE_AUTO, ENGINE_STEPS, ENGINE_FUSED = 0, 1, 2
 
 STATUS = {
     0: "OK", -1: "INVALID_ARG", -2: "NOT_A_PERMUTATION", -3: "GROUP_TOO_LARGE",
@@ -68,11 +69,12 @@ class HvStats(C.Structure):
 class CampaignOpts(C.Structure):
     _fields_ = [("R", C.c_int32), ("steps", C.c_int32), ("seed", C.c_uint64), ("storage", C.c_int32),
                 ("dist", C.c_int32), ("all_M", C.c_int32), ("two_M", C.c_int32), ("spin_flip", C.c_int32),
-                ("chains_per_run", C.c_int32), ("g", C.c_double)]
+                ("chains_per_run", C.c_int32), ("g", C.c_double), ("engine", C.c_int32),
+                ("fused_max_rounds", C.c_int32)]
 
 
 class CampaignStats(C.Structure):
-    _fields_ = [("sectors", C.c_int32), ("blocks", C.c_int32), ("empty_blocks", C.c_int32), ("reserved", C.c_int32),
+    _fields_ = [("sectors", C.c_int32), ("blocks", C.c_int32), ("empty_blocks", C.c_int32), ("fused_blocks", C.c_int32),
                 ("rows", C.c_uint64), ("products", C.c_uint64), ("work", C.c_uint64),
                 ("seconds_build", C.c_double), ("seconds_lanczos", C.c_double), ("seconds_thermo", C.c_double),
                 ("seconds_total", C.c_double)]
@@ -80,6 +82,12 @@ class CampaignStats(C.Structure):
 
 class RunInfo(C.Structure):
     _fields_ = [("layout", C.c_int32), ("hv_launches", C.c_int32), ("rows", C.c_uint64), ("hv_ms", C.c_double)]
+
+
+class FusedJob(C.Structure):
+    _fields_ = [("block", C.c_void_p), ("R", C.c_int32), ("steps", C.c_int32), ("seed", C.c_uint64),
+                ("storage", C.c_int32), ("dist", C.c_int32), ("first_chain", C.c_int32), ("reserved", C.c_int32),
+                ("alpha", C.POINTER(C.c_double)), ("beta", C.POINTER(C.c_double)), ("nsteps", C.POINTER(C.c_int32))]
 
 
 class JobDesc(C.Structure):
@@ -129,6 +137,7 @@ SIGNATURES = {
     "ftlm_run": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, F64P, F64P, I32P, VP]),
     "ftlm_run_ex": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, F64P, F64P, I32P, VP,
                               C.POINTER(RunInfo)]),
+    "ftlm_run_fused": (C.c_int, [C.POINTER(FusedJob), C.c_int32, VP]),
     "ftlm_tridiag_ritz": (C.c_int, [F64P, F64P, C.c_int32, F64P, F64P]),
     "ftlm_campaign": (C.c_int, [C.POINTER(Cluster), I32P, C.c_int32, C.POINTER(CampaignOpts), F64P, C.c_int32,
                                 F64P, F64P, F64P, F64P, C.POINTER(CampaignStats)]),

@@ -203,6 +203,27 @@ class Block:
         return alpha, beta, ns
 
 
+def run_fused(jobs, stream=None):
+    """ftlm_run_fused: the fused small-block Lanczos kernel over many jobs.
+
+    jobs: sequence of dicts with keys block, R, steps, seed and optionally
+    storage (F64), dist (RADEMACHER), first_chain (0).  Returns one
+    (alpha, beta, nsteps) triple per job, as Block.ftlm does."""
+    out = []
+    arr = (L.FusedJob * max(len(jobs), 1))()
+    for i, j in enumerate(jobs):
+        R, steps = int(j["R"]), int(j["steps"])
+        alpha = np.zeros((R, steps))
+        beta = np.zeros((R, steps))
+        ns = np.zeros(R, np.int32)
+        out.append((alpha, beta, ns))
+        arr[i] = L.FusedJob(j["block"]._h, R, steps, C.c_uint64(j["seed"]), int(j.get("storage", F64)),
+                            int(j.get("dist", RADEMACHER)), int(j.get("first_chain", 0)), 0,
+                            alpha.ctypes.data_as(L.F64P), beta.ctypes.data_as(L.F64P), ns.ctypes.data_as(L.I32P))
+    check(lib().ftlm_run_fused(arr, len(jobs), L.stream_handle(stream) if stream is not None else None))
+    return out
+
+
 def tridiag_ritz(alpha, beta):
     alpha = np.ascontiguousarray(alpha, dtype=np.float64)
     beta = np.ascontiguousarray(beta, dtype=np.float64)
@@ -255,13 +276,17 @@ __all__ = ["Group", "Sector", "Block", "tridiag_ritz", "ritz_from_run", "observa
 
 
 def campaign(cluster, gens, two_s, R, steps, seed, T, storage=F64, dist=RADEMACHER, all_M=True, two_M=0,
-             spin_flip=False, chains_per_run=0, g=1.0):
-    """Whole-cluster FTLM (ftlm_campaign): E, C, chi, logZ on T and the run statistics."""
+             spin_flip=False, chains_per_run=0, g=1.0, engine=0, fused_max_rounds=0):
+    """Whole-cluster FTLM (ftlm_campaign): E, C, chi, logZ on T and the run statistics.
+
+    engine: ENGINE_AUTO (fused small-block kernel for sectors of few
+    representatives, per-step kernels otherwise), ENGINE_STEPS or ENGINE_FUSED."""
     T = np.ascontiguousarray(T, dtype=np.float64)
     cl = L.make_cluster(cluster.N, two_s, cluster.bonds, cluster.J)
     gens = np.ascontiguousarray(np.asarray(gens, dtype=np.int32).reshape(-1, cluster.N))
     o = L.CampaignOpts(int(R), int(steps), C.c_uint64(seed), int(storage), int(dist), 1 if all_M else 0,
-                       int(two_M), 1 if spin_flip else 0, int(chains_per_run), float(g))
+                       int(two_M), 1 if spin_flip else 0, int(chains_per_run), float(g), int(engine),
+                       int(fused_max_rounds))
     out = [np.empty(len(T)) for _ in range(4)]
     st = L.CampaignStats()
     check(lib().ftlm_campaign(C.byref(cl), gens.ctypes.data_as(L.I32P), len(gens), C.byref(o),

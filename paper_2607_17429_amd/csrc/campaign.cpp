@@ -1,9 +1,11 @@
 // Whole-cluster FTLM (paper Sections 2.2, 3 and 4): every M >= 0 sector and
 // every irrep block (optionally G x Z2 at M = 0), R Lanczos chains per block,
 // Ritz data per chain, and the thermal sums of Eqs. (4)-(7), (14) over all of
-// them.  Blocks run one after another on one non-blocking stream of the
-// library (Lanczos steps replay a captured graph); the sector tables of one M
-// are shared by its blocks and freed before the next M.
+// them.  Sectors of few representatives go to the fused small-block kernel
+// (one workgroup per block job, all such jobs in one batch launched on a
+// second stream); the blocks of larger sectors run one after another with the
+// per-step kernels (Lanczos steps replay a captured graph), overlapping the
+// batch.  The sector tables of one large M are freed before the next M.
 #include <chrono>
 #include <cstring>
 #include <vector>
@@ -13,6 +15,10 @@
 namespace ftlm {
 
 namespace {
+// fused kernel: largest representative rounds per lane group and step for
+// which a sector's blocks go to the fused batch under FTLM_ENGINE_AUTO
+constexpr uint64_t kFusedMaxRounds = 8;
+
 double secs(std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
   return std::chrono::duration<double>(b - a).count();
 }
@@ -30,7 +36,8 @@ void run_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, co
   auto G = std::make_shared<Group>(build_group(cl->N, gens, ngens));
   compute_irreps(*G);
   if (!G->all_real) fail(FTLM_ERR_COMPLEX_IRREP_UNSUPPORTED, "group has irreps that are not of real type");
-  hipStream_t stream = nullptr;
+  // per-step kernels on `stream`; batches of fused small-block jobs on `wstream`
+  hipStream_t stream = nullptr, wstream = nullptr;
   FTLM_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
   struct StreamGuard {
     hipStream_t s;
@@ -41,6 +48,8 @@ void run_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, co
       }
     }
   } guard{stream};
+  FTLM_HIP(hipStreamCreateWithFlags(&wstream, hipStreamNonBlocking));
+  StreamGuard wguard{wstream};
   AllocStreamScope scope(stream);
 
   // Ritz data of every block (kept until the sums)
@@ -48,7 +57,7 @@ void run_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, co
     int two_M = 0, d = 0, R = 0, ld = 0;
     uint64_t D = 0;
     std::vector<int32_t> n;
-    std::vector<double> theta, w;
+    std::vector<double> alpha, beta, theta, w;
   };
   std::vector<BlockRitz> all;
   const int Ns2 = cl->N * cl->two_s;  // 2 N s
@@ -58,6 +67,40 @@ void run_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, co
   else
     twoMs.push_back(o->two_M);
   const int per_run = o->chains_per_run == 0 ? o->R : std::min(o->chains_per_run, o->R);
+  const uint64_t max_rounds = o->fused_max_rounds > 0 ? (uint64_t)o->fused_max_rounds : kFusedMaxRounds;
+
+  // Fused jobs wait in `pending` (their blocks kept alive) and go out as one
+  // batch when a sector of large blocks starts, so the two streams overlap,
+  // when they hold much memory, or at the end.
+  std::vector<WgTask> pending;
+  std::vector<std::unique_ptr<Block>> pending_blocks, inflight_blocks;
+  std::unique_ptr<WgBatch> inflight;
+  int64_t pending_bytes = 0;
+  const void* pending_sector = nullptr;
+  auto finish_inflight = [&] {
+    if (!inflight) return;
+    auto tl = clk::now();
+    inflight->finish();
+    inflight.reset();
+    inflight_blocks.clear();
+    S.seconds_lanczos += secs(tl, clk::now());
+  };
+  auto launch_pending = [&] {
+    if (pending.empty()) return;
+    finish_inflight();
+    auto tl = clk::now();
+    inflight = std::make_unique<WgBatch>(std::move(pending), wstream);
+    inflight_blocks = std::move(pending_blocks);
+    pending.clear();
+    pending_blocks.clear();
+    pending_bytes = 0;
+    pending_sector = nullptr;
+    S.seconds_lanczos += secs(tl, clk::now());
+  };
+  size_t free_b = 0, total_b = 0;
+  FTLM_HIP(hipMemGetInfo(&free_b, &total_b));
+  const int64_t pending_limit = (int64_t)(free_b / 8);
+
   for (int two_M : twoMs) {
     auto tb = clk::now();
     ftlm_opts so{};
@@ -67,6 +110,11 @@ void run_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, co
     S.seconds_build += secs(tb, clk::now());
     if (sec->D_M == 0) continue;
     S.sectors += 1;
+    // every block of a sector spans the sector's representatives, so the
+    // fused kernel's serial length is a property of the sector
+    const bool fused_sector = o->engine == FTLM_ENGINE_FUSED ||
+                              (o->engine == FTLM_ENGINE_AUTO && wg_rounds(sec->n_reps, per_run) <= max_rounds);
+    if (!fused_sector) launch_pending();
     const int nirr = (int)G->irreps.size() * (sec->zflip ? 2 : 1);
     for (int irrep = 0; irrep < nirr; ++irrep) {
       tb = clk::now();
@@ -85,37 +133,69 @@ void run_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, co
       br.R = o->R;
       br.ld = o->steps;
       br.n.assign(o->R, 0);
-      br.theta.assign((size_t)o->R * o->steps, 0.0);
-      br.w.assign((size_t)o->R * o->steps, 0.0);
-      std::vector<double> alpha((size_t)o->R * o->steps), beta((size_t)o->R * o->steps);
-      auto tl = clk::now();
+      br.alpha.assign((size_t)o->R * o->steps, 0.0);
+      br.beta.assign((size_t)o->R * o->steps, 0.0);
       // chains in groups of per_run (all R at once unless a single-vector
       // comparison asks otherwise); chain r keeps its key (seed, 2M, irrep, row, r)
-      for (int r0 = 0; r0 < o->R; r0 += per_run) {
-        const int rr = std::min(per_run, o->R - r0);
-        LanczosRun L(*blk, rr, o->steps, o->seed, o->storage, o->dist);
-        L.first_chain = r0;
-        L.allocate();
-        L.enqueue(stream);
-        L.download(stream, alpha.data() + (size_t)r0 * o->steps, beta.data() + (size_t)r0 * o->steps,
-                   br.n.data() + r0);
-        FTLM_HIP(hipStreamSynchronize(stream));
+      if (fused_sector && o->engine != FTLM_ENGINE_STEPS && wg_supported(*blk, per_run, o->storage)) {
+        S.fused_blocks += 1;
+        for (int r0 = 0; r0 < o->R; r0 += per_run) {
+          const int rr = std::min(per_run, o->R - r0);
+          pending.push_back(WgTask{blk.get(), rr, o->steps, o->storage, o->dist, r0, o->seed,
+                                   br.alpha.data() + (size_t)r0 * o->steps, br.beta.data() + (size_t)r0 * o->steps,
+                                   br.n.data() + r0});
+        }
+        pending_bytes += 2 * (int64_t)blk->D * o->R * (o->storage == FTLM_F64 ? 8 : 4) +
+                         (pending_sector == sec.get() ? blk->device_bytes() - sec->device_bytes()
+                                                      : blk->device_bytes());
+        pending_sector = sec.get();
+        pending_blocks.push_back(std::move(blk));
+      } else {
+        auto tl = clk::now();
+        for (int r0 = 0; r0 < o->R; r0 += per_run) {
+          const int rr = std::min(per_run, o->R - r0);
+          LanczosRun L(*blk, rr, o->steps, o->seed, o->storage, o->dist);
+          L.first_chain = r0;
+          L.allocate();
+          L.enqueue(stream);
+          L.download(stream, br.alpha.data() + (size_t)r0 * o->steps, br.beta.data() + (size_t)r0 * o->steps,
+                     br.n.data() + r0);
+          FTLM_HIP(hipStreamSynchronize(stream));
+        }
+        S.seconds_lanczos += secs(tl, clk::now());
       }
-      S.seconds_lanczos += secs(tl, clk::now());
-      auto tt = clk::now();
-      for (int r = 0; r < o->R; ++r) {
-        const int n = br.n[r];
-        S.products += (uint64_t)n;
-        S.work += (uint64_t)n * blk->D;
-        if (n > 0)
-          tridiag_ritz(alpha.data() + (size_t)r * o->steps, beta.data() + (size_t)r * o->steps, n,
-                       br.theta.data() + (size_t)r * o->steps, br.w.data() + (size_t)r * o->steps);
-      }
-      S.seconds_thermo += secs(tt, clk::now());
       all.push_back(std::move(br));
     }
+    if (!fused_sector) finish_inflight();
+    if (pending_bytes > pending_limit) launch_pending();
   }
+  launch_pending();
+  finish_inflight();
+
   auto tt = clk::now();
+  for (auto& br : all) {
+    for (int r = 0; r < br.R; ++r) {
+      const int n = br.n[r];
+      S.products += (uint64_t)n;
+      S.work += (uint64_t)n * br.D;
+    }
+  }
+  // Ritz data of every chain (independent problems, spread over host threads)
+  std::vector<std::pair<size_t, int>> chains;
+  for (size_t b = 0; b < all.size(); ++b) {
+    all[b].theta.assign((size_t)all[b].R * all[b].ld, 0.0);
+    all[b].w.assign((size_t)all[b].R * all[b].ld, 0.0);
+    for (int r = 0; r < all[b].R; ++r)
+      if (all[b].n[r] > 0) chains.push_back({b, r});
+  }
+  parallel_for((int64_t)chains.size(), 16, [&](int64_t i) {
+    BlockRitz& br = all[chains[i].first];
+    const size_t o = (size_t)chains[i].second * br.ld;
+    tridiag_ritz(br.alpha.data() + o, br.beta.data() + o, br.n[chains[i].second], br.theta.data() + o,
+                 br.w.data() + o);
+  });
+  S.seconds_thermo += secs(tt, clk::now());
+  tt = clk::now();
   std::vector<ftlm_ritz> rz;
   for (auto& b : all)
     rz.push_back(ftlm_ritz{b.two_M, b.d, b.D, b.R, b.ld, b.n.data(), b.theta.data(), b.w.data()});

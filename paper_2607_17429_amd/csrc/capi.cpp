@@ -262,6 +262,32 @@ int ftlm_run_ex(ftlm_block* b, int32_t R, int32_t steps, uint64_t seed, int32_t 
   });
 }
 
+int ftlm_run_fused(const ftlm_fused_job* jobs, int32_t n, void* stream) {
+  return guarded([&] {
+    if (n < 0 || (n > 0 && !jobs)) fail(FTLM_ERR_INVALID_ARG, "bad job list");
+    std::vector<WgTask> tasks;
+    for (int32_t i = 0; i < n; ++i) {
+      const ftlm_fused_job& j = jobs[i];
+      if (!j.block) fail(FTLM_ERR_INVALID_ARG, "null block");
+      if (j.R < 1 || j.R > 32 || j.steps <= 0) fail(FTLM_ERR_INVALID_ARG, "need 1 <= R <= 32 and steps > 0");
+      if (j.first_chain < 0) fail(FTLM_ERR_INVALID_ARG, "first_chain must be >= 0");
+      if (j.block->b->D == 0) {  // empty block: no steps
+        if (!j.alpha || !j.beta || !j.nsteps) fail(FTLM_ERR_INVALID_ARG, "null output");
+        std::memset(j.alpha, 0, sizeof(double) * (size_t)j.R * j.steps);
+        std::memset(j.beta, 0, sizeof(double) * (size_t)j.R * j.steps);
+        std::memset(j.nsteps, 0, sizeof(int32_t) * (size_t)j.R);
+        continue;
+      }
+      if (!wg_supported(*j.block->b, j.R, j.storage))
+        fail(FTLM_ERR_INVALID_ARG, "job " + std::to_string(i) + " does not fit the fused kernel");
+      tasks.push_back(WgTask{j.block->b.get(), j.R, j.steps, j.storage, j.dist, j.first_chain, j.seed, j.alpha,
+                             j.beta, j.nsteps});
+    }
+    WgBatch batch(std::move(tasks), (hipStream_t)stream);
+    batch.finish();
+  });
+}
+
 int ftlm_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, const ftlm_campaign_opts* opts,
                   const double* T, int32_t nT, double* E, double* C, double* chi, double* logZ,
                   ftlm_campaign_stats* stats) {

@@ -2,9 +2,13 @@
 // storage, HIP status checks.
 #pragma once
 
+#include <algorithm>
 #include <cstdint>
+#include <exception>
+#include <mutex>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include <hip/hip_runtime.h>
@@ -108,5 +112,32 @@ struct DevBuf {
     return h;
   }
 };
+
+// fn(i) for 0 <= i < n on up to 16 host threads (static contiguous ranges;
+// results written per index are independent of the split).  The first
+// exception thrown by any fn is rethrown on the calling thread.
+template <typename F>
+void parallel_for(int64_t n, int64_t min_per_thread, F fn) {
+  const int64_t hw = std::max<int64_t>(1, (int64_t)std::thread::hardware_concurrency());
+  const int64_t nt = std::max<int64_t>(1, std::min<int64_t>({hw, 16, n / std::max<int64_t>(min_per_thread, 1)}));
+  if (nt <= 1) {
+    for (int64_t i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::exception_ptr err;
+  std::mutex mu;
+  std::vector<std::thread> th;
+  for (int64_t t = 0; t < nt; ++t)
+    th.emplace_back([&, t] {
+      try {
+        for (int64_t i = n * t / nt; i < n * (t + 1) / nt; ++i) fn(i);
+      } catch (...) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!err) err = std::current_exception();
+      }
+    });
+  for (auto& x : th) x.join();
+  if (err) std::rethrow_exception(err);
+}
 
 }  // namespace ftlm

@@ -5,11 +5,14 @@
 // A packed label stores site k's digit a_k = m_k + s in bits [k*b, k*b+b),
 // b = ceil(log2(2s+1)).  Comparing packed labels as integers gives the same
 // order as comparing the labels n of Eq. (2), so "smallest label in the
-// orbit" is the smallest packed word.
+// orbit" is the smallest packed word.  Also the start-vector generator of the
+// Lanczos chains.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <cstdint>
+
+#include "ftlm.h"
 
 namespace ftlm {
 namespace dev {
@@ -220,6 +223,22 @@ __device__ __forceinline__ uint64_t mix64(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
   z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
   return z ^ (z >> 31);
+}
+
+// Start-vector element j of the chain keyed by key (SplitMix64, Steele, Lea,
+// Flood 2014): Rademacher takes the sign of the top bit of the (j+1)-th output;
+// Gaussian draws outputs 2j+1, 2j+2 through the Box-Muller transform.
+constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+__device__ __forceinline__ double start_value(uint64_t key, uint64_t j, int dist) {
+  if (dist == FTLM_RADEMACHER) {
+    const uint64_t x = mix64(key + (j + 1) * kGamma);
+    return (x >> 63) ? -1.0 : 1.0;
+  }
+  const uint64_t x1 = mix64(key + (2 * j + 1) * kGamma);
+  const uint64_t x2 = mix64(key + (2 * j + 2) * kGamma);
+  const double u1 = ((double)(x1 >> 11) + 1.0) * 0x1.0p-53;
+  const double u2 = (double)(x2 >> 11) * 0x1.0p-53;
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
 }
 
 }  // namespace dev

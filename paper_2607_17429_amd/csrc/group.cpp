@@ -16,6 +16,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <limits>
 #include <map>
 #include <string>
 #include <unordered_map>
@@ -145,53 +146,103 @@ Group build_group(int N, const int32_t* gens, int ngens) {
   return G;
 }
 
-std::vector<double> jacobi_eigh(std::vector<double>& A, int n, std::vector<double>& V) {
+// Symmetric eigenproblem A = V diag(w) V^T (w ascending, eigenvectors in the
+// columns of V; A is overwritten): Householder reduction to tridiagonal form
+// with the reflections accumulated into V, then implicit QL iterations with
+// Wilkinson-type shifts whose rotations are applied to the rows of V
+// (Golub and Van Loan, Matrix Computations, Sections 8.3.1 and 8.3.3).
+std::vector<double> sym_eigh(std::vector<double>& A, int n, std::vector<double>& V) {
+  auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
   V.assign((size_t)n * n, 0.0);
   for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
-  auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
-  double scale = 0.0;
-  for (size_t i = 0; i < A.size(); ++i) scale = std::max(scale, std::fabs(A[i]));
-  if (scale == 0.0) scale = 1.0;
-  for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0;
-    for (int p = 0; p < n; ++p)
-      for (int q = p + 1; q < n; ++q) off += a(p, q) * a(p, q);
-    if (std::sqrt(off) <= 1e-15 * scale * n) break;
-    for (int p = 0; p < n; ++p) {
-      for (int q = p + 1; q < n; ++q) {
-        double apq = a(p, q);
-        if (std::fabs(apq) <= 1e-300) continue;
-        // rotation that zeroes a_pq: tan(phi) = t solves t^2 + 2 theta t - 1 = 0
-        double theta = (a(q, q) - a(p, p)) / (2.0 * apq);
-        double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-        double c = 1.0 / std::sqrt(t * t + 1.0);
-        double s = t * c;
-        for (int k = 0; k < n; ++k) {
-          double akp = a(k, p), akq = a(k, q);
-          a(k, p) = c * akp - s * akq;
-          a(k, q) = s * akp + c * akq;
-        }
-        for (int k = 0; k < n; ++k) {
-          double apk = a(p, k), aqk = a(q, k);
-          a(p, k) = c * apk - s * aqk;
-          a(q, k) = s * apk + c * aqk;
-        }
-        for (int k = 0; k < n; ++k) {
-          double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
-          V[(size_t)k * n + p] = c * vkp - s * vkq;
-          V[(size_t)k * n + q] = s * vkp + c * vkq;
-        }
-      }
+  std::vector<double> v(n), p(n), q(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    // reflection H = I - beta u u^T on rows / columns k+1..n-1 zeroing a(k+2.., k)
+    double xn = 0.0;
+    for (int i = k + 1; i < n; ++i) xn += a(i, k) * a(i, k);
+    xn = std::sqrt(xn);
+    if (xn == 0.0) continue;
+    const double al = a(k + 1, k) > 0 ? -xn : xn;
+    for (int i = k + 1; i < n; ++i) v[i] = a(i, k);
+    v[k + 1] -= al;
+    double vv = 0.0;
+    for (int i = k + 1; i < n; ++i) vv += v[i] * v[i];
+    if (vv == 0.0) continue;
+    const double beta = 2.0 / vv;
+    // p = beta A v, q = p - (beta v^T p / 2) v, A -= v q^T + q v^T
+    double vp = 0.0;
+    for (int i = k + 1; i < n; ++i) {
+      double s = 0.0;
+      for (int j = k + 1; j < n; ++j) s += a(i, j) * v[j];
+      p[i] = beta * s;
+      vp += v[i] * p[i];
+    }
+    const double K = 0.5 * beta * vp;
+    for (int i = k + 1; i < n; ++i) q[i] = p[i] - K * v[i];
+    for (int i = k + 1; i < n; ++i)
+      for (int j = k + 1; j < n; ++j) a(i, j) -= v[i] * q[j] + q[i] * v[j];
+    a(k + 1, k) = a(k, k + 1) = al;
+    for (int i = k + 2; i < n; ++i) a(i, k) = a(k, i) = 0.0;
+    // V <- V H
+    for (int r = 0; r < n; ++r) {
+      double s = 0.0;
+      for (int j = k + 1; j < n; ++j) s += V[(size_t)r * n + j] * v[j];
+      s *= beta;
+      for (int j = k + 1; j < n; ++j) V[(size_t)r * n + j] -= s * v[j];
     }
   }
-  std::vector<double> w(n);
-  for (int i = 0; i < n; ++i) w[i] = a(i, i);
+  std::vector<double> d(n), e(n, 0.0);
+  for (int i = 0; i < n; ++i) d[i] = a(i, i);
+  for (int i = 0; i + 1 < n; ++i) e[i] = a(i + 1, i);
+  const double eps = std::numeric_limits<double>::epsilon();
+  for (int l = 0; l < n; ++l) {
+    for (int iter = 0;; ++iter) {
+      int m = l;
+      for (; m < n - 1; ++m)
+        if (std::fabs(e[m]) <= eps * (std::fabs(d[m]) + std::fabs(d[m + 1]))) break;
+      if (m == l) break;
+      if (iter > 200) fail(FTLM_ERR_IRREPS_FAILED, "symmetric QL did not converge");
+      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+      double r = std::sqrt(g * g + 1.0);
+      g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+      double s = 1.0, c = 1.0, pp = 0.0;
+      bool split = false;
+      for (int i = m - 1; i >= l; --i) {
+        const double f = s * e[i], b = c * e[i];
+        r = std::sqrt(f * f + g * g);
+        e[i + 1] = r;
+        if (r == 0.0) {
+          d[i + 1] -= pp;
+          e[m] = 0.0;
+          split = true;
+          break;
+        }
+        s = f / r;
+        c = g / r;
+        g = d[i + 1] - pp;
+        r = (d[i] - g) * s + 2.0 * c * b;
+        pp = s * r;
+        d[i + 1] = g + pp;
+        g = c * r - b;
+        for (int k = 0; k < n; ++k) {
+          double* row = &V[(size_t)k * n];
+          const double x1 = row[i + 1];
+          row[i + 1] = s * row[i] + c * x1;
+          row[i] = c * row[i] - s * x1;
+        }
+      }
+      if (split) continue;
+      d[l] -= pp;
+      e[l] = g;
+      e[m] = 0.0;
+    }
+  }
   std::vector<int> idx(n);
   for (int i = 0; i < n; ++i) idx[i] = i;
-  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return w[x] < w[y]; });
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return d[x] < d[y]; });
   std::vector<double> ws(n), Vs((size_t)n * n);
   for (int j = 0; j < n; ++j) {
-    ws[j] = w[idx[j]];
+    ws[j] = d[idx[j]];
     for (int i = 0; i < n; ++i) Vs[(size_t)i * n + j] = V[(size_t)i * n + idx[j]];
   }
   V.swap(Vs);
@@ -261,7 +312,7 @@ void compute_irreps(Group& G) {
       for (int y = 0; y < n; ++y)
         S[(size_t)x * n + y] = c[G.idx_mul(G.inv[x], y)] + c[G.idx_mul(G.inv[y], x)];
     std::vector<double> Q;
-    std::vector<double> w = jacobi_eigh(S, n, Q);
+    std::vector<double> w = sym_eigh(S, n, Q);
     double spread = w.back() - w.front();
     double tol = 1e-7 * std::max(1.0, spread);
     std::vector<std::pair<int, int>> clusters;

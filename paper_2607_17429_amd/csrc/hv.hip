@@ -149,15 +149,13 @@ std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dt
   return out;
 }
 
-void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t st,
-                 const LanczosEpilogue* lz, int gl, bool pad) {
+template <typename T>
+void hv_setup(const Block& b, int nvec, int64_t ld, int gl, bool pad, const LanczosEpilogue* lz, LaunchCfg& c,
+              HvArgs<T>& a) {
   const Sector& s = *b.sec;
-  if (nvec <= 0 || ld < nvec) fail(FTLM_ERR_INVALID_ARG, "need 0 < nvec <= ld");
-  if (b.D == 0 || s.n_reps == 0) return;
-  if (!X || !Y) fail(FTLM_ERR_INVALID_ARG, "null vector");
   const bool otf = s.hv_mode == FTLM_HV_ONTHEFLY;
   const Layout L = choose_layout(nvec, otf, gl);
-  LaunchCfg c{};
+  c = LaunchCfg{};
   c.grid = hv_grid(b, L);
   c.otf = otf;
   c.wide = s.wide;
@@ -193,7 +191,7 @@ void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
   o = align16(o + (uint64_t)s.nbonds * 2 * 4);
   c.slds = (o - base) <= kSmallLdsBudget && o <= kLdsLimit;
   c.shm = c.slds ? o : base;
-  auto fill = [&](auto& a) {
+  {
     a.reps = s.d_reps.p;
     a.row_ptr = s.d_row_ptr.p;
     a.entries = s.d_entries.p;
@@ -247,7 +245,23 @@ void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
     a.tab_words = (uint32_t)tab_words;
     a.scal = lz ? lz->scal : nullptr;
     a.partials = lz ? lz->partials : nullptr;
-  };
+  }
+}
+
+template void hv_setup<double>(const Block&, int, int64_t, int, bool, const LanczosEpilogue*, LaunchCfg&,
+                               HvArgs<double>&);
+template void hv_setup<float>(const Block&, int, int64_t, int, bool, const LanczosEpilogue*, LaunchCfg&,
+                              HvArgs<float>&);
+template void hv_setup<_Float16>(const Block&, int, int64_t, int, bool, const LanczosEpilogue*, LaunchCfg&,
+                                 HvArgs<_Float16>&);
+
+void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t st,
+                 const LanczosEpilogue* lz, int gl, bool pad) {
+  const Sector& s = *b.sec;
+  if (nvec <= 0 || ld < nvec) fail(FTLM_ERR_INVALID_ARG, "need 0 < nvec <= ld");
+  if (b.D == 0 || s.n_reps == 0) return;
+  if (!X || !Y) fail(FTLM_ERR_INVALID_ARG, "null vector");
+  LaunchCfg c{};
   HvArgs<double> a64{};
   HvArgs<float> a32{};
   HvArgs<_Float16> a16{};
@@ -255,17 +269,17 @@ void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
   const HvArgs<float>* p32 = nullptr;
   const HvArgs<_Float16>* p16 = nullptr;
   if (dtype == FTLM_F64) {
-    fill(a64);
+    hv_setup(b, nvec, ld, gl, pad, lz, c, a64);
     a64.X = (const double*)X;
     a64.Y = (double*)Y;
     p64 = &a64;
   } else if (dtype == FTLM_F32) {
-    fill(a32);
+    hv_setup(b, nvec, ld, gl, pad, lz, c, a32);
     a32.X = (const float*)X;
     a32.Y = (float*)Y;
     p32 = &a32;
   } else if (dtype == FTLM_F16) {
-    fill(a16);
+    hv_setup(b, nvec, ld, gl, pad, lz, c, a16);
     a16.X = (const _Float16*)X;
     a16.Y = (_Float16*)Y;
     p16 = &a16;

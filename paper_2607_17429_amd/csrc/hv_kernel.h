@@ -132,50 +132,41 @@ __device__ __forceinline__ const E* stage(const E* src, uint32_t count, char* ds
   return dst;
 }
 
-template <typename T, int DG, int VPL, bool OTF, int NCH, bool LDS_TAB, bool SLDS>
-__global__ void __launch_bounds__(kThreads)
-__attribute__((amdgpu_waves_per_eu(DG * VPL <= FTLM_HV_FLOOR_WIDTH ? FTLM_HV_WAVES_PER_EU : 1)))
-k_hv(HvArgs<T> a) {
-  using W = word_t<NCH>;
-  extern __shared__ uint64_t smem_raw[];
-  char* sm = (char*)smem_raw;
-  const bool EPI = a.partials != nullptr;
-  const W* tab = nullptr;
-  if constexpr (OTF) tab = LDS_TAB ? stage<W>((const W*)a.tab, a.tab_words, sm) : (const W*)a.tab;
-  const dev::OrbitTabs<W, NCH> otabs = dev::orbit_tabs<W, NCH>(tab, a.nH, a.nT);
-  const double* rhoT = a.rhoT;
-  const double* Vt = a.V;
-  const double* stabf = a.stabf;
-  const double* Jb = a.J;
-  const double* fac = a.fac;
-  const int32_t* bonds = a.bonds;
-  if constexpr (SLDS) {
-    rhoT = stage<double>(a.rhoT, (uint32_t)a.G * DG * DG, sm + a.o_rho);
-    Vt = stage<double>(a.V, (uint32_t)a.n_stab * DG * DG, sm + a.o_V);
-    stabf = stage<double>(a.stabf, (uint32_t)a.n_stab * 4, sm + a.o_stab);
-    Jb = stage<double>(a.J, (uint32_t)a.nbonds, sm + a.o_J);
-    fac = stage<double>(a.fac, (uint32_t)(2 * a.dloc * a.dloc), sm + a.o_fac);
-    bonds = stage<int32_t>(a.bonds, (uint32_t)(2 * a.nbonds), sm + a.o_bonds);
-  }
-  if constexpr (SLDS || (OTF && LDS_TAB)) __syncthreads();
+struct HvTabs {
+  const double* rhoT;
+  const double* Vt;
+  const double* stabf;
+  const double* Jb;
+  const double* fac;
+  const int32_t* bonds;
+};
 
+// The H.V over the representatives p = slot, slot + slot_stride, ... of one
+// column tile: lane group of GL lanes per representative (see the file text).
+// dot[j] accumulates q_j . w of this lane's column j in the Lanczos epilogue.
+template <typename T, int DG, int VPL, bool OTF, int NCH>
+__device__ __forceinline__ void hv_pass(const HvArgs<T>& a, const HvTabs& tb,
+                                        const dev::OrbitTabs<word_t<NCH>, NCH>& otabs, int tile, int ntiles,
+                                        uint64_t slot, uint64_t slot_stride, double (&dot)[VPL], bool (&vok)[VPL]) {
+  using W = word_t<NCH>;
+  const bool EPI = a.partials != nullptr;
+  const double* rhoT = tb.rhoT;
+  const double* Vt = tb.Vt;
+  const double* stabf = tb.stabf;
+  const double* Jb = tb.Jb;
+  const double* fac = tb.fac;
+  const int32_t* bonds = tb.bonds;
   const int lane = threadIdx.x & 63;
   const int GL = a.GL;
   const int lg = lane & (GL - 1);
   const int gbase = lane - lg;
-  const int vbase = blockIdx.y * a.tile_w + lg;
-  bool vok[VPL];
+  const int vbase = tile * a.tile_w + lg;
 #pragma unroll
   for (int j = 0; j < VPL; ++j) vok[j] = vbase + j * GL < a.nvec;
   // uniform: the whole launch may gather without clamps (see the gather below)
-  const bool dense = a.pad && a.dstride == DG && a.nvec == a.tile_w * (int)gridDim.y && a.tile_w == GL * VPL;
-  const int slots_per_wave = 64 >> a.log2GL;
-  const int waves = blockDim.x >> 6;
-  const uint64_t slot = ((uint64_t)blockIdx.x * waves + (threadIdx.x >> 6)) * slots_per_wave + (lane >> a.log2GL);
-  const uint64_t slot_stride = (uint64_t)gridDim.x * waves * slots_per_wave;
+  const bool dense = a.pad && a.dstride == DG && a.nvec == a.tile_w * ntiles && a.tile_w == GL * VPL;
   const W lmask = (W(1) << a.b) - 1;
   const int ncand = 2 * a.nbonds;
-  double dot[VPL];
 #pragma unroll
   for (int j = 0; j < VPL; ++j) dot[j] = 0.0;
 
@@ -358,6 +349,45 @@ k_hv(HvArgs<T> a) {
       }
     }
   }
+}
+
+template <typename T, int DG, int VPL, bool OTF, int NCH, bool LDS_TAB, bool SLDS>
+__global__ void __launch_bounds__(kThreads)
+__attribute__((amdgpu_waves_per_eu(DG * VPL <= FTLM_HV_FLOOR_WIDTH ? FTLM_HV_WAVES_PER_EU : 1)))
+k_hv(HvArgs<T> a) {
+  using W = word_t<NCH>;
+  extern __shared__ uint64_t smem_raw[];
+  char* sm = (char*)smem_raw;
+  const bool EPI = a.partials != nullptr;
+  const W* tab = nullptr;
+  if constexpr (OTF) tab = LDS_TAB ? stage<W>((const W*)a.tab, a.tab_words, sm) : (const W*)a.tab;
+  const dev::OrbitTabs<W, NCH> otabs = dev::orbit_tabs<W, NCH>(tab, a.nH, a.nT);
+  const double* rhoT = a.rhoT;
+  const double* Vt = a.V;
+  const double* stabf = a.stabf;
+  const double* Jb = a.J;
+  const double* fac = a.fac;
+  const int32_t* bonds = a.bonds;
+  if constexpr (SLDS) {
+    rhoT = stage<double>(a.rhoT, (uint32_t)a.G * DG * DG, sm + a.o_rho);
+    Vt = stage<double>(a.V, (uint32_t)a.n_stab * DG * DG, sm + a.o_V);
+    stabf = stage<double>(a.stabf, (uint32_t)a.n_stab * 4, sm + a.o_stab);
+    Jb = stage<double>(a.J, (uint32_t)a.nbonds, sm + a.o_J);
+    fac = stage<double>(a.fac, (uint32_t)(2 * a.dloc * a.dloc), sm + a.o_fac);
+    bonds = stage<int32_t>(a.bonds, (uint32_t)(2 * a.nbonds), sm + a.o_bonds);
+  }
+  if constexpr (SLDS || (OTF && LDS_TAB)) __syncthreads();
+
+  const HvTabs tb{rhoT, Vt, stabf, Jb, fac, bonds};
+  const int lane = threadIdx.x & 63;
+  const int GL = a.GL;
+  const int slots_per_wave = 64 >> a.log2GL;
+  const int waves = blockDim.x >> 6;
+  const uint64_t slot = ((uint64_t)blockIdx.x * waves + (threadIdx.x >> 6)) * slots_per_wave + (lane >> a.log2GL);
+  const uint64_t slot_stride = (uint64_t)gridDim.x * waves * slots_per_wave;
+  double dot[VPL];
+  bool vok[VPL];
+  hv_pass<T, DG, VPL, OTF, NCH>(a, tb, otabs, (int)blockIdx.y, (int)gridDim.y, slot, slot_stride, dot, vok);
   if (EPI) {
     __shared__ double red[kThreads];
     // one vector slot j at a time: lanes with equal lg hold the same column
@@ -439,4 +469,12 @@ void launch_dg(const HvArgs<double>* a64, const HvArgs<float>* a32, const HvArgs
   }
 
 }  // namespace hvk
+
+// Launch shape, LDS layout and kernel arguments (all but X and Y) of one H.V
+// over nvec vectors of leading dimension ld with gl lanes per representative
+// (0: the default or autotuned layout).
+template <typename T>
+void hv_setup(const Block& b, int nvec, int64_t ld, int gl, bool pad, const LanczosEpilogue* lz, hvk::LaunchCfg& c,
+              hvk::HvArgs<T>& a);
+
 }  // namespace ftlm

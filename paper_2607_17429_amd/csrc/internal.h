@@ -1,6 +1,7 @@
 // Internal objects behind the opaque C handles.
 #pragma once
 
+#include <array>
 #include <atomic>
 #include <cstdint>
 #include <memory>
@@ -165,6 +166,38 @@ struct LanczosRun {
 
 void run_lanczos(Block& b, int R, int steps, uint64_t seed, int storage, int dist, double* alpha,
                  double* beta, int32_t* nsteps, hipStream_t stream, ftlm_run_info* info = nullptr);
+
+// Fused small-block Lanczos: one workgroup runs every step of one block job.
+// wg_supported: the kernel can run R chains of this block in this storage
+// (FP64 or FP32, entry-table H.V, irrep tables in LDS, R <= 32); wg_rounds:
+// representatives per lane group and step in a sector of n_reps
+// representatives, the job's serial length.
+bool wg_supported(const Block& b, int R, int storage);
+uint64_t wg_rounds(uint64_t n_reps, int R);
+struct WgTask {
+  const Block* block;            // must outlive the batch
+  int R, steps, storage, dist, first_chain;
+  uint64_t seed;
+  double* alpha;                 // host outputs: R x steps, R x steps, R
+  double* beta;
+  int32_t* nsteps;
+};
+// A batch of jobs enqueued on one stream at construction (one launch per
+// kernel shape); finish() waits and fills every task's outputs.
+struct WgBatch {
+  std::vector<WgTask> tasks;
+  hipStream_t st = nullptr;
+  DevBuf<uint8_t> arena;
+  std::vector<uint8_t> staging;
+  std::vector<std::array<size_t, 3>> res;
+  size_t up_bytes = 0, out_off = 0, out_bytes = 0;
+  bool launched = false;
+  WgBatch(std::vector<WgTask> tasks, hipStream_t st);
+  WgBatch(const WgBatch&) = delete;
+  WgBatch& operator=(const WgBatch&) = delete;
+  void finish();
+  ~WgBatch();
+};
 
 void tridiag_ritz(const double* alpha, const double* beta, int n, double* theta, double* weight);
 void observables(const ftlm_ritz* blocks, int nb, const double* T, int nT, double g, double* E, double* C,

@@ -28,7 +28,8 @@ namespace ftlm {
 
 namespace {
 
-constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+using dev::kGamma;
+using dev::start_value;
 
 struct Chain {
   double s;       // scale of q_j
@@ -42,18 +43,6 @@ struct Chain {
                   // here, so one captured graph serves every step)
   double sigma;   // power-of-two storage scale (1 unless FP16)
 };
-
-__device__ __forceinline__ double start_value(uint64_t key, uint64_t j, int dist) {
-  if (dist == FTLM_RADEMACHER) {
-    const uint64_t x = dev::mix64(key + (j + 1) * kGamma);
-    return (x >> 63) ? -1.0 : 1.0;
-  }
-  const uint64_t x1 = dev::mix64(key + (2 * j + 1) * kGamma);
-  const uint64_t x2 = dev::mix64(key + (2 * j + 2) * kGamma);
-  const double u1 = ((double)(x1 >> 11) + 1.0) * 0x1.0p-53;
-  const double u2 = (double)(x2 >> 11) * 0x1.0p-53;
-  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586476925286766559 * u2);
-}
 
 // Threads are laid out as (row-in-block r0, chain v) with TB = R * (256 / R)
 // threads per block, so each thread's elements belong to one chain and the

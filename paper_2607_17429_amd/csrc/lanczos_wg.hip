@@ -1,0 +1,195 @@
+// Host side of the fused small-block Lanczos kernel (lanczos_wg.h): which
+// blocks it can run, one device arena per batch of block jobs, jobs grouped by
+// kernel shape (storage type, irrep dimension bucket, vectors per lane, label
+// width) with one launch per group, and the results copied back per job.
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "lanczos_wg.h"
+
+namespace ftlm {
+
+using namespace hvk;
+
+namespace {
+
+// lanes per representative: 4 for up to 4 chains (flip entries of a chunk are
+// fetched together), else 8 with up to 4 vectors per lane
+int wg_lanes(int R) { return R <= 4 ? 4 : 8; }
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t elem_bytes(int storage) { return storage == FTLM_F64 ? 8 : 4; }
+
+struct Shape {
+  int dtype, dgp, vpl;
+  bool wide;
+  bool operator<(const Shape& o) const {
+    return std::tie(dtype, dgp, vpl, wide) < std::tie(o.dtype, o.dgp, o.vpl, o.wide);
+  }
+};
+
+void launch_shape(const Shape& sh, const void* jobs, int n, size_t shm, hipStream_t st) {
+  switch (sh.dgp) {
+    case 1: wg_launch<1>(sh.dtype, sh.vpl, sh.wide, jobs, n, shm, st); break;
+    case 2: wg_launch<2>(sh.dtype, sh.vpl, sh.wide, jobs, n, shm, st); break;
+    case 3: wg_launch<3>(sh.dtype, sh.vpl, sh.wide, jobs, n, shm, st); break;
+    case 4: wg_launch<4>(sh.dtype, sh.vpl, sh.wide, jobs, n, shm, st); break;
+    case 5: wg_launch<5>(sh.dtype, sh.vpl, sh.wide, jobs, n, shm, st); break;
+    case 6: wg_launch<6>(sh.dtype, sh.vpl, sh.wide, jobs, n, shm, st); break;
+    case 8: wg_launch<8>(sh.dtype, sh.vpl, sh.wide, jobs, n, shm, st); break;
+    case 12: wg_launch<12>(sh.dtype, sh.vpl, sh.wide, jobs, n, shm, st); break;
+    default: fail(FTLM_ERR_DIM_GT_12, "irrep dimension above 12");
+  }
+}
+
+}  // namespace
+
+bool wg_supported(const Block& b, int R, int storage) {
+  if (R < 1 || R > kWgMaxR || b.D == 0 || b.sec->n_reps == 0) return false;
+  if (storage != FTLM_F64 && storage != FTLM_F32) return false;
+  if (b.sec->hv_mode != FTLM_HV_ENTRIES || b.lanczos_layout == FTLM_LAYOUT_PADDED) return false;
+  if (irrep_dim_bucket(b.dg) < 0) return false;
+  LaunchCfg c{};
+  HvArgs<double> a{};
+  hv_setup(b, R, R, wg_lanes(R), false, nullptr, c, a);
+  return c.slds && a.tile_w >= R && c.vpl <= 4;
+}
+
+uint64_t wg_rounds(uint64_t n_reps, int R) {
+  const uint64_t slots = (uint64_t)kThreads / (uint64_t)wg_lanes(R);
+  return (n_reps + slots - 1) / slots;
+}
+
+WgBatch::WgBatch(std::vector<WgTask> t, hipStream_t st_) : tasks(std::move(t)), st(st_) {
+  const size_t n = tasks.size();
+  if (n == 0) return;
+  for (const WgTask& k : tasks)
+    if (!k.block || !wg_supported(*k.block, k.R, k.storage) || k.steps <= 0 || !k.alpha || !k.beta || !k.nsteps ||
+        (k.dist != FTLM_RADEMACHER && k.dist != FTLM_GAUSSIAN))
+      fail(FTLM_ERR_INVALID_ARG, "fused Lanczos: job not supported by the kernel");
+  // kernel shape and arguments of every job
+  std::vector<Shape> shape(n);
+  std::vector<LaunchCfg> cfg(n);
+  std::vector<HvArgs<double>> a64(n);
+  std::vector<HvArgs<float>> a32(n);
+  std::map<Shape, std::vector<size_t>> groups;
+  for (size_t i = 0; i < n; ++i) {
+    const WgTask& k = tasks[i];
+    const Block& b = *k.block;
+    if (k.storage == FTLM_F64)
+      hv_setup(b, k.R, k.R, wg_lanes(k.R), false, nullptr, cfg[i], a64[i]);
+    else
+      hv_setup(b, k.R, k.R, wg_lanes(k.R), false, nullptr, cfg[i], a32[i]);
+    shape[i] = Shape{k.storage, b.dgp, cfg[i].vpl, b.sec->wide};
+    groups[shape[i]].push_back(i);
+  }
+  // arena: [job arrays][keys] (uploaded) [alpha][beta][n] (downloaded) [q0 q1 per job]
+  size_t off = 0;
+  std::map<Shape, size_t> goff;
+  for (auto& g : groups) {
+    goff[g.first] = off;
+    const size_t js = g.first.dtype == FTLM_F64 ? sizeof(WgJob<double>) : sizeof(WgJob<float>);
+    off = align256(off + js * g.second.size());
+  }
+  std::vector<size_t> okey(n), oal(n), obe(n), on(n), oq0(n), oq1(n);
+  for (size_t i = 0; i < n; ++i) {
+    okey[i] = off;
+    off += 8 * (size_t)tasks[i].R;
+  }
+  up_bytes = off = align256(off);
+  out_off = off;
+  for (size_t i = 0; i < n; ++i) {
+    const size_t rs = (size_t)tasks[i].R * tasks[i].steps;
+    oal[i] = off;
+    off += 8 * rs;
+    obe[i] = off;
+    off += 8 * rs;
+    on[i] = off;
+    off += 4 * (size_t)tasks[i].R;
+    off = (off + 7) & ~size_t(7);
+  }
+  out_bytes = off - out_off;
+  off = align256(off);
+  for (size_t i = 0; i < n; ++i) {
+    const size_t qb = (size_t)tasks[i].block->D * tasks[i].R * elem_bytes(tasks[i].storage);
+    oq0[i] = off;
+    off = align256(off + qb);
+    oq1[i] = off;
+    off = align256(off + qb);
+  }
+  {
+    AllocStreamScope scope(st);
+    arena.alloc(off);
+  }
+  uint8_t* base = arena.p;
+  staging.assign(up_bytes, 0);
+  for (auto& g : groups) {
+    size_t pos = goff[g.first];
+    for (size_t i : g.second) {
+      const WgTask& k = tasks[i];
+      const Block& b = *k.block;
+      auto fill = [&](auto job) {
+        job.q0 = (decltype(job.q0))(base + oq0[i]);
+        job.q1 = (decltype(job.q1))(base + oq1[i]);
+        job.keys = (const uint64_t*)(base + okey[i]);
+        job.alpha = (double*)(base + oal[i]);
+        job.beta = (double*)(base + obe[i]);
+        job.nsteps = (int32_t*)(base + on[i]);
+        job.D = b.D;
+        job.R = k.R;
+        job.steps = k.steps;
+        job.target = (int)std::min<uint64_t>((uint64_t)k.steps, b.D);
+        job.dist = k.dist;
+        job.sigma = 1.0;
+        std::memcpy(staging.data() + pos, &job, sizeof(job));
+        pos += sizeof(job);
+      };
+      if (k.storage == FTLM_F64) {
+        WgJob<double> j{};
+        j.a = a64[i];
+        fill(j);
+      } else {
+        WgJob<float> j{};
+        j.a = a32[i];
+        fill(j);
+      }
+      uint64_t* keys = (uint64_t*)(staging.data() + okey[i]);
+      for (int v = 0; v < k.R; ++v)
+        keys[v] = chain_key(k.seed, b.sec->two_M, b.irrep, b.row, k.first_chain + v);
+    }
+  }
+  FTLM_HIP(hipMemcpyAsync(base, staging.data(), up_bytes, hipMemcpyHostToDevice, st));
+  for (auto& g : groups) {
+    size_t shm = 0;
+    for (size_t i : g.second) shm = std::max(shm, cfg[i].shm);
+    launch_shape(g.first, base + goff[g.first], (int)g.second.size(), shm, st);
+  }
+  FTLM_HIP(hipGetLastError());
+  launched = true;
+  // where each job's results sit in the downloaded region
+  res.resize(n);
+  for (size_t i = 0; i < n; ++i) res[i] = {oal[i] - out_off, obe[i] - out_off, on[i] - out_off};
+}
+
+void WgBatch::finish() {
+  if (!launched) return;
+  launched = false;
+  std::vector<uint8_t> h(out_bytes);
+  FTLM_HIP(hipMemcpyAsync(h.data(), arena.p + out_off, out_bytes, hipMemcpyDeviceToHost, st));
+  FTLM_HIP(hipStreamSynchronize(st));
+  for (size_t i = 0; i < tasks.size(); ++i) {
+    const WgTask& k = tasks[i];
+    const size_t rs = (size_t)k.R * k.steps;
+    std::memcpy(k.alpha, h.data() + res[i][0], 8 * rs);
+    std::memcpy(k.beta, h.data() + res[i][1], 8 * rs);
+    std::memcpy(k.nsteps, h.data() + res[i][2], 4 * (size_t)k.R);
+  }
+}
+
+WgBatch::~WgBatch() {
+  if (launched) (void)hipStreamSynchronize(st);  // the arena is released on st after the kernels
+}
+
+}  // namespace ftlm

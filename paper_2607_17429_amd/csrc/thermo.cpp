@@ -13,6 +13,16 @@ namespace ftlm {
 // tridiagonal matrix by the implicit QL method with Wilkinson-type shifts.
 // Only the first row of the accumulated rotation product is tracked, which is
 // all the FTLM weights need.  d: diagonal (n), e: off-diagonal (n-1).
+namespace {
+// sqrt(a^2 + b^2); the scaled std::hypot only where the squares could
+// overflow or underflow
+inline double pyth(double a, double b) {
+  const double m = std::max(std::fabs(a), std::fabs(b));
+  if (m > 1e150 || (m < 1e-150 && m > 0.0)) return std::hypot(a, b);
+  return std::sqrt(a * a + b * b);
+}
+}  // namespace
+
 void tridiag_ritz(const double* alpha, const double* beta, int n, double* theta, double* weight) {
   std::vector<double> d(alpha, alpha + n), e(n, 0.0), z(n, 0.0);
   for (int i = 0; i + 1 < n; ++i) e[i] = beta[i];
@@ -29,7 +39,7 @@ void tridiag_ritz(const double* alpha, const double* beta, int n, double* theta,
       if (iter > 200) fail(FTLM_ERR_INVALID_ARG, "tridiagonal QL did not converge");
       // shift from the leading 2x2 block at l
       double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-      double r = std::hypot(g, 1.0);
+      double r = pyth(g, 1.0);
       g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
       double s = 1.0, c = 1.0, p = 0.0;
       int i = m - 1;
@@ -37,7 +47,7 @@ void tridiag_ritz(const double* alpha, const double* beta, int n, double* theta,
       for (; i >= l; --i) {
         double f = s * e[i];
         double b = c * e[i];
-        r = std::hypot(f, g);
+        r = pyth(f, g);
         e[i + 1] = r;
         if (r == 0.0) {  // underflow: split the problem here
           d[i + 1] -= p;
@@ -81,7 +91,8 @@ void observables(const ftlm_ritz* blocks, int nb, const double* T, int nT, doubl
       for (int k = 0; k < B.nsteps[r]; ++k) E0 = std::min(E0, B.theta[(size_t)r * B.ld + k]);
   }
   if (!std::isfinite(E0)) fail(FTLM_ERR_INVALID_ARG, "no Ritz values in the given blocks");
-  for (int t = 0; t < nT; ++t) {
+  // temperatures are independent: one thread per range of them
+  parallel_for(nT, 4, [&](int64_t t) {
     const double beta = 1.0 / T[t];
     double Z = 0, H1 = 0, H2 = 0, num = 0, den = 0;
     for (int b = 0; b < nb; ++b) {
@@ -111,7 +122,7 @@ void observables(const ftlm_ritz* blocks, int nb, const double* T, int nT, doubl
     if (C) C[t] = beta * beta * (e2 - e1 * e1);
     if (chi) chi[t] = g * g * beta * num / den;
     if (logZ) logZ[t] = std::log(Z) - beta * E0;
-  }
+  });
 }
 
 }  // namespace ftlm

@@ -1,8 +1,9 @@
 """GPU tests of the whole-cluster FTLM driver (ftlm_campaign).
 
 * Orchestration: the campaign's E, C, chi, ln Z equal, bit for bit, those of
-  the same blocks run one by one through ftlm_run and summed by
-  ftlm_observables (same library irreps, seeds and chain keys).
+  the same blocks run one by one through ftlm_run (per-step engine) or
+  through ftlm_run_fused (fused engine) and summed by ftlm_observables (same
+  library irreps, seeds and chain keys).
 * Exact limits of the aggregate, independent of the chains: Z(T -> inf) =
   (2s+1)^N and T chi / g^2 -> N s(s+1)/3.
 * With the spin flip at M = 0 (G x Z2) and 48 chains, E(T) agrees with the
@@ -27,7 +28,7 @@ P = pytest.importorskip("paper_2607_17429_amd")
 T_GRID = np.geomspace(0.05, 10, 50)
 
 
-def _blockwise(name, two_s, R, steps, seed, storage):
+def _blockwise(name, two_s, R, steps, seed, storage, fused=False):
     cl = clusters.get(name)
     G = lib_group(name)
     n_irr = len(G.irreps()["dims"])
@@ -38,7 +39,10 @@ def _blockwise(name, two_s, R, steps, seed, storage):
             B = P.Block(S, gi, 0)
             if B.D == 0:
                 continue
-            a, b, n = B.ftlm(R, steps, seed, storage=storage)
+            if fused:
+                (a, b, n), = P.run_fused([dict(block=B, R=R, steps=steps, seed=seed, storage=storage)])
+            else:
+                a, b, n = B.ftlm(R, steps, seed, storage=storage)
             ths, ws = P.ritz_from_run(a, b, n)
             blocks.append(dict(two_M=two_M, d_gamma=B.d_gamma, D=B.D, thetas=ths, weights=ws))
     return blocks
@@ -47,10 +51,11 @@ def _blockwise(name, two_s, R, steps, seed, storage):
 def test_campaign_equals_blockwise_runs():
     log("[campaign] icosahedron vs block-by-block")
     cl = clusters.get("icosahedron")
-    res = P.campaign(cl, cl.gens, 1, 4, 30, 0x5EED0001, T_GRID, storage=P.F64)
-    E, C, chi, lz = P.observables(_blockwise("icosahedron", 1, 4, 30, 0x5EED0001, P.F64), T_GRID)
-    assert np.array_equal(res["E"], E) and np.array_equal(res["C"], C)
-    assert np.array_equal(res["chi"], chi) and np.array_equal(res["logZ"], lz)
+    for engine, fused in ((P.ENGINE_STEPS, False), (P.ENGINE_FUSED, True)):
+        res = P.campaign(cl, cl.gens, 1, 4, 30, 0x5EED0001, T_GRID, storage=P.F64, engine=engine)
+        E, C, chi, lz = P.observables(_blockwise("icosahedron", 1, 4, 30, 0x5EED0001, P.F64, fused), T_GRID)
+        assert np.array_equal(res["E"], E) and np.array_equal(res["C"], C)
+        assert np.array_equal(res["chi"], chi) and np.array_equal(res["logZ"], lz)
     st = res["stats"]
     assert st["sectors"] == 7 and st["blocks"] + st["empty_blocks"] == 70
     hi = P.campaign(cl, cl.gens, 1, 4, 30, 0x5EED0001, np.array([1e9]), storage=P.F64)
