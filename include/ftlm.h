@@ -347,10 +347,12 @@ int ftlm_observables(const ftlm_ritz* blocks, int32_t nblocks, const double* T, 
  * representatives per lane group of one workgroup; 0 = the library default
  * of 8) run in the fused small-block kernel: one workgroup does every
  * Lanczos step of one block job (R chains, or chains_per_run of them), and
- * all such jobs of the campaign go out as one batch on a second stream of
- * the library.  The blocks of larger sectors run one after another with the
- * per-step kernels (the steps replay a captured graph), overlapping the
- * batch.  FTLM_ENGINE_STEPS forces the per-step kernels everywhere,
+ * all such jobs of the campaign go out as one batch on a stream of the
+ * library.  The blocks of larger sectors run with the per-step kernels (the
+ * steps replay a captured graph), spread over two worker streams so that
+ * blocks, the batch and the next sector's build overlap; their results are
+ * read back when the runs in flight pass a quarter of the free device memory
+ * or at the end.  Sectors run from the largest 2M down.  FTLM_ENGINE_STEPS forces the per-step kernels everywhere,
  * FTLM_ENGINE_FUSED the fused kernel wherever it applies (FP64 or FP32
  * storage, entry-table H.V, irrep tables within LDS, at most 32 chains per
  * job).  The sector tables of a large M are freed before the next M.

@@ -1,11 +1,15 @@
 // Whole-cluster FTLM (paper Sections 2.2, 3 and 4): every M >= 0 sector and
 // every irrep block (optionally G x Z2 at M = 0), R Lanczos chains per block,
 // Ritz data per chain, and the thermal sums of Eqs. (4)-(7), (14) over all of
-// them.  Sectors of few representatives go to the fused small-block kernel
-// (one workgroup per block job, all such jobs in one batch launched on a
-// second stream); the blocks of larger sectors run one after another with the
-// per-step kernels (Lanczos steps replay a captured graph), overlapping the
-// batch.  The sector tables of one large M are freed before the next M.
+// them.  Sectors run from the largest 2M down.  Sectors of few
+// representatives go to the fused small-block kernel (one workgroup per block
+// job, all such jobs in one batch on a stream of their own); the blocks of
+// larger sectors run with the per-step kernels (Lanczos steps replay a
+// captured graph) over two worker streams, so blocks, the batch and the next
+// sector's build overlap.  Runs in flight keep their sector's tables alive
+// until they are read back, which happens when their memory passes a quarter
+// of the free device memory, and at the end.
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <vector>
@@ -18,6 +22,11 @@ namespace {
 // fused kernel: largest representative rounds per lane group and step for
 // which a sector's blocks go to the fused batch under FTLM_ENGINE_AUTO
 constexpr uint64_t kFusedMaxRounds = 8;
+// worker streams for the per-step blocks; with the build stream and the
+// batch stream they fill HIP's default four hardware queues, so the build
+// never waits behind a worker's queued steps (measured on the dodecahedron
+// campaign: four workers sharing queues with the build made it slower)
+constexpr int kStepStreams = 2;
 
 double secs(std::chrono::steady_clock::time_point a, std::chrono::steady_clock::time_point b) {
   return std::chrono::duration<double>(b - a).count();
@@ -36,11 +45,12 @@ void run_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, co
   auto G = std::make_shared<Group>(build_group(cl->N, gens, ngens));
   compute_irreps(*G);
   if (!G->all_real) fail(FTLM_ERR_COMPLEX_IRREP_UNSUPPORTED, "group has irreps that are not of real type");
-  // per-step kernels on `stream`; batches of fused small-block jobs on `wstream`
+  // sector and block builds on `stream`, per-step Lanczos runs on the worker
+  // streams, batches of fused small-block jobs on `wstream`
   hipStream_t stream = nullptr, wstream = nullptr;
   FTLM_HIP(hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
   struct StreamGuard {
-    hipStream_t s;
+    hipStream_t s = nullptr;
     ~StreamGuard() {
       if (s) {
         (void)hipStreamSynchronize(s);
@@ -50,6 +60,12 @@ void run_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, co
   } guard{stream};
   FTLM_HIP(hipStreamCreateWithFlags(&wstream, hipStreamNonBlocking));
   StreamGuard wguard{wstream};
+  hipStream_t sstreams[kStepStreams] = {};
+  StreamGuard sguard[kStepStreams];
+  for (int k = 0; k < kStepStreams; ++k) {
+    FTLM_HIP(hipStreamCreateWithFlags(&sstreams[k], hipStreamNonBlocking));
+    sguard[k].s = sstreams[k];
+  }
   AllocStreamScope scope(stream);
 
   // Ritz data of every block (kept until the sums)
@@ -61,9 +77,11 @@ void run_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, co
   };
   std::vector<BlockRitz> all;
   const int Ns2 = cl->N * cl->two_s;  // 2 N s
+  // largest |M| first: the small sectors fill the fused batch, which then
+  // runs while the large sectors' blocks go through the per-step kernels
   std::vector<int> twoMs;
   if (o->all_M)
-    for (int m = Ns2 % 2; m <= Ns2; m += 2) twoMs.push_back(m);
+    for (int m = Ns2; m >= Ns2 % 2; m -= 2) twoMs.push_back(m);
   else
     twoMs.push_back(o->two_M);
   const int per_run = o->chains_per_run == 0 ? o->R : std::min(o->chains_per_run, o->R);
@@ -100,6 +118,40 @@ void run_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, co
   size_t free_b = 0, total_b = 0;
   FTLM_HIP(hipMemGetInfo(&free_b, &total_b));
   const int64_t pending_limit = (int64_t)(free_b / 8);
+
+  // Per-step runs in flight on the worker streams (their blocks kept alive).
+  struct StepJob {
+    std::unique_ptr<Block> blk;
+    std::vector<std::pair<std::unique_ptr<LanczosRun>, int>> runs;  // run, first chain
+    size_t ritz = 0;
+    int stream = 0;
+  };
+  std::vector<StepJob> step_jobs;
+  struct SyncOnExit {  // an error leaves no run of step_jobs executing when they are destroyed
+    hipStream_t* s;
+    ~SyncOnExit() {
+      for (int k = 0; k < kStepStreams; ++k) (void)hipStreamSynchronize(s[k]);
+    }
+  } step_sync{sstreams};
+  size_t step_bytes = 0;
+  const void* step_sector = nullptr;
+  const size_t step_limit = free_b / 4;
+  int next_stream = 0;
+  auto drain_steps = [&] {
+    if (step_jobs.empty()) return;
+    auto tl = clk::now();
+    for (auto& j : step_jobs) {
+      BlockRitz& br = all[j.ritz];
+      for (auto& [L, r0] : j.runs)
+        L->download(sstreams[j.stream], br.alpha.data() + (size_t)r0 * o->steps,
+                    br.beta.data() + (size_t)r0 * o->steps, br.n.data() + r0);
+    }
+    for (int k = 0; k < kStepStreams; ++k) FTLM_HIP(hipStreamSynchronize(sstreams[k]));
+    step_jobs.clear();
+    step_bytes = 0;
+    step_sector = nullptr;
+    S.seconds_lanczos += secs(tl, clk::now());
+  };
 
   for (int two_M : twoMs) {
     auto tb = clk::now();
@@ -151,26 +203,49 @@ void run_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, co
         pending_sector = sec.get();
         pending_blocks.push_back(std::move(blk));
       } else {
+        // per-step kernels on the next worker stream; results are read back
+        // when the sector ends (or memory runs short), so the blocks of a
+        // sector overlap on the device
         auto tl = clk::now();
+        // vectors of the runs, the block's tables and (once) its sector's tables
+        const size_t need = LanczosRun::estimate_bytes(*blk, per_run, o->steps, o->storage) *
+                                (size_t)((o->R + per_run - 1) / per_run) +
+                            (size_t)(blk->device_bytes() - sec->device_bytes()) +
+                            (step_sector == sec.get() ? 0 : (size_t)sec->device_bytes());
+        if (!step_jobs.empty() && step_bytes + need > step_limit) drain_steps();
+        const int k = next_stream++ % kStepStreams;
+        StepJob job;
         for (int r0 = 0; r0 < o->R; r0 += per_run) {
           const int rr = std::min(per_run, o->R - r0);
-          LanczosRun L(*blk, rr, o->steps, o->seed, o->storage, o->dist);
-          L.first_chain = r0;
-          L.allocate();
-          L.enqueue(stream);
-          L.download(stream, br.alpha.data() + (size_t)r0 * o->steps, br.beta.data() + (size_t)r0 * o->steps,
-                     br.n.data() + r0);
-          FTLM_HIP(hipStreamSynchronize(stream));
+          auto L = std::make_unique<LanczosRun>(*blk, rr, o->steps, o->seed, o->storage, o->dist);
+          L->first_chain = r0;
+          {
+            AllocStreamScope run_scope(sstreams[k]);  // buffers ordered on the stream that uses them
+            L->allocate();
+          }
+          L->enqueue(sstreams[k]);
+          job.runs.push_back({std::move(L), r0});
         }
+        job.stream = k;
+        job.ritz = all.size();
+        job.blk = std::move(blk);
+        step_jobs.push_back(std::move(job));
+        step_bytes += need;
+        step_sector = sec.get();
         S.seconds_lanczos += secs(tl, clk::now());
       }
       all.push_back(std::move(br));
     }
-    if (!fused_sector) finish_inflight();
+    // runs stay in flight across sectors (the next sector builds meanwhile)
+    // until their memory passes the limit
+    if (step_bytes > step_limit) drain_steps();
     if (pending_bytes > pending_limit) launch_pending();
   }
   launch_pending();
+  drain_steps();
   finish_inflight();
+  // blocks in ascending 2M (and irrep) order for the sums
+  std::stable_sort(all.begin(), all.end(), [](const BlockRitz& a, const BlockRitz& b) { return a.two_M < b.two_M; });
 
   auto tt = clk::now();
   for (auto& br : all) {

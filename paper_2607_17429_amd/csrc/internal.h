@@ -196,6 +196,8 @@ struct WgBatch {
   WgBatch(const WgBatch&) = delete;
   WgBatch& operator=(const WgBatch&) = delete;
   void finish();
+  template <typename Groups, typename Offsets, typename Cfgs>
+  void launch_groups(const Groups& groups, const Offsets& goff, const Cfgs& cfg);
   ~WgBatch();
 };
 

@@ -161,16 +161,24 @@ WgBatch::WgBatch(std::vector<WgTask> t, hipStream_t st_) : tasks(std::move(t)), 
     }
   }
   FTLM_HIP(hipMemcpyAsync(base, staging.data(), up_bytes, hipMemcpyHostToDevice, st));
-  for (auto& g : groups) {
-    size_t shm = 0;
-    for (size_t i : g.second) shm = std::max(shm, cfg[i].shm);
-    launch_shape(g.first, base + goff[g.first], (int)g.second.size(), shm, st);
-  }
-  FTLM_HIP(hipGetLastError());
   launched = true;
+  launch_groups(groups, goff, cfg);
   // where each job's results sit in the downloaded region
   res.resize(n);
   for (size_t i = 0; i < n; ++i) res[i] = {oal[i] - out_off, obe[i] - out_off, on[i] - out_off};
+}
+
+// One launch per kernel shape, one after another on st (measured: forking
+// the shapes onto streams of their own made them share hardware queues with
+// the caller's other streams and stalled those).
+template <typename Groups, typename Offsets, typename Cfgs>
+void WgBatch::launch_groups(const Groups& groups, const Offsets& goff, const Cfgs& cfg) {
+  for (auto& g : groups) {
+    size_t shm = 0;
+    for (size_t i : g.second) shm = std::max(shm, cfg[i].shm);
+    launch_shape(g.first, arena.p + goff.at(g.first), (int)g.second.size(), shm, st);
+  }
+  FTLM_HIP(hipGetLastError());
 }
 
 void WgBatch::finish() {
