@@ -215,7 +215,7 @@ def ring(N: int, dihedral: bool = True) -> Cluster:
     if dihedral and N > 2:
         gens.append(np.array([(-k) % N for k in range(N)], dtype=np.int32))
     order = 2 * N if (dihedral and N > 2) else N
-    return Cluster(f"ring{N}", N, bonds, np.stack(gens), group_order=order)
+    return Cluster(f"ring{N}" + ("" if dihedral else "_C"), N, bonds, np.stack(gens), group_order=order)
 
 
 def dimer() -> Cluster:
@@ -248,6 +248,8 @@ def get(name: str) -> Cluster:
     if name in BUILTIN:
         return BUILTIN[name]()
     if name.startswith("ring"):
+        if name.endswith("_C"):      # cyclic group only (translations of the ring)
+            return ring(int(name[4:-2]), dihedral=False)
         return ring(int(name[4:]))
     if name.startswith("K"):
         return complete_graph(int(name[1:]))
