@@ -113,7 +113,9 @@ typedef struct ftlm_opts {
                                of its blocks are Gamma_i^+ and Gamma_i^- at indices 2i and
                                2i + 1, rho'(g, f) = (+-1)^f rho_i(g) (user_rho then gives
                                rho_i on G).  INVALID_ARG unless 2M = 0. */
-  int32_t reserved2;
+  int32_t user_rho_weight;  /* block creation with user_rho: trace weight of the block in
+                               the thermal sums (0 = user_rho_dim; user_rho_dim / 2 for the
+                               real form of a complex pair) */
   int64_t reserved[5];
 } ftlm_opts;
 
@@ -127,17 +129,27 @@ typedef struct ftlm_block ftlm_block;
  * real orthogonal form for Frobenius-Schur indicator +1, verification of
  * unitarity, character orthogonality and sum d^2 = |G|).  Host only.
  * Errors: NOT_A_PERMUTATION, GROUP_TOO_LARGE (|G| > 65535), IRREPS_FAILED.
- * Irreps are computed for |G| <= 1024; a group with irreps that are not of
- * real type builds, but its irreps report COMPLEX_IRREP_UNSUPPORTED. */
+ *
+ * The library's irreps are real: an irrep of complex type (indicator 0) and
+ * its conjugate are listed once, together, as a real orthogonal
+ * representation of dimension 2d (indicator reported as 0), irreducible over
+ * the reals.  Its row block (any row) is the real form of the complex block
+ * of either member of the pair: twice its dimension, every level twice; in
+ * the thermal sums it carries the trace weight d = dim / 2 (ftlm_ritz.d_gamma).
+ * This replaces the paper's complex-arithmetic path.  Irreps are computed for
+ * |G| <= 1024; a group with a quaternionic irrep (indicator -1) builds, but
+ * its irreps report COMPLEX_IRREP_UNSUPPORTED. */
 int ftlm_group_create(int32_t N, const int32_t* gens, int32_t ngens, ftlm_group** out);
 /* |G|, number of irreps, number of conjugacy classes, number of sites. */
 int ftlm_group_info(const ftlm_group* g, int32_t* order, int32_t* n_irreps, int32_t* n_classes,
                     int32_t* N);
 /* Permutation table, |G| x N int32 (host array owned by the caller). */
 int ftlm_group_elements(const ftlm_group* g, int32_t* perms);
-/* Per irrep: dimension, Frobenius-Schur indicator, characters by class
- * (n_irreps x n_classes, row-major) and the class of every element (|G|).
- * Any pointer may be NULL.  Also the largest verification residual. */
+/* Per irrep: dimension, Frobenius-Schur indicator (0 marks a realified
+ * complex pair, trace weight dim / 2; +1 a real-type irrep, weight dim),
+ * characters of the real form by class (n_irreps x n_classes, row-major) and
+ * the class of every element (|G|).  Any pointer may be NULL.  Also the
+ * largest verification residual. */
 int ftlm_group_irreps(const ftlm_group* g, int32_t* dims, int32_t* indicators, double* chars,
                       int32_t* class_of, double* max_residual);
 /* Irrep matrices rho(g), |G| x d x d row-major. */
@@ -207,6 +219,10 @@ typedef struct ftlm_block_info {
   int32_t row;
   int32_t hv_mode;       /* mode actually used by apply */
   int64_t device_bytes;  /* device memory of block + sector */
+  int32_t trace_weight;  /* d_Gamma in the thermal sums: d_gamma, or d_gamma / 2 for a
+                            realified complex pair (library irreps) or as given by
+                            ftlm_opts.user_rho_weight */
+  int32_t reserved;
 } ftlm_block_info;
 int ftlm_block_info_get(const ftlm_block* b, ftlm_block_info* info);
 /* Host copies (n_reps each, any may be NULL): labels of Eq. (2), stabilizer
@@ -317,7 +333,8 @@ int ftlm_tridiag_ritz(const double* alpha, const double* beta, int32_t n, double
 /* Ritz data of one block for the thermal sums. */
 typedef struct ftlm_ritz {
   int32_t two_M;
-  int32_t d_gamma;
+  int32_t d_gamma;         /* trace weight of the block's irrep: its dimension, or
+                              dim / 2 for a realified complex pair */
   uint64_t D;
   int32_t R;
   int32_t ld;              /* stride of theta/weight rows (>= max nsteps) */

@@ -45,7 +45,7 @@ class Opts(C.Structure):
     _fields_ = [("hv_mode", C.c_int32), ("lanczos_layout", C.c_int32),
                 ("user_rho", C.POINTER(C.c_double)), ("user_rho_dim", C.c_int32),
                 ("entry_format", C.c_int32), ("hbm_limit_bytes", C.c_int64),
-                ("spin_flip", C.c_int32), ("reserved2", C.c_int32), ("reserved", C.c_int64 * 5)]
+                ("spin_flip", C.c_int32), ("user_rho_weight", C.c_int32), ("reserved", C.c_int64 * 5)]
 
 
 class SectorInfo(C.Structure):
@@ -57,7 +57,8 @@ class BlockInfo(C.Structure):
     _fields_ = [("D_M", C.c_uint64), ("n_reps", C.c_uint64), ("n_active", C.c_uint64),
                 ("D", C.c_uint64), ("d_gamma", C.c_int32), ("group_order", C.c_int32),
                 ("two_M", C.c_int32), ("irrep", C.c_int32), ("row", C.c_int32),
-                ("hv_mode", C.c_int32), ("device_bytes", C.c_int64)]
+                ("hv_mode", C.c_int32), ("device_bytes", C.c_int64), ("trace_weight", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class HvStats(C.Structure):
@@ -193,8 +194,10 @@ def make_cluster(N, two_s, bonds, J=None):
     return cl
 
 
-def make_opts(hv_mode=HV_AUTO, user_rho=None, hbm_limit=0, layout=0, entry_format=0, spin_flip=False):
+def make_opts(hv_mode=HV_AUTO, user_rho=None, hbm_limit=0, layout=0, entry_format=0, spin_flip=False,
+              user_rho_weight=0):
     o = Opts()
+    o.user_rho_weight = int(user_rho_weight)
     o.spin_flip = 1 if spin_flip else 0
     o.hv_mode = hv_mode
     o.entry_format = int(entry_format)

@@ -45,7 +45,9 @@ class Group:
         res = C.c_double()
         check(lib().ftlm_group_irreps(self._h, dims.ctypes.data_as(L.I32P), ind.ctypes.data_as(L.I32P),
                                       chars.ctypes.data_as(L.F64P), cls.ctypes.data_as(L.I32P), C.byref(res)))
-        return dict(dims=dims, indicators=ind, chars=chars, class_of=cls, residual=res.value)
+        # indicator 0 marks a realified complex pair: trace weight dim / 2
+        weights = np.where(ind == 0, dims // 2, dims)
+        return dict(dims=dims, indicators=ind, weights=weights, chars=chars, class_of=cls, residual=res.value)
 
     def rho(self, irrep):
         d = int(self.irreps()["dims"][irrep])
@@ -104,9 +106,9 @@ class Sector:
 class Block:
     """One (M, Gamma, row) block; owns device tables, shares the sector's."""
 
-    def __init__(self, sector: Sector, irrep, row=0, user_rho=None, hbm_limit=0, layout=0):
+    def __init__(self, sector: Sector, irrep, row=0, user_rho=None, hbm_limit=0, layout=0, user_rho_weight=0):
         self.sector = sector
-        opts = L.make_opts(user_rho=user_rho, hbm_limit=hbm_limit, layout=layout)
+        opts = L.make_opts(user_rho=user_rho, hbm_limit=hbm_limit, layout=layout, user_rho_weight=user_rho_weight)
         h = C.c_void_p()
         check(lib().ftlm_block_create(sector._h, int(irrep), int(row), C.byref(opts), C.byref(h)))
         self._h = h

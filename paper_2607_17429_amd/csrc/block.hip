@@ -158,16 +158,19 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
     const int d = opts->user_rho_dim;
     if (d > 12) fail(FTLM_ERR_DIM_GT_12, "irrep dimension above 12");
     B->dg = d;
+    B->weight = opts->user_rho_weight > 0 ? opts->user_rho_weight : d;
+    if (B->weight > d) fail(FTLM_ERR_INVALID_ARG, "user_rho_weight above user_rho_dim");
     B->rho.assign(opts->user_rho, opts->user_rho + (size_t)n * d * d);
     double res = check_user_rho(G, B->rho.data(), d);
     if (!(res < 1e-9)) fail(FTLM_ERR_BAD_RHO, "user rho is not an orthogonal representation (residual " + std::to_string(res) + ")");
   } else {
     if (!G.irreps_computed) fail(FTLM_ERR_UNSUPPORTED, "group irreps not available (|G| > 1024); pass user_rho");
-    if (!G.all_real) fail(FTLM_ERR_COMPLEX_IRREP_UNSUPPORTED, "group has irreps that are not of real type");
+    if (!G.all_real) fail(FTLM_ERR_COMPLEX_IRREP_UNSUPPORTED, "group has quaternionic irreps (no real form)");
     if (base_irrep >= (int)G.irreps.size()) fail(FTLM_ERR_IRREP_OUT_OF_RANGE, "irrep index out of range");
     const Irrep& ir = G.irreps[base_irrep];
     if (ir.dim > 12) fail(FTLM_ERR_DIM_GT_12, "irrep dimension above 12");
     B->dg = ir.dim;
+    B->weight = ir.weight();
     B->rho = ir.rho;
   }
   const int d = B->dg;

@@ -44,7 +44,7 @@ void run_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, co
   auto t0 = clk::now();
   auto G = std::make_shared<Group>(build_group(cl->N, gens, ngens));
   compute_irreps(*G);
-  if (!G->all_real) fail(FTLM_ERR_COMPLEX_IRREP_UNSUPPORTED, "group has irreps that are not of real type");
+  if (!G->all_real) fail(FTLM_ERR_COMPLEX_IRREP_UNSUPPORTED, "group has quaternionic irreps (no real form)");
   // sector and block builds on `stream`, per-step Lanczos runs on the worker
   // streams, batches of fused small-block jobs on `wstream`
   hipStream_t stream = nullptr, wstream = nullptr;
@@ -180,7 +180,7 @@ void run_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, co
       S.rows += blk->D;
       BlockRitz br;
       br.two_M = two_M;
-      br.d = blk->dg;
+      br.d = blk->weight;  // trace weight: d_Gamma, also for a realified complex pair
       br.D = blk->D;
       br.R = o->R;
       br.ld = o->steps;

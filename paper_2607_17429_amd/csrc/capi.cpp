@@ -182,6 +182,8 @@ int ftlm_block_info_get(const ftlm_block* b, ftlm_block_info* info) {
     info->row = B.row;
     info->hv_mode = B.sec->hv_mode;
     info->device_bytes = B.device_bytes();
+    info->trace_weight = B.weight;
+    info->reserved = 0;
   });
 }
 

@@ -8,10 +8,14 @@
 // Irreps: the eigenspaces of a generic real symmetric element
 // S = A + A^T, A = sum_g c_g R(g), of the right regular algebra are invariant
 // under the left regular representation; restricted to one eigenspace Q the
-// left action rho(g) = Q^T L(g) Q is an irrep in real orthogonal form when
-// the irrep has Frobenius-Schur indicator +1.  Eigenspaces carrying a pair of
-// complex (or a quaternionic) irreps are reducible over C; they are detected
-// through their characters and left out (all_real = false).
+// left action rho(g) = Q^T L(g) Q is a real representation that is
+// irreducible over the reals.  With <chi, chi> = 1 it is an irrep of real
+// type (indicator +1) in real orthogonal form.  With <chi, chi> = 2 and
+// indicator 0 it is a conjugate pair Gamma, Gamma* of complex type in real
+// form (dimension 2 d_Gamma); it is kept as one real irrep of kind 2, whose
+// blocks are the real forms of the complex Gamma blocks (the paper keeps a
+// complex-arithmetic path for these; here everything stays real).  A
+// quaternionic irrep (<chi, chi> = 4) is left out and all_real is false.
 #include "group.h"
 
 #include <algorithm>
@@ -287,6 +291,9 @@ double verify_irreps(const Group& G, const std::vector<const Irrep*>& irs) {
               for (int g = 0; g < n; ++g)
                 s += A.rho[((size_t)g * A.dim + i) * A.dim + j] * B.rho[((size_t)g * B.dim + k) * B.dim + l];
               s *= double(A.dim) / n;
+              // a realified pair (kind 2) satisfies the relation within one
+              // row (i == k), which is what the block construction uses
+              if (x == y && A.kind == 2 && i != k) continue;
               double ref = (x == y && i == k && j == l) ? 1.0 : 0.0;
               worst = std::max(worst, std::fabs(s - ref));
             }
@@ -338,12 +345,22 @@ void compute_irreps(Group& G) {
       }
       double nrm = 0;
       for (int g = 0; g < n; ++g) nrm += chi[g] * chi[g];
-      if (std::fabs(nrm / n - 1.0) > 1e-6) { complete = false; continue; }
+      double nu = 0;
+      for (int g = 0; g < n; ++g) nu += chi[G.idx_mul(g, g)];
+      nu /= n;
+      // <chi, chi> = 1: real type; 2 with indicator 0: a complex pair,
+      // irreducible over the reals; anything else (quaternionic, or a
+      // degenerate split) is left out
+      int kind = 0;
+      if (std::fabs(nrm / n - 1.0) < 1e-6 && std::fabs(nu - 1.0) < 1e-6) kind = 1;
+      if (std::fabs(nrm / n - 2.0) < 1e-6 && std::fabs(nu) < 1e-6 && m % 2 == 0) kind = 2;
+      if (!kind) { complete = false; continue; }
       std::vector<long long> key(nclass);
       for (int cc = 0; cc < nclass; ++cc) key[cc] = std::llround(chi[rep_of_class[cc]] * 1e6);
       if (found.count(key)) continue;
       Irrep ir;
       ir.dim = m;
+      ir.kind = kind;
       ir.rho.assign((size_t)n * m * m, 0.0);
       for (int g = 0; g < n; ++g) {
         int gi = G.inv[g];
@@ -357,9 +374,7 @@ void compute_irreps(Group& G) {
       }
       ir.chars.resize(nclass);
       for (int cc = 0; cc < nclass; ++cc) ir.chars[cc] = chi[rep_of_class[cc]];
-      double nu = 0;
-      for (int g = 0; g < n; ++g) nu += chi[G.idx_mul(g, g)];
-      ir.indicator = (int)std::lround(nu / n);
+      ir.indicator = (int)std::lround(nu);
       found.emplace(key, std::move(ir));
     }
     std::vector<Irrep> irs;
@@ -372,8 +387,8 @@ void compute_irreps(Group& G) {
       }
       return false;
     });
-    int sumsq = 0;
-    for (auto& ir : irs) sumsq += ir.dim * ir.dim;
+    int sumsq = 0;  // sum over complex irreps of d^2: a realified pair holds two of dimension dim / 2
+    for (auto& ir : irs) sumsq += ir.dim * ir.weight();
     std::vector<const Irrep*> ptrs;
     for (auto& ir : irs) ptrs.push_back(&ir);
     double res = verify_irreps(G, ptrs);

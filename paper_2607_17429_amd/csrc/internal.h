@@ -76,6 +76,7 @@ struct Block {
   std::shared_ptr<Sector> sec;  // shared with other blocks of the sector
   std::shared_ptr<Group> own_group;
   int irrep = 0, row = 0, dg = 0;
+  int weight = 0;               // trace weight in the thermal sums (dg, or dg / 2 for a realified pair)
   int dgp = 0;                  // kernel dimension bucket (tables zero-padded to it)
   uint64_t D = 0, n_active = 0;
   uint64_t D_pad = 0;           // n_reps * dg: rows of the padded vector layout

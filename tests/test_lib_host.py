@@ -121,3 +121,61 @@ def test_observables_match_oracle():
 def test_observables_errors():
     with pytest.raises(P.FtlmError):
         P.observables([dict(two_M=0, d_gamma=1, D=1, thetas=[np.zeros(1)], weights=[np.ones(1)])], np.array([-1.0]))
+
+
+@pytest.mark.parametrize("name", ["ring5_C", "ring8_C", "square3x3_T", "square4x4_T", "ring6", "cuboctahedron"])
+def test_real_forms_match_oracle(name):
+    """Complex-type irreps come as realified pairs (indicator 0, weight dim/2),
+    in the oracle's order and with its real-form characters."""
+    from oracle import realform
+    cl = clusters.get(name)
+    G = P.Group(cl.N, cl.gens)
+    OG = ogroup.close(cl.gens, cl.N)
+    forms = realform.real_forms(OG, oirreps.compute_irreps(OG))
+    ir = G.irreps()
+    rep_class = [c[0] for c in OG.classes]
+    assert list(ir["dims"]) == [f.irrep.dim for f in forms]
+    assert list(ir["weights"]) == [f.weight for f in forms]
+    assert list(ir["indicators"]) == [0 if f.kind == "complex pair" else 1 for f in forms]
+    assert int((ir["dims"] * ir["weights"]).sum()) == G.order
+    assert ir["residual"] < 1e-12
+    for k, f in enumerate(forms):
+        assert np.allclose(ir["chars"][k], f.irrep.chars[rep_class].real, atol=1e-9)
+        rho = G.rho(k)
+        assert np.allclose(np.einsum("gji,gjk->gik", rho, rho), np.eye(rho.shape[1]), atol=1e-12)
+        assert np.allclose(np.einsum("gij,hjk->ghik", rho, rho), rho[OG.mul], atol=1e-12)
+
+
+def _q8_regular():
+    """Quaternion group Q8 acting on itself by left multiplication (8 sites);
+    its two-dimensional irrep is quaternionic."""
+    # elements as (sign, unit) with unit in 1, i, j, k; site = 2 * unit + (sign < 0)
+    table = {("1", u): (1, u) for u in "1ijk"}
+    table.update({("i", "1"): (1, "i"), ("i", "i"): (-1, "1"), ("i", "j"): (1, "k"), ("i", "k"): (-1, "j"),
+                  ("j", "1"): (1, "j"), ("j", "i"): (-1, "k"), ("j", "j"): (-1, "1"), ("j", "k"): (1, "i")})
+    units = "1ijk"
+
+    def site(sign, u):
+        return 2 * units.index(u) + (1 if sign < 0 else 0)
+
+    gens = []
+    for a in "ij":
+        p = np.empty(8, dtype=np.int32)
+        for u in units:
+            for sign in (1, -1):
+                s2, v = table[(a, u)]
+                p[site(sign, u)] = site(sign * s2, v)
+        gens.append(p)
+    return np.stack(gens)
+
+
+def test_quaternionic_group_is_rejected():
+    gens = _q8_regular()
+    G = P.Group(8, gens)
+    assert G.order == 8
+    ir = G.irreps()
+    assert list(ir["dims"]) == [1, 1, 1, 1]          # the quaternionic 2-dim irrep has no real form here
+    cl = clusters.complete_graph(8)
+    with pytest.raises(P.FtlmError) as e:
+        P.campaign(cl, gens, 1, 2, 5, 1, np.array([1.0]))
+    assert e.value.name == "COMPLEX_IRREP_UNSUPPORTED"
