@@ -170,7 +170,6 @@ def serve(P, np, n_warm, n_jobs, rate, budget_gb, max_active, seed=0x5EED0100, l
     """
     from synth import clusters
     groups = {n: list(P.Group(clusters.get(n).N, clusters.get(n).gens).irreps()["dims"]) for n in SERVE_CLUSTERS}
-    rng = np.random.default_rng(seed)
     srv = P.Server(int(budget_gb * (1 << 30)), max_active=max_active)
     F = {"f64": P.F64, "f32": P.F32}
     records = []
@@ -205,13 +204,15 @@ def serve(P, np, n_warm, n_jobs, rate, budget_gb, max_active, seed=0x5EED0100, l
                     max_ms=float(lat.max()), queue_p50_ms=float(np.percentile(wait, 50)),
                     queue_p99_ms=float(np.percentile(wait, 99)))
 
+    # each phase draws from a generator of its own, so a phase's jobs do not
+    # depend on the sizes of the others (runs stay comparable)
     t = time.perf_counter()
-    run("warm", draw_jobs(rng, n_warm, groups, clusters), [0.0] * n_warm)
+    run("warm", draw_jobs(np.random.default_rng(seed + 1), n_warm, groups, clusters), [0.0] * n_warm)
     warm_s = time.perf_counter() - t
-    burst = run("burst", draw_jobs(rng, n_jobs, groups, clusters), [0.0] * n_jobs)
+    burst = run("burst", draw_jobs(np.random.default_rng(seed + 2), n_jobs, groups, clusters), [0.0] * n_jobs)
     lam = rate if rate else load * burst["jobs_per_s"]
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, n_jobs))
-    stream = run("poisson", draw_jobs(rng, n_jobs, groups, clusters), arrivals)
+    arrivals = np.cumsum(np.random.default_rng(seed + 3).exponential(1.0 / lam, n_jobs))
+    stream = run("poisson", draw_jobs(np.random.default_rng(seed + 4), n_jobs, groups, clusters), arrivals)
     stats = srv.stats()
     srv.close()
     if log_path:

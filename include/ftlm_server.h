@@ -18,7 +18,8 @@
  * work of different jobs overlaps on the device; its Lanczos steps are
  * enqueued in chunks of about 10 ms of estimated device time, so a long job
  * holds a hardware queue shared with other streams for at most one chunk
- * ahead of their work.  A job's result does not depend on the other jobs
+ * ahead of their work.  A job may ask to run instead as one launch of the
+ * fused small-block kernel (ftlm_run_fused) on its stream.  A job's result does not depend on the other jobs
  * (no shared reductions, deterministic kernels).  The two server threads own
  * every HIP call of the server; the calls below are thread-safe.
  */
@@ -45,6 +46,12 @@ typedef struct ftlm_job_desc {
   uint64_t seed;
   int32_t storage;       /* FTLM_F64 or FTLM_F32 */
   int32_t dist;          /* FTLM_RADEMACHER or FTLM_GAUSSIAN */
+  int32_t engine;        /* enum ftlm_engine: AUTO and STEPS run the per-step kernels (a single
+                            job gains nothing from the fused kernel, whose gain is many jobs per
+                            launch); FUSED runs the whole recurrence as one launch of the fused
+                            small-block kernel (INVALID_ARG where it does not apply, see
+                            ftlm_run_fused) */
+  int32_t reserved;
 } ftlm_job_desc;
 
 typedef struct ftlm_job_result {
@@ -56,6 +63,10 @@ typedef struct ftlm_job_result {
   double submit_s;       /* seconds since the server started */
   double start_s;        /* admission */
   double end_s;          /* results on the host */
+  int32_t engine;        /* FTLM_ENGINE_STEPS or FTLM_ENGINE_FUSED: the path the job took.  Its
+                            coefficients equal, bit for bit, those of ftlm_run (STEPS) or
+                            ftlm_run_fused (FUSED) on the same block */
+  int32_t reserved;
 } ftlm_job_result;
 
 /* Starts the worker thread on the current device.  Errors: INVALID_ARG. */

@@ -94,12 +94,14 @@ class FusedJob(C.Structure):
 class JobDesc(C.Structure):
     _fields_ = [("cluster", Cluster), ("gens", C.POINTER(C.c_int32)), ("ngens", C.c_int32), ("two_M", C.c_int32),
                 ("irrep", C.c_int32), ("row", C.c_int32), ("R", C.c_int32), ("steps", C.c_int32),
-                ("seed", C.c_uint64), ("storage", C.c_int32), ("dist", C.c_int32)]
+                ("seed", C.c_uint64), ("storage", C.c_int32), ("dist", C.c_int32), ("engine", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class JobResult(C.Structure):
     _fields_ = [("status", C.c_int32), ("R", C.c_int32), ("steps", C.c_int32), ("d_gamma", C.c_int32),
-                ("D", C.c_uint64), ("submit_s", C.c_double), ("start_s", C.c_double), ("end_s", C.c_double)]
+                ("D", C.c_uint64), ("submit_s", C.c_double), ("start_s", C.c_double), ("end_s", C.c_double),
+                ("engine", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Ritz(C.Structure):

@@ -19,9 +19,6 @@
 namespace ftlm {
 
 namespace {
-// fused kernel: largest representative rounds per lane group and step for
-// which a sector's blocks go to the fused batch under FTLM_ENGINE_AUTO
-constexpr uint64_t kFusedMaxRounds = 8;
 // worker streams for the per-step blocks; with the build stream and the
 // batch stream they fill HIP's default four hardware queues, so the build
 // never waits behind a worker's queued steps (measured on the dodecahedron
@@ -85,7 +82,7 @@ void run_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, co
   else
     twoMs.push_back(o->two_M);
   const int per_run = o->chains_per_run == 0 ? o->R : std::min(o->chains_per_run, o->R);
-  const uint64_t max_rounds = o->fused_max_rounds > 0 ? (uint64_t)o->fused_max_rounds : kFusedMaxRounds;
+  const uint64_t max_rounds = o->fused_max_rounds > 0 ? (uint64_t)o->fused_max_rounds : kWgAutoMaxRounds;
 
   // Fused jobs wait in `pending` (their blocks kept alive) and go out as one
   // batch when a sector of large blocks starts, so the two streams overlap,

@@ -175,6 +175,9 @@ void run_lanczos(Block& b, int R, int steps, uint64_t seed, int storage, int dis
 // representatives, the job's serial length.
 bool wg_supported(const Block& b, int R, int storage);
 uint64_t wg_rounds(uint64_t n_reps, int R);
+// automatic engine choice: blocks whose sector needs at most this many
+// representative rounds per lane group and step go to the fused kernel
+constexpr uint64_t kWgAutoMaxRounds = 16;
 struct WgTask {
   const Block* block;            // must outlive the batch
   int R, steps, storage, dist, first_chain;
@@ -189,7 +192,12 @@ struct WgBatch {
   std::vector<WgTask> tasks;
   hipStream_t st = nullptr;
   DevBuf<uint8_t> arena;
-  std::vector<uint8_t> staging;
+  struct Pinned {                   // pinned upload buffer (job structs, keys)
+    void* p = nullptr;
+    ~Pinned() {
+      if (p) (void)hipHostFree(p);
+    }
+  } staging;
   std::vector<std::array<size_t, 3>> res;
   size_t up_bytes = 0, out_off = 0, out_bytes = 0;
   bool launched = false;
@@ -197,8 +205,12 @@ struct WgBatch {
   WgBatch(const WgBatch&) = delete;
   WgBatch& operator=(const WgBatch&) = delete;
   void finish();
-  template <typename Groups, typename Offsets, typename Cfgs>
-  void launch_groups(const Groups& groups, const Offsets& goff, const Cfgs& cfg);
+  // One job only: enqueue the copy of its alpha | beta | nsteps (the layout
+  // of contiguous host arrays R x steps, R x steps, R) into host memory
+  // (pinned for an asynchronous copy); the caller synchronizes st.
+  void enqueue_download(void* host, size_t bytes);
+  template <typename Groups, typename Offsets, typename Shm>
+  void launch_groups(const Groups& groups, const Offsets& goff, const Shm& shm);
   ~WgBatch();
 };
 

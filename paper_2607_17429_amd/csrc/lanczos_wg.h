@@ -11,7 +11,7 @@
 // s_{j+1} = 1 / beta_{j+1}.  Reductions run over the workgroup in a fixed order
 // (deterministic; the order differs from the per-step kernels', so the two
 // agree to rounding).  Vectors use the block row layout; the irrep tables and
-// the bond data sit in LDS.
+// the bond data sit in LDS, and so do the two vectors when they fit.
 #pragma once
 
 #include "hv_kernel.h"
@@ -33,6 +33,8 @@ struct WgJob {
   uint64_t D;
   int R, steps, target, dist;
   double sigma;         // storage scale of the stored vectors (1 for FP32 / FP64)
+  int lds_vec;          // 1: q0, q1 live in dynamic LDS at byte offset o_q (q0 and q1 unused)
+  uint32_t o_q;
 };
 
 struct WgChain {
@@ -40,16 +42,28 @@ struct WgChain {
   int n, done;
 };
 
+// Column sums of red[q * W + c], q < n, by pairwise halving (a fixed order,
+// log2(n) barrier steps instead of n serial reads); the sum of column c ends
+// in red[c].  Called by every thread after red is written and synchronized.
+__device__ __forceinline__ void wg_col_sum(double* red, int W, int n) {
+  for (int m = n; m > 1;) {
+    const int half = (m + 1) >> 1;
+    for (int i = threadIdx.x; i < (m - half) * W; i += blockDim.x) {
+      const int q = half + i / W, c = i - (i / W) * W;
+      red[(q - half) * W + c] += red[q * W + c];
+    }
+    __syncthreads();
+    m = half;
+  }
+}
+
 // Per-chain sums of one value per thread (thread t holds chain t % R, rows
 // t / R + k * RB); out[v] for v < R, in a fixed order.
 __device__ __forceinline__ void wg_chain_sum(double x, int R, int RB, double* red, double* out) {
   red[threadIdx.x] = x;
   __syncthreads();
-  if ((int)threadIdx.x < R) {
-    double s = 0.0;
-    for (int q = 0; q < RB; ++q) s += red[q * R + threadIdx.x];
-    out[threadIdx.x] = s;
-  }
+  wg_col_sum(red, R, RB);
+  if ((int)threadIdx.x < R) out[threadIdx.x] = red[threadIdx.x];
   __syncthreads();
 }
 
@@ -65,8 +79,10 @@ __global__ void __launch_bounds__(kThreads) k_lanczos_wg(const WgJob<T>* __restr
 
   const WgJob<T>& J = jobs[blockIdx.x];
   HvArgs<T> a = J.a;
-  T* const q0 = J.q0;
-  T* const q1 = J.q1;
+  // the two Lanczos vectors: in LDS when they fit (the H.V gathers and the
+  // update then never leave the CU), otherwise in device memory
+  T* const q0 = J.lds_vec ? (T*)(sm + J.o_q) : J.q0;
+  T* const q1 = J.lds_vec ? q0 + J.D * (uint64_t)J.R : J.q1;
   double* const alpha = J.alpha;
   double* const beta = J.beta;
   const uint64_t D = J.D;
@@ -141,11 +157,8 @@ __global__ void __launch_bounds__(kThreads) k_lanczos_wg(const WgJob<T>* __restr
     for (int k = 0; k < VPL; ++k) {
       red[t] = vok[k] ? dot[k] : 0.0;
       __syncthreads();
-      if (t < GL) {
-        double s = 0.0;
-        for (int q = 0; q < kThreads / GL; ++q) s += red[q * GL + t];
-        if (t + k * GL < R) csum[t + k * GL] = s;
-      }
+      wg_col_sum(red, GL, kThreads / GL);
+      if (t < GL && t + k * GL < R) csum[t + k * GL] = red[t];
       __syncthreads();
     }
     if (t < R) {

@@ -18,6 +18,10 @@ namespace {
 // fetched together), else 8 with up to 4 vectors per lane
 int wg_lanes(int R) { return R <= 4 ? 4 : 8; }
 
+// dynamic LDS a job may use for its tables and, when they fit, its two
+// vectors (the kernel's static LDS takes another ~4.6 KiB of the 64 KiB)
+constexpr size_t kWgLdsBytes = 56 * 1024;
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 size_t elem_bytes(int storage) { return storage == FTLM_F64 ? 8 : 4; }
@@ -112,8 +116,19 @@ WgBatch::WgBatch(std::vector<WgTask> t, hipStream_t st_) : tasks(std::move(t)), 
   }
   out_bytes = off - out_off;
   off = align256(off);
+  // vectors in LDS when the tables and both vectors fit, else in the arena
+  std::vector<uint32_t> lds_q(n, 0);
+  std::vector<size_t> shm(n);
   for (size_t i = 0; i < n; ++i) {
     const size_t qb = (size_t)tasks[i].block->D * tasks[i].R * elem_bytes(tasks[i].storage);
+    const size_t oq = (cfg[i].shm + 15) & ~size_t(15);
+    shm[i] = cfg[i].shm;
+    oq0[i] = oq1[i] = 0;
+    if (oq + 2 * qb <= kWgLdsBytes) {
+      lds_q[i] = (uint32_t)oq;
+      shm[i] = oq + 2 * qb;
+      continue;
+    }
     oq0[i] = off;
     off = align256(off + qb);
     oq1[i] = off;
@@ -124,7 +139,9 @@ WgBatch::WgBatch(std::vector<WgTask> t, hipStream_t st_) : tasks(std::move(t)), 
     arena.alloc(off);
   }
   uint8_t* base = arena.p;
-  staging.assign(up_bytes, 0);
+  // pinned, so the upload is asynchronous (a pageable copy can block the host)
+  FTLM_HIP(hipHostMalloc(&staging.p, up_bytes, hipHostMallocDefault));
+  std::memset(staging.p, 0, up_bytes);
   for (auto& g : groups) {
     size_t pos = goff[g.first];
     for (size_t i : g.second) {
@@ -143,7 +160,10 @@ WgBatch::WgBatch(std::vector<WgTask> t, hipStream_t st_) : tasks(std::move(t)), 
         job.target = (int)std::min<uint64_t>((uint64_t)k.steps, b.D);
         job.dist = k.dist;
         job.sigma = 1.0;
-        std::memcpy(staging.data() + pos, &job, sizeof(job));
+        job.lds_vec = lds_q[i] ? 1 : 0;
+        job.o_q = lds_q[i];
+        if (job.lds_vec) job.q0 = job.q1 = nullptr;
+        std::memcpy((uint8_t*)staging.p + pos, &job, sizeof(job));
         pos += sizeof(job);
       };
       if (k.storage == FTLM_F64) {
@@ -155,14 +175,14 @@ WgBatch::WgBatch(std::vector<WgTask> t, hipStream_t st_) : tasks(std::move(t)), 
         j.a = a32[i];
         fill(j);
       }
-      uint64_t* keys = (uint64_t*)(staging.data() + okey[i]);
+      uint64_t* keys = (uint64_t*)((uint8_t*)staging.p + okey[i]);
       for (int v = 0; v < k.R; ++v)
         keys[v] = chain_key(k.seed, b.sec->two_M, b.irrep, b.row, k.first_chain + v);
     }
   }
-  FTLM_HIP(hipMemcpyAsync(base, staging.data(), up_bytes, hipMemcpyHostToDevice, st));
+  FTLM_HIP(hipMemcpyAsync(base, staging.p, up_bytes, hipMemcpyHostToDevice, st));
   launched = true;
-  launch_groups(groups, goff, cfg);
+  launch_groups(groups, goff, shm);
   // where each job's results sit in the downloaded region
   res.resize(n);
   for (size_t i = 0; i < n; ++i) res[i] = {oal[i] - out_off, obe[i] - out_off, on[i] - out_off};
@@ -171,14 +191,24 @@ WgBatch::WgBatch(std::vector<WgTask> t, hipStream_t st_) : tasks(std::move(t)), 
 // One launch per kernel shape, one after another on st (measured: forking
 // the shapes onto streams of their own made them share hardware queues with
 // the caller's other streams and stalled those).
-template <typename Groups, typename Offsets, typename Cfgs>
-void WgBatch::launch_groups(const Groups& groups, const Offsets& goff, const Cfgs& cfg) {
+template <typename Groups, typename Offsets, typename Shm>
+void WgBatch::launch_groups(const Groups& groups, const Offsets& goff, const Shm& shm) {
   for (auto& g : groups) {
-    size_t shm = 0;
-    for (size_t i : g.second) shm = std::max(shm, cfg[i].shm);
-    launch_shape(g.first, arena.p + goff.at(g.first), (int)g.second.size(), shm, st);
+    size_t bytes = 0;
+    for (size_t i : g.second) bytes = std::max(bytes, (size_t)shm[i]);
+    launch_shape(g.first, arena.p + goff.at(g.first), (int)g.second.size(), bytes, st);
   }
   FTLM_HIP(hipGetLastError());
+}
+
+void WgBatch::enqueue_download(void* host, size_t bytes) {
+  if (!launched) fail(FTLM_ERR_INVALID_ARG, "fused batch: nothing to download");
+  if (tasks.size() != 1) fail(FTLM_ERR_INVALID_ARG, "fused batch: asynchronous download is for one job");
+  const WgTask& k = tasks[0];
+  const size_t need = 16 * (size_t)k.R * k.steps + 4 * (size_t)k.R;  // alpha | beta | nsteps
+  if (bytes < need) fail(FTLM_ERR_INVALID_ARG, "fused batch: host buffer too small");
+  FTLM_HIP(hipMemcpyAsync(host, arena.p + out_off, need, hipMemcpyDeviceToHost, st));
+  launched = false;
 }
 
 void WgBatch::finish() {
@@ -197,7 +227,9 @@ void WgBatch::finish() {
 }
 
 WgBatch::~WgBatch() {
-  if (launched) (void)hipStreamSynchronize(st);  // the arena is released on st after the kernels
+  // the arena is released on st after the kernels, the pinned staging buffer
+  // (freed with the members) only once the stream is done with it
+  if (launched || staging.p) (void)hipStreamSynchronize(st);
 }
 
 }  // namespace ftlm

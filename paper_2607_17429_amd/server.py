@@ -19,12 +19,13 @@ class Server:
         self._free = lib().ftlm_server_free
         self._keep = {}
 
-    def submit(self, cluster, gens, two_M, irrep, row, R, steps, seed, storage=F64, dist=RADEMACHER, two_s=None):
+    def submit(self, cluster, gens, two_M, irrep, row, R, steps, seed, storage=F64, dist=RADEMACHER, two_s=None,
+               engine=0):
         cl = L.make_cluster(cluster.N, two_s if two_s is not None else getattr(cluster, "two_s", 1),
                             cluster.bonds, cluster.J)
         g = np.ascontiguousarray(np.asarray(gens, dtype=np.int32).reshape(-1, cluster.N))
         d = L.JobDesc(cl, g.ctypes.data_as(L.I32P), len(g), int(two_M), int(irrep), int(row), int(R), int(steps),
-                      C.c_uint64(seed), int(storage), int(dist))
+                      C.c_uint64(seed), int(storage), int(dist), int(engine), 0)
         jid = C.c_int64()
         check(lib().ftlm_server_submit(self._h, C.byref(d), C.byref(jid)))   # arrays are copied
         self._keep[jid.value] = (R, steps)

@@ -9,6 +9,7 @@
   since a last-bit change of a stored FP32 element moves later coefficients
   by ~1e-7 relative); one call mixing kernel shapes (R, storage, dimension,
   label width) gives each job the result of that job alone, bit for bit.
+  A chain offset (first_chain) reproduces the start vectors of the larger run.
 * Edge cases: blocks with D < steps (the chain stops at D), a one-row block,
   an empty block, chain offsets (first_chain), repeated blocks, and rejected
   jobs (R > 32, FP16 storage, on-the-fly sectors).
@@ -126,10 +127,14 @@ def test_fused_mixed_batch_equals_single_jobs():
 
 
 def test_fused_first_chain_offsets_keys():
+    # chains 4, 5 of a 6-chain job and a 2-chain job starting at chain 4 share
+    # their start vectors; the lane layout (and so the summation order) differs
     LB = _lib_block("icosahedron", 1, 0, 9)
     (a, b, n), = P.run_fused([dict(block=LB, R=6, steps=20, seed=8)])
     (a2, b2, n2), = P.run_fused([dict(block=LB, R=2, steps=20, seed=8, first_chain=4)])
-    assert np.array_equal(a[4:6], a2) and np.array_equal(b[4:6], b2)
+    for r in range(2):
+        ka, kb = _significant(b[4 + r], 12)
+        assert _rel(a2[r, :ka], a[4 + r, :ka]) < 1e-12 and _rel(b2[r, :kb], b[4 + r, :kb]) < 1e-12
 
 
 def test_fused_short_blocks_stop_at_dimension():
@@ -178,7 +183,10 @@ def test_campaign_fused_engine_matches_per_step_engine():
                        engine=P.ENGINE_STEPS)
         assert f["stats"]["fused_blocks"] == f["stats"]["blocks"] == s["stats"]["blocks"]
         assert s["stats"]["fused_blocks"] == 0
-        assert f["stats"]["work"] == s["stats"]["work"]
+        # a chain whose Krylov space is exhausted stops when rounding noise
+        # falls below the breakdown threshold, which the two summation orders
+        # may reach a step apart
+        assert abs(f["stats"]["work"] - s["stats"]["work"]) <= 1e-3 * s["stats"]["work"]
         for key in ("E", "C", "chi", "logZ"):
             assert _rel(f[key], s[key]) < 1e-9, key
 
@@ -189,6 +197,6 @@ def test_campaign_auto_engine_splits_by_sector_size():
     a = P.campaign(cl, cl.gens, 1, 24, 60, 9, T_GRID, storage=P.F64)
     s = P.campaign(cl, cl.gens, 1, 24, 60, 9, T_GRID, storage=P.F64, engine=P.ENGINE_STEPS)
     assert 0 < a["stats"]["fused_blocks"] < a["stats"]["blocks"]
-    assert a["stats"]["work"] == s["stats"]["work"]
+    assert abs(a["stats"]["work"] - s["stats"]["work"]) <= 1e-3 * s["stats"]["work"]
     for key in ("E", "C", "chi"):
         assert _rel(a[key], s[key]) < 1e-8, key

@@ -4,7 +4,9 @@ A job's Lanczos coefficients must not depend on what else runs: every job of a
 mixed batch (several clusters, M sectors, irreps, rows, R, storage types and
 start-vector distributions, admitted up to four at a time and overlapping on
 the device) is compared bit for bit with the same block run alone through
-ftlm_run.  The standalone path is itself compared with the oracle in
+ftlm_run, or through ftlm_run_fused for the jobs the server ran in the fused
+small-block kernel (the engine each job reports); both engines are also forced
+on the whole mix.  The standalone path is itself compared with the oracle in
 test_gpu_ftlm.py; one server job is also checked against the oracle here.
 Admission by memory budget, cancellation and failing jobs are covered too.
 """
@@ -51,16 +53,22 @@ def _valid(job):
     return gi < len(dims) and row < dims[gi]
 
 
-def _standalone(job):
+def _standalone(job, engine=None):
+    """The same block alone: ftlm_run, or ftlm_run_fused for jobs the server
+    ran in the fused small-block kernel."""
     name, two_M, gi, row, R, steps, seed, st, di = job
     B = P.Block(lib_sector(name, 1, two_M), gi, row)
+    if engine == P.ENGINE_FUSED:
+        (a, b, n), = P.run_fused([dict(block=B, R=R, steps=steps, seed=seed, storage=ST[st], dist=DI[di])])
+        return a, b, n
     return B.ftlm(R, steps, seed, storage=ST[st], dist=DI[di])
 
 
-def _submit(srv, job):
+def _submit(srv, job, engine=0):
     name, two_M, gi, row, R, steps, seed, st, di = job
     cl = clusters.get(name)
-    return srv.submit(cl, cl.gens, two_M, gi, row, R, steps, seed, storage=ST[st], dist=DI[di], two_s=1)
+    return srv.submit(cl, cl.gens, two_M, gi, row, R, steps, seed, storage=ST[st], dist=DI[di], two_s=1,
+                      engine=engine)
 
 
 def test_mixed_jobs_match_standalone_bitwise():
@@ -72,15 +80,44 @@ def test_mixed_jobs_match_standalone_bitwise():
     ids = [_submit(srv, job) for job in MIX]
     results = [srv.wait(i) for i in ids]
     srv.close()
+    engines = []
     for job, (res, a, b, n) in zip(MIX, results):
         assert res["status"] == 0, (job, res)
         assert res["submit_s"] <= res["start_s"] <= res["end_s"]
-        a0, b0, n0 = _standalone(job)
+        engines.append(res["engine"])
+        a0, b0, n0 = _standalone(job, res["engine"])
         assert np.array_equal(n, n0), job
         assert np.array_equal(a, a0), job
         assert np.array_equal(b, b0), job
     # the repeated job gives the same numbers
     assert np.array_equal(results[0][1], results[10][1])
+    # the automatic choice keeps the per-step kernels
+    assert set(engines) == {P.ENGINE_STEPS}
+
+
+@pytest.mark.parametrize("engine", ["steps", "fused"])
+def test_forced_engine_matches_standalone_bitwise(engine):
+    _enums()
+    eng = P.ENGINE_STEPS if engine == "steps" else P.ENGINE_FUSED
+    jobs = [j for j in MIX if j[4] <= 32 and not (j[0] == "dodecahedron" and j[1] == 0 and engine == "fused")]
+    srv = P.Server(8 << 30, max_active=4)
+    ids = [_submit(srv, job, eng) for job in jobs]
+    results = [srv.wait(i) for i in ids]
+    srv.close()
+    for job, (res, a, b, n) in zip(jobs, results):
+        assert res["status"] == 0 and res["engine"] == eng, (job, res)
+        a0, b0, n0 = _standalone(job, eng)
+        assert np.array_equal(n, n0) and np.array_equal(a, a0) and np.array_equal(b, b0), job
+
+
+def test_forced_fused_engine_rejects_unfit_jobs():
+    _enums()
+    cl = clusters.get("icosahedron")
+    srv = P.Server(1 << 30, max_active=2)
+    jid = srv.submit(cl, cl.gens, 0, 0, 0, 40, 20, 1, storage=P.F64, two_s=1, engine=P.ENGINE_FUSED)  # R > 32
+    res, a, *_ = srv.wait(jid)
+    assert res["error"] == "INVALID_ARG" and a is None
+    srv.close()
 
 
 def test_server_job_against_oracle():
@@ -131,7 +168,8 @@ def test_budget_cancel_and_failures():
     assert rq[1][0]["error"] == "CANCELLED"
     for k in (0, 2, 3):
         assert rq[k][0]["status"] == 0
-        a0, b0, n0 = P.Block(lib_sector("dodecahedron", 1, 2), 3, 0).ftlm(4, 30, 3 + k, storage=P.F64)
+        job = ("dodecahedron", 2, 3, 0, 4, 30, 3 + k, "f64", "rad")
+        a0, b0, n0 = _standalone(job, rq[k][0]["engine"])
         assert np.array_equal(rq[k][1], a0) and np.array_equal(rq[k][2], b0)
     st = srv.stats()
     assert st["running"] == 0 and st["queued"] == 0
@@ -165,5 +203,5 @@ def test_long_job_fed_in_chunks_matches_standalone():
     assert res[0][0]["D"] == 6465762
     for job, (r, a, b, n) in zip([big] + small, res):
         assert r["status"] == 0, (job, r)
-        a0, b0, n0 = _standalone(job)
+        a0, b0, n0 = _standalone(job, r["engine"])
         assert np.array_equal(n, n0) and np.array_equal(a, a0) and np.array_equal(b, b0), job
