@@ -324,6 +324,45 @@ typedef struct ftlm_fused_job {
  * (2 D R vectors per job) is allocated per call.  Synchronous. */
 int ftlm_run_fused(const ftlm_fused_job* jobs, int32_t n, void* stream);
 
+/* ----------------------------------------------------------------- KPM ---
+ * Kernel polynomial method (the spectral-density route to thermodynamic
+ * averages that the paper names next to FTLM, its Ref. [6]) on the same
+ * symmetry-adapted H.V: Chebyshev moments mu_n = <r|T_n(H~)|r> / <r|r> of
+ * H~ = (H - center) / half_width for R start vectors r (the vectors of
+ * ftlm_run's chains 0..R-1: same keys, generator and normalisation), from
+ * t_0 = r, t_1 = H~ r, t_{n+1} = 2 H~ t_n - t_{n-1}, two moments per H.V
+ * (mu_{2n+1} = 2<t_{n+1},t_n> - mu_1, mu_{2n+2} = 2<t_{n+1},t_{n+1}> - mu_0;
+ * Weisse et al., Rev. Mod. Phys. 78, 275 (2006)).  Vectors in FTLM_F64 or
+ * FTLM_F32 storage (block row layout), FP64 products and reductions in a
+ * fixed order.  The block spectrum must lie inside center +- half_width (for
+ * example the extreme Ritz values of a short ftlm_run, widened by a few
+ * percent); moments that leave [-1, 1] report INVALID_ARG.  Host output
+ * moments: R x n_moments (row-major).  ceil((n_moments - 1) / 2) H.V
+ * products.  Synchronous; device scratch allocated per call. */
+int ftlm_kpm(ftlm_block* b, int32_t R, int32_t n_moments, uint64_t seed, int32_t storage, int32_t dist,
+             double center, double half_width, double* moments, void* stream);
+
+/* KPM moments of one block for the thermal sums. */
+typedef struct ftlm_kpm_block {
+  int32_t two_M;
+  int32_t d_gamma;         /* trace weight (as in ftlm_ritz) */
+  uint64_t D;
+  int32_t R;
+  int32_t n_moments;
+  double center, half_width;
+  const double* moments;   /* R x n_moments */
+} ftlm_kpm_block;
+
+/* Host FP64 thermal sums from KPM moments: per block the chain-averaged
+ * moments with the Jackson kernel give quadrature weights W_k on the n_nodes
+ * Chebyshev nodes x_k = cos(pi (k + 1/2) / n_nodes) (0: twice the largest
+ * n_moments), W_k = (1/K)[g_0 mu_0 + 2 sum_n g_n mu_n cos(n theta_k)], at
+ * energies center + half_width x_k; then Z, E, C, chi as in ftlm_observables
+ * with Boltzmann factors shifted by the lowest node energy.  Errors:
+ * INVALID_ARG. */
+int ftlm_kpm_observables(const ftlm_kpm_block* blocks, int32_t nblocks, const double* T, int32_t nT, double g,
+                         int32_t n_nodes, double* E, double* C, double* chi, double* logZ);
+
 /* Host FP64: eigenvalues theta (ascending) and weights w_k = (first
  * eigenvector component)^2 of the n x n tridiagonal with diagonal alpha and
  * off-diagonal beta[0..n-2] (Section 2.2).  n <= 4096. */

@@ -110,6 +110,12 @@ class Ritz(C.Structure):
                 ("theta", C.POINTER(C.c_double)), ("weight", C.POINTER(C.c_double))]
 
 
+class KpmBlock(C.Structure):
+    _fields_ = [("two_M", C.c_int32), ("d_gamma", C.c_int32), ("D", C.c_uint64), ("R", C.c_int32),
+                ("n_moments", C.c_int32), ("center", C.c_double), ("half_width", C.c_double),
+                ("moments", C.POINTER(C.c_double))]
+
+
 VP = C.c_void_p
 I32P = C.POINTER(C.c_int32)
 F64P = C.POINTER(C.c_double)
@@ -141,6 +147,10 @@ SIGNATURES = {
     "ftlm_run_ex": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, F64P, F64P, I32P, VP,
                               C.POINTER(RunInfo)]),
     "ftlm_run_fused": (C.c_int, [C.POINTER(FusedJob), C.c_int32, VP]),
+    "ftlm_kpm": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                           F64P, VP]),
+    "ftlm_kpm_observables": (C.c_int, [C.POINTER(KpmBlock), C.c_int32, F64P, C.c_int32, C.c_double, C.c_int32,
+                                       F64P, F64P, F64P, F64P]),
     "ftlm_tridiag_ritz": (C.c_int, [F64P, F64P, C.c_int32, F64P, F64P]),
     "ftlm_campaign": (C.c_int, [C.POINTER(Cluster), I32P, C.c_int32, C.POINTER(CampaignOpts), F64P, C.c_int32,
                                 F64P, F64P, F64P, F64P, C.POINTER(CampaignStats)]),

@@ -188,6 +188,14 @@ class Block:
                                  X.stride(0), dtype, L.stream_handle(stream)))
         return Y
 
+    def kpm(self, R, n_moments, seed, center, half_width, storage=F64, dist=RADEMACHER, stream=None):
+        """Chebyshev moments (ftlm_kpm): R x n_moments."""
+        mom = np.zeros((R, n_moments))
+        check(lib().ftlm_kpm(self._h, int(R), int(n_moments), C.c_uint64(seed), int(storage), int(dist),
+                             float(center), float(half_width), mom.ctypes.data_as(L.F64P),
+                             L.stream_handle(stream) if stream is not None else None))
+        return mom
+
     def ftlm(self, R, steps, seed, storage=F64, dist=RADEMACHER, stream=None, info=False):
         """Batched Lanczos: returns alpha, beta (R x steps) and nsteps (R).
 
@@ -224,6 +232,25 @@ def run_fused(jobs, stream=None):
                             alpha.ctypes.data_as(L.F64P), beta.ctypes.data_as(L.F64P), ns.ctypes.data_as(L.I32P))
     check(lib().ftlm_run_fused(arr, len(jobs), L.stream_handle(stream) if stream is not None else None))
     return out
+
+
+def kpm_observables(blocks, T, g=1.0, n_nodes=0):
+    """ftlm_kpm_observables: blocks are dicts (two_M, d_gamma, D, moments (R x M), center, half_width)
+    -> E, C, chi, logZ on T."""
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    arr = (L.KpmBlock * len(blocks))()
+    keep = []
+    for i, b in enumerate(blocks):
+        m = np.ascontiguousarray(np.atleast_2d(b["moments"]), dtype=np.float64)
+        keep.append(m)
+        arr[i] = L.KpmBlock(int(b["two_M"]), int(b["d_gamma"]), int(b["D"]), m.shape[0], m.shape[1],
+                            float(b["center"]), float(b["half_width"]), m.ctypes.data_as(L.F64P))
+    nT = len(T)
+    E, Cv, chi, lz = np.empty(nT), np.empty(nT), np.empty(nT), np.empty(nT)
+    check(lib().ftlm_kpm_observables(arr, len(blocks), T.ctypes.data_as(L.F64P), nT, float(g), int(n_nodes),
+                                     E.ctypes.data_as(L.F64P), Cv.ctypes.data_as(L.F64P), chi.ctypes.data_as(L.F64P),
+                                     lz.ctypes.data_as(L.F64P)))
+    return E, Cv, chi, lz
 
 
 def tridiag_ritz(alpha, beta):

@@ -290,6 +290,24 @@ int ftlm_run_fused(const ftlm_fused_job* jobs, int32_t n, void* stream) {
   });
 }
 
+int ftlm_kpm(ftlm_block* b, int32_t R, int32_t n_moments, uint64_t seed, int32_t storage, int32_t dist,
+             double center, double half_width, double* moments, void* stream) {
+  return guarded([&] {
+    if (!b) fail(FTLM_ERR_INVALID_ARG, "null block");
+    run_kpm(*b->b, R, n_moments, seed, storage, dist, center, half_width, moments, (hipStream_t)stream);
+  });
+}
+
+int ftlm_kpm_observables(const ftlm_kpm_block* blocks, int32_t nblocks, const double* T, int32_t nT, double g,
+                         int32_t n_nodes, double* E, double* C, double* chi, double* logZ) {
+  return guarded([&] {
+    if (nblocks <= 0 || !blocks || nT < 0 || (nT > 0 && !T) || n_nodes < 0) fail(FTLM_ERR_INVALID_ARG, "bad arguments");
+    for (int i = 0; i < nT; ++i)
+      if (!(T[i] > 0)) fail(FTLM_ERR_INVALID_ARG, "temperatures must be positive");
+    kpm_observables(blocks, nblocks, T, nT, g, n_nodes, E, C, chi, logZ);
+  });
+}
+
 int ftlm_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, const ftlm_campaign_opts* opts,
                   const double* T, int32_t nT, double* E, double* C, double* chi, double* logZ,
                   ftlm_campaign_stats* stats) {

@@ -245,6 +245,7 @@ void hv_setup(const Block& b, int nvec, int64_t ld, int gl, bool pad, const Lanc
     a.tab_words = (uint32_t)tab_words;
     a.scal = lz ? lz->scal : nullptr;
     a.partials = lz ? lz->partials : nullptr;
+    a.eshift = lz ? lz->eshift : 0.0;
   }
 }
 

@@ -29,7 +29,9 @@
 //
 // Lanczos epilogue (partials != nullptr): the kernel writes
 // w = s_j (H q_j) - bs_j q_prev over q_prev (Y holds q_prev on entry) and
-// per-workgroup FP64 partial sums of q_j . w (w as stored).
+// per-workgroup FP64 partial sums of q_j . w (w as stored).  With a shift
+// e (eshift) the kernel applies H - e instead of H (the Chebyshev recursion
+// of the kernel polynomial method); e = 0 otherwise.
 #pragma once
 
 #include <algorithm>
@@ -99,6 +101,7 @@ struct HvArgs {
   // Lanczos epilogue
   const double* scal;
   double* partials;
+  double eshift;        // H - eshift is applied (0 except for the Chebyshev recursion)
 };
 
 struct LaunchCfg {
@@ -336,7 +339,7 @@ __device__ __forceinline__ void hv_pass(const HvArgs<T>& a, const HvTabs& tb,
           const int v = vbase + j * GL;
           const uint64_t at = (offp + k) * a.ld + v;
           const double xv = (double)a.X[at];
-          const double hx = y + ed * xv;
+          const double hx = y + (ed - a.eshift) * xv;
           if (!EPI) {
             a.Y[at] = (T)hx;
           } else {

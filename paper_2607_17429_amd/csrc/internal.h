@@ -114,6 +114,7 @@ struct LanczosEpilogue {
   const double* scal;   // per vector: [s_j, beta_j * s_{j-1}] pairs
   double* partials;     // n_groups x nvec
   int n_groups;
+  double eshift = 0.0;  // the pass applies H - eshift (Chebyshev recursion); 0 for Lanczos
 };
 void apply_hv(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t stream,
               const LanczosEpilogue* lz = nullptr);
@@ -213,6 +214,11 @@ struct WgBatch {
   void launch_groups(const Groups& groups, const Offsets& goff, const Shm& shm);
   ~WgBatch();
 };
+
+void run_kpm(Block& b, int R, int M, uint64_t seed, int storage, int dist, double center, double half_width,
+             double* moments, hipStream_t st);
+void kpm_observables(const ftlm_kpm_block* blocks, int nb, const double* T, int nT, double g, int n_nodes, double* E,
+                     double* C, double* chi, double* logZ);
 
 void tridiag_ritz(const double* alpha, const double* beta, int n, double* theta, double* weight);
 void observables(const ftlm_ritz* blocks, int nb, const double* T, int nT, double g, double* E, double* C,

@@ -125,4 +125,72 @@ void observables(const ftlm_ritz* blocks, int nb, const double* T, int nT, doubl
   });
 }
 
+// KPM thermal sums (see ftlm.h): Jackson-damped chain-averaged moments ->
+// Gauss-Chebyshev node weights per block -> shifted Boltzmann sums.
+void kpm_observables(const ftlm_kpm_block* blocks, int nb, const double* T, int nT, double g, int n_nodes, double* E,
+                     double* C, double* chi, double* logZ) {
+  struct Nodes {
+    double fac, M2;  // mult * d_Gamma * D, M^2
+    std::vector<double> e, w;
+  };
+  std::vector<Nodes> all;
+  int maxM = 0;
+  for (int b = 0; b < nb; ++b) maxM = std::max(maxM, blocks[b].n_moments);
+  const int K = n_nodes > 0 ? n_nodes : 2 * maxM;
+  if (K <= 0) fail(FTLM_ERR_INVALID_ARG, "no moments");
+  double E0 = std::numeric_limits<double>::infinity();
+  for (int b = 0; b < nb; ++b) {
+    const ftlm_kpm_block& B = blocks[b];
+    if (B.D == 0 || B.R <= 0 || B.n_moments <= 0) continue;
+    if (!B.moments || !(B.half_width > 0)) fail(FTLM_ERR_INVALID_ARG, "bad KPM block");
+    const int M = B.n_moments;
+    std::vector<double> c(M, 0.0);
+    for (int r = 0; r < B.R; ++r)
+      for (int n = 0; n < M; ++n) c[n] += B.moments[(size_t)r * M + n];
+    const double pq = M_PI / (M + 1);
+    for (int n = 0; n < M; ++n) {
+      const double gj = ((M - n + 1) * std::cos(pq * n) + std::sin(pq * n) / std::tan(pq)) / (M + 1);
+      c[n] *= gj / B.R;  // Jackson kernel times the chain average
+    }
+    Nodes nd;
+    nd.fac = (B.two_M == 0 ? 1.0 : 2.0) * (double)B.d_gamma * (double)B.D;
+    nd.M2 = 0.25 * B.two_M * B.two_M;
+    nd.e.resize(K);
+    nd.w.resize(K);
+    for (int k = 0; k < K; ++k) {
+      const double th = M_PI * (k + 0.5) / K;
+      double s = c[0];
+      for (int n = 1; n < M; ++n) s += 2.0 * c[n] * std::cos(n * th);
+      nd.w[k] = s / K;
+      nd.e[k] = B.center + B.half_width * std::cos(th);
+      E0 = std::min(E0, nd.e[k]);
+    }
+    all.push_back(std::move(nd));
+  }
+  if (all.empty()) fail(FTLM_ERR_INVALID_ARG, "no moments in the given blocks");
+  parallel_for(nT, 4, [&](int64_t t) {
+    const double beta = 1.0 / T[t];
+    double Z = 0, H1 = 0, H2 = 0, num = 0;
+    for (const Nodes& nd : all) {
+      double z = 0, h1 = 0, h2 = 0;
+      for (size_t k = 0; k < nd.e.size(); ++k) {
+        const double sh = nd.e[k] - E0;
+        const double bz = std::exp(-beta * sh) * nd.w[k];
+        z += bz;
+        h1 += bz * sh;
+        h2 += bz * sh * sh;
+      }
+      Z += nd.fac * z;
+      H1 += nd.fac * h1;
+      H2 += nd.fac * h2;
+      num += nd.fac * nd.M2 * z;
+    }
+    const double e1 = H1 / Z, e2 = H2 / Z;
+    if (E) E[t] = E0 + e1;
+    if (C) C[t] = beta * beta * (e2 - e1 * e1);
+    if (chi) chi[t] = g * g * beta * num / Z;
+    if (logZ) logZ[t] = std::log(Z) - beta * E0;
+  });
+}
+
 }  // namespace ftlm

@@ -1,0 +1,131 @@
+"""GPU parity of the kernel polynomial method (ftlm_kpm) on symmetry blocks.
+
+* Chebyshev moments of every start vector against the oracle's definition
+  (eigen-decomposition of the explicit block matrix, cos(n arccos x)):
+  FP64 within 1e-10, FP32 storage within 1e-5; odd and even moment counts,
+  irrep dimensions 1-5, realified complex pairs; mu_0 = 1.
+* The start vectors are ftlm_run's (same keys): mu_1 = (alpha_0 - c) / w for
+  every chain.
+* A centre and half width that do not enclose the spectrum are reported.
+* Whole-cluster thermodynamics from KPM moments of all blocks (library irreps,
+  ftlm_kpm_observables) agree with full exact diagonalization above the
+  kernel's resolution within the stochastic error (2-3% of the curve
+  maximum), and with the oracle's KPM sums on the same moments to rounding.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import lib_group, lib_sector, log, oracle_block, oracle_group, oracle_sector
+from oracle import basis, ftlm as oftlm, group, hv, irreps, kpm as okpm, realform, sector
+from synth import clusters
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2607_17429_amd")
+
+CASES = [("icosahedron", 1, 0, 8), ("icosahedron", 1, 2, 2), ("cuboctahedron", 1, 0, 4), ("ring6", 2, 0, 4),
+         ("K4", 3, 2, 3), ("dodecahedron", 1, 6, 9)]
+
+
+def _bounds(Hb):
+    e = np.linalg.eigvalsh(Hb)
+    return 0.5 * (e[0] + e[-1]), max(0.52 * (e[-1] - e[0]), 1e-2)
+
+
+@pytest.mark.parametrize("name,two_s,two_M,gi", CASES)
+@pytest.mark.parametrize("M,storage", [(64, "f64"), (101, "f64"), (64, "f32")])
+def test_kpm_moments_against_oracle(name, two_s, two_M, gi, M, storage):
+    log(f"[kpm] {name} 2s={two_s} 2M={two_M} irrep {gi} M={M} {storage}")
+    cl, G, irs = oracle_group(name)
+    sec, H = oracle_sector(name, two_s, two_M)
+    B = oracle_block(name, two_s, two_M, gi)
+    if B.D == 0:
+        pytest.skip("empty block")
+    Hb = hv.block_matrix(B, H)
+    c, w = _bounds(Hb)
+    LB = P.Block(lib_sector(name, two_s, two_M), gi, 0, user_rho=irs[gi].rho)
+    st = P.F64 if storage == "f64" else P.F32
+    R = 3
+    mom = LB.kpm(R, M, 17, c, w, storage=st)
+    tol = 1e-10 if storage == "f64" else 1e-5
+    for r in range(R):
+        v0 = oftlm.start_vector(B.D, 17, two_M, gi, 0, r, "rademacher")
+        want = okpm.moments(Hb, v0, c, w, M)
+        assert mom[r, 0] == 1.0
+        assert np.max(np.abs(mom[r] - want)) < tol, (r, np.max(np.abs(mom[r] - want)))
+
+
+def test_kpm_start_vectors_are_the_lanczos_chains():
+    LB = P.Block(lib_sector("icosahedron", 1, 0), 8, 0)
+    a, b, n = LB.ftlm(4, 5, 23)
+    c, w = -2.0, 10.0
+    mom = LB.kpm(4, 8, 23, c, w)
+    assert np.allclose(mom[:, 1], (a[:, 0] - c) / w, rtol=1e-12, atol=1e-14)
+
+
+def test_kpm_realified_pair_against_oracle():
+    cl = clusters.get("ring8_C")
+    G = group.close(cl.gens, cl.N)
+    forms = realform.real_forms(G, irreps.compute_irreps(G))
+    sec = basis.sector_reps(G, cl.N, 1, 0)
+    H = sector.hamiltonian(sec.labels, cl.N, 1, cl.bonds, cl.J)
+    S = P.Sector(cl, lib_group("ring8_C"), 0, two_s=1)
+    done = 0
+    for k, f in enumerate(forms):
+        if f.kind != "complex pair":
+            continue
+        B = basis.build_block(G, f.irrep, sec)
+        if B.D == 0:
+            continue
+        Hb = hv.block_matrix(B, H)
+        c, w = _bounds(Hb)
+        LB = P.Block(S, k, 0, user_rho=f.irrep.rho, user_rho_weight=f.weight)
+        mom = LB.kpm(2, 40, 5, c, w)
+        for r in range(2):
+            v0 = oftlm.start_vector(B.D, 5, 0, k, 0, r, "rademacher")
+            assert np.max(np.abs(mom[r] - okpm.moments(Hb, v0, c, w, 40))) < 1e-10
+        done += 1
+    assert done > 0
+
+
+def test_kpm_rejects_a_window_that_misses_the_spectrum():
+    LB = P.Block(lib_sector("icosahedron", 1, 0), 8, 0)
+    with pytest.raises(P.FtlmError, match="INVALID_ARG"):
+        LB.kpm(2, 200, 1, 0.0, 1.0)       # the spectrum reaches about -5
+    with pytest.raises(P.FtlmError, match="INVALID_ARG"):
+        LB.kpm(2, 20, 1, 0.0, -1.0)
+
+
+def test_kpm_thermodynamics_of_the_icosahedron():
+    log("[kpm] icosahedron, all sectors and irreps")
+    name = "icosahedron"
+    cl = clusters.get(name)
+    LG = lib_group(name)
+    info = LG.irreps()
+    R, M = 24, 256
+    c, w = 0.7, 7.2           # the spectrum lies in [-6.19, 7.5] (checked below)
+    blocks, oblocks, spectra = [], [], {}
+    for two_M in range(0, cl.N + 1, 2):
+        labels = sector.enumerate_sector(cl.N, 1, two_M)
+        Hs = sector.hamiltonian(labels, cl.N, 1, cl.bonds, cl.J).toarray()
+        spectra[two_M] = np.linalg.eigvalsh(Hs)
+        assert spectra[two_M][0] > c - w and spectra[two_M][-1] < c + w
+        S = P.Sector(cl, LG, two_M, two_s=1)
+        for k in range(len(info["dims"])):
+            B = P.Block(S, k, 0)
+            if B.D == 0:
+                continue
+            mom = B.kpm(R, M, 0x5EED0009, c, w)
+            blocks.append(dict(two_M=two_M, d_gamma=int(info["weights"][k]), D=B.D, moments=mom, center=c,
+                               half_width=w))
+            oblocks.append(okpm.KpmBlock(two_M, int(info["weights"][k]), B.D, mom, c, w))
+    # above T ~ 0.8 the Jackson broadening (pi w / M ~ 0.09) is negligible
+    T = np.geomspace(0.8, 10, 30)
+    E, C, chi, lz = P.kpm_observables(blocks, T)
+    Eo, Co, chio = okpm.observables(oblocks, T)
+    assert np.allclose(E, Eo, rtol=1e-11) and np.allclose(C, Co, rtol=1e-10) and np.allclose(chi, chio, rtol=1e-10)
+    Eed, Ced, chied = oftlm.ed_observables(spectra, T)
+    assert np.max(np.abs(E - Eed)) < 0.02 * np.max(np.abs(Eed))
+    assert np.max(np.abs(C - Ced)) < 0.03 * np.max(np.abs(Ced))
+    assert np.max(np.abs(chi - chied)) < 0.02 * np.max(np.abs(chied))

@@ -179,3 +179,25 @@ def test_quaternionic_group_is_rejected():
     with pytest.raises(P.FtlmError) as e:
         P.campaign(cl, gens, 1, 2, 5, 1, np.array([1.0]))
     assert e.value.name == "COMPLEX_IRREP_UNSUPPORTED"
+
+
+def test_kpm_observables_match_oracle():
+    """Host KPM thermal sums against the oracle's (Jackson kernel, Chebyshev nodes)."""
+    from oracle import kpm as okpm
+    rng = np.random.default_rng(8)
+    blocks_o, blocks_l = [], []
+    for two_M, dg, D, M in [(0, 1, 12, 40), (0, 3, 30, 64), (2, 5, 20, 33), (4, 2, 7, 64)]:
+        mom = np.concatenate([np.ones((3, 1)), rng.uniform(-0.3, 0.3, (3, M - 1)) * np.exp(-np.arange(1, M) / 9.0)],
+                             axis=1)
+        c, w = -1.0 + 0.5 * two_M, 3.0 + dg
+        blocks_o.append(okpm.KpmBlock(two_M, dg, D, mom, c, w))
+        blocks_l.append(dict(two_M=two_M, d_gamma=dg, D=D, moments=mom, center=c, half_width=w))
+    T = np.geomspace(0.1, 20, 40)
+    for K in (0, 300):
+        # n_nodes = 0: twice the largest moment count, for every block
+        E, C, chi, lz = okpm.observables(blocks_o, T, g=2.0, K=K or 2 * 64, with_logZ=True)
+        E2, C2, chi2, lz2 = P.kpm_observables(blocks_l, T, g=2.0, n_nodes=K)
+        for a, b in ((E, E2), (C, C2), (chi, chi2), (lz, lz2)):
+            assert np.allclose(a, b, rtol=1e-11, atol=1e-12)
+    with pytest.raises(P.FtlmError):
+        P.kpm_observables(blocks_l, np.array([-1.0]))
