@@ -392,7 +392,8 @@ def main():
         torch.cuda.synchronize()
         t3 = time.perf_counter()
         return dict(D=B.D, products=int(n.sum()), build=t1 - t0, lanczos=t2 - t1, thermo=t3 - t2, total=t3 - t0,
-                    E0=float(min(t.min() for t in ths)), hv_ms=info["hv_ms"], hv_launches=info["hv_launches"],
+                    E0=float(min(t.min() for t in ths)), Emax=float(max(t.max() for t in ths)),
+                    hv_ms=info["hv_ms"], hv_launches=info["hv_launches"],
                     layout=info["layout"], rows=info["rows"])
 
     if args.profile_hv:
@@ -474,6 +475,22 @@ def main():
     torch.cuda.synchronize()
     hv1_ms = ev0.elapsed_time(ev1) / 5
 
+    # the second workload on the same H.V: KPM moments (2 per product) for the
+    # same R start vectors, window from the Ritz values widened by 5%
+    kpm = None
+    if storage in (P.F64, P.F32):
+        lo, hi = recs[0]["E0"], recs[0]["Emax"]
+        kc, kw = 0.5 * (lo + hi), 0.525 * (hi - lo)
+        n_mom = 2 * wl["steps"] + 1
+        B.kpm(wl["R"], 3, 1, kc, kw, storage=storage, dist=dist, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        B.kpm(wl["R"], n_mom, 0x5EED0003, kc, kw, storage=storage, dist=dist, stream=stream)
+        torch.cuda.synchronize()
+        kt = time.perf_counter() - t0
+        kpm = {"moments": n_mom, "hv_products": wl["steps"], "seconds": kt,
+               "elem_vec_per_s": B.D * wl["R"] * wl["steps"] / kt, "center": kc, "half_width": kw}
+
     # HBM bytes per launch from the committed counter summary, valid only while
     # the kernel source is the one the counters were taken on
     from paper_2607_17429_amd.profiling import hv_source_sha
@@ -516,6 +533,7 @@ def main():
                "batched_elem_vec_per_s": B.D * wl["R"] / (hv_ms * 1e-3),
                "single_fp64_elem_vec_per_s": B.D / (hv1_ms * 1e-3), "single_fp64_ms": hv1_ms,
                "connections": stats["connections"], "active_connections": stats["active_connections"]},
+        "kpm": kpm,
         "E0": recs[0]["E0"],
         "autotune": {"lanes_per_rep": tuned[0], "ms": tuned[1], "tried_ms": tuned[2]},
     }
