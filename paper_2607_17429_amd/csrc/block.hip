@@ -223,33 +223,18 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
     B->trivial[s] = (S.size() == 1) ? 1 : 0;
   }
   hipStream_t st = tl_alloc_stream;  // the caller's build stream, or the null stream
-  // device tables
-  if (sec->n_reps) {
-    DevBuf<uint8_t> d_n;
-    d_n.upload(B->n_stab);
-    DevBuf<unsigned long long> per;
-    per.alloc(1);
-    FTLM_HIP(hipMemsetAsync(per.p, 0, per.bytes(), st));
-    DevBuf<uint64_t> off;
-    off.alloc(sec->n_reps + 1);
-    FTLM_HIP(hipMemsetAsync(off.p + sec->n_reps, 0, sizeof(uint64_t), st));
-    hipLaunchKernelGGL(k_rep_counts, dim3(grid1(sec->n_reps)), dim3(256), 0, st, sec->d_stab_id.p, sec->n_reps, d_n.p,
-                       off.p, per.p);
-    FTLM_HIP(hipGetLastError());
-    uint64_t D = 0;
-    scan_exclusive_u64(off.p, off.p, sec->n_reps + 1, &D, st);
-    if (D >= (1ull << 48)) fail(FTLM_ERR_UNSUPPORTED, "block dimension above 2^48");
-    B->D = D;
-    B->D_pad = sec->n_reps * (uint64_t)B->dg;
-    B->d_meta.alloc(sec->n_reps);
-    hipLaunchKernelGGL(k_meta, dim3(grid1(sec->n_reps)), dim3(256), 0, st, off.p, sec->d_stab_id.p, sec->n_reps,
-                       B->d_meta.p);
-    FTLM_HIP(hipGetLastError());
-    unsigned long long h_act = 0;
-    FTLM_HIP(hipMemcpyAsync(&h_act, per.p, sizeof(h_act), hipMemcpyDeviceToHost, st));
-    FTLM_HIP(hipStreamSynchronize(st));
-    B->n_active = h_act;
+  // D and the active count from the sector's representatives per stabilizer
+  uint64_t D = 0, n_act = 0;
+  for (int s = 0; s < ns; ++s) {
+    D += sec->stab_count[s] * (uint64_t)B->n_stab[s];
+    n_act += B->n_stab[s] ? sec->stab_count[s] : 0;
   }
+  if (D >= (1ull << 48)) fail(FTLM_ERR_UNSUPPORTED, "block dimension above 2^48");
+  B->D = D;
+  B->n_active = n_act;
+  B->D_pad = sec->n_reps * (uint64_t)B->dg;
+  // device tables: every copy is asynchronous from host arrays that live to
+  // the one synchronization at the end
   // rho^T[g][beta][gamma] = rho(g)[gamma][beta], zero-padded to the kernel's dimension bucket
   const int dp = B->dgp;
   // only the |G| matrices of G: the flipped half is parity * rho(g), applied
@@ -259,12 +244,12 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
   for (int g = 0; g < n; ++g)
     for (int be = 0; be < d; ++be)
       for (int ga = 0; ga < d; ++ga) rt[((size_t)g * dp + be) * dp + ga] = B->rho[((size_t)g * d + ga) * d + be];
-  B->d_rhoT64.upload(rt);
+  B->d_rhoT64.upload_async(rt, st);
   std::vector<double> vp((size_t)std::max(ns, 1) * dp * dp, 0.0);
   for (int s = 0; s < ns; ++s)
     for (int i = 0; i < d; ++i)
       for (int k = 0; k < d; ++k) vp[((size_t)s * dp + i) * dp + k] = B->V_stab[((size_t)s * d + i) * d + k];
-  B->d_V64.upload(vp);
+  B->d_V64.upload_async(vp, st);
   std::vector<double> sf((size_t)std::max(ns, 1) * 4, 0.0);
   for (int s = 0; s < ns; ++s) {
     sf[4 * s + 0] = B->n_stab[s];
@@ -272,7 +257,26 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
     sf[4 * s + 2] = 1.0 / std::sqrt(B->L_stab[s]);
     sf[4 * s + 3] = B->trivial[s];
   }
-  B->d_stabf64.upload(sf);
+  B->d_stabf64.upload_async(sf, st);
+  DevBuf<uint8_t> d_n;
+  DevBuf<unsigned long long> per;
+  DevBuf<uint64_t> off;
+  if (sec->n_reps) {
+    // row offsets = exclusive scan of n_Gamma over the representatives
+    d_n.upload_async(B->n_stab, st);
+    per.alloc(1);
+    FTLM_HIP(hipMemsetAsync(per.p, 0, per.bytes(), st));
+    off.alloc(sec->n_reps + 1);
+    FTLM_HIP(hipMemsetAsync(off.p + sec->n_reps, 0, sizeof(uint64_t), st));
+    hipLaunchKernelGGL(k_rep_counts, dim3(grid1(sec->n_reps)), dim3(256), 0, st, sec->d_stab_id.p, sec->n_reps, d_n.p,
+                       off.p, per.p);
+    FTLM_HIP(hipGetLastError());
+    scan_exclusive_u64(off.p, off.p, sec->n_reps + 1, nullptr, st);
+    B->d_meta.alloc(sec->n_reps);
+    hipLaunchKernelGGL(k_meta, dim3(grid1(sec->n_reps)), dim3(256), 0, st, off.p, sec->d_stab_id.p, sec->n_reps,
+                       B->d_meta.p);
+    FTLM_HIP(hipGetLastError());
+  }
   FTLM_HIP(hipStreamSynchronize(st));
   if (opts && opts->hbm_limit_bytes > 0 && B->device_bytes() > opts->hbm_limit_bytes)
     fail(FTLM_ERR_OUT_OF_MEMORY, "block tables exceed the HBM limit");

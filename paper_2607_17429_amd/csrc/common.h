@@ -102,6 +102,13 @@ struct DevBuf {
     }
   }
   void upload(const std::vector<T>& v, hipStream_t st = nullptr) { upload(v.data(), v.size(), st); }
+  // Asynchronous host -> device copy: the host array must stay unchanged
+  // until the stream has passed the copy.
+  void upload_async(const T* h, size_t count, hipStream_t st) {
+    alloc(count);
+    if (count) FTLM_HIP(hipMemcpyAsync(p, h, count * sizeof(T), hipMemcpyHostToDevice, st));
+  }
+  void upload_async(const std::vector<T>& v, hipStream_t st) { upload_async(v.data(), v.size(), st); }
   std::vector<T> download(hipStream_t st = nullptr) const {
     std::vector<T> h(n);
     if (!st) st = tl_alloc_stream;

@@ -428,7 +428,20 @@ std::vector<char> generated(const Group& G, const std::vector<int>& gens) {
 
 }  // namespace
 
+namespace {
+Factorization factor_group_uncached(const Group& G, int max_plain);
+}
+
 Factorization factor_group(const Group& G, int max_plain) {
+  std::lock_guard<std::mutex> lk(G.fac_mu);
+  auto it = G.fac_cache.find(max_plain);
+  if (it == G.fac_cache.end())
+    it = G.fac_cache.emplace(max_plain, std::make_shared<const Factorization>(factor_group_uncached(G, max_plain))).first;
+  return *it->second;
+}
+
+namespace {
+Factorization factor_group_uncached(const Group& G, int max_plain) {
   const int n = G.order;
   std::vector<char> best;
   int best_h = 1;
@@ -481,5 +494,6 @@ Factorization factor_group(const Group& G, int max_plain) {
     for (int h = 0; h < nH; ++h) f.gidx[(size_t)t * nH + h] = (uint16_t)G.idx_mul(f.T[t], f.H[h]);
   return f;
 }
+}  // namespace
 
 }  // namespace ftlm

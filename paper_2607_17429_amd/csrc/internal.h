@@ -36,6 +36,7 @@ struct Sector {
   std::vector<uint64_t> cnt;    // (N+1) x (Amax+1) digit-sum counts
   int cnt_stride = 0;
   std::vector<uint16_t> stab_size;               // per stabilizer id
+  std::vector<uint64_t> stab_count;              // representatives per stabilizer id
   std::vector<std::vector<int32_t>> stab_elems;  // per stabilizer id
   int32_t n_stab = 0;
   // device tables

@@ -62,7 +62,7 @@ void scan_exclusive_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t*
   FTLM_HIP(hipGetLastError());
   if (tiles > 1) {
     uint64_t tt = 0;
-    scan_exclusive_u64(sums.p, sums.p, tiles, &tt, s);
+    scan_exclusive_u64(sums.p, sums.p, tiles, total ? &tt : nullptr, s);
     hipLaunchKernelGGL(scan_add, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, out, n, sums.p);
     FTLM_HIP(hipGetLastError());
     if (total) *total = tt;
@@ -70,7 +70,8 @@ void scan_exclusive_u64(const uint64_t* in, uint64_t* out, uint64_t n, uint64_t*
     FTLM_HIP(hipMemcpyAsync(total, sums.p, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     FTLM_HIP(hipStreamSynchronize(s));
   }
-  if (tiles > 1) FTLM_HIP(hipStreamSynchronize(s));  // keep `sums` alive until the adds ran
+  // `sums` must outlive the adds: a stream-ordered free does; a plain one waits
+  if (tiles > 1 && !sums.async) FTLM_HIP(hipStreamSynchronize(s));
 }
 
 }  // namespace ftlm

@@ -473,6 +473,8 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
   // G = T H with |H| + |T| tables
   const int G_ = G->order;
   const size_t wbytes = s.wide ? 8 : 4;
+  std::vector<uint8_t> tab_host;                 // host copies of tables in flight to the device
+  std::vector<double> fac(2 * s.d * s.d);
   {
     const int max_plain = (int)std::max<size_t>(1, 16384 / ((size_t)s.nch * 16 * wbytes));
     const Factorization fz = factor_group(*G, max_plain);
@@ -507,13 +509,14 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
     std::memcpy(&bytes[rows * s.nch * 16 * wbytes], fz.gidx.data(), fz.gidx.size() * 2);
     s.d_tab.alloc((bytes.size() + 7) / 8);
     FTLM_HIP(hipMemcpyAsync(s.d_tab.p, bytes.data(), bytes.size(), hipMemcpyHostToDevice, st));
-    FTLM_HIP(hipStreamSynchronize(st));
+    tab_host.swap(bytes);  // kept until the stream has passed the copy
   }
-  s.d_cnt.upload(s.cnt);
-  s.d_bonds.upload(s.bonds);
-  s.d_J.upload(s.J);
+  // the small tables go up without a wait each; the first synchronization
+  // below (after the representative count) covers them
+  s.d_cnt.upload_async(s.cnt, st);
+  s.d_bonds.upload_async(s.bonds, st);
+  s.d_J.upload_async(s.J, st);
   {
-    std::vector<double> fac(2 * s.d * s.d);
     const double sp = 0.5 * s.two_s, ss = sp * (sp + 1);
     for (int ai = 0; ai < s.d; ++ai)
       for (int aj = 0; aj < s.d; ++aj) {
@@ -524,7 +527,7 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
         fac[(1 * s.d + ai) * s.d + aj] = 0.5 * std::sqrt(std::max(0.0, ss - mi * (mi - 1))) *
                                          std::sqrt(std::max(0.0, ss - mj * (mj + 1)));
       }
-    s.d_fac.upload(fac);
+    s.d_fac.upload_async(fac, st);
   }
   const size_t tab_bytes = (size_t)s.tab_words * wbytes;
   const bool lds = tab_bytes <= (size_t)max_lds_bytes();
@@ -659,13 +662,17 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
     if (!trivial_done) trivial_id = intern(trivial_mask);
     s.trivial_sid = trivial_id;
     s.n_stab = (int32_t)ids.size();
+    // representatives per stabilizer id (block dimensions follow from them)
+    s.stab_count.assign(s.n_stab, 0);
+    s.stab_count[trivial_id] += s.n_reps - n_nt;
+    for (uint64_t q = 0; q < n_nt; ++q) s.stab_count[ids_nt[q]] += 1;
     DevBuf<uint16_t> d_ids;
-    d_ids.upload(ids_nt);
+    d_ids.upload_async(ids_nt, st);
     s.d_stab_id.alloc(s.n_reps);
     hipLaunchKernelGGL(k_assign_stab, dim3(grid_for(s.n_reps)), dim3(kThreads), 0, st, pos.p, s.n_reps, d_ids.p,
                        trivial_id, s.d_stab_id.p);
     FTLM_HIP(hipGetLastError());
-    FTLM_HIP(hipStreamSynchronize(st));
+    FTLM_HIP(hipStreamSynchronize(st));  // ids_nt and the temporaries go out of scope
   }
 
   // diagonal energies and the entry table
