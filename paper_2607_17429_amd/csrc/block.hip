@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(256) k_hv_stats(const uint64_t* __restrict__ m
 void block_hv_stats(const Block& b, ftlm_hv_stats* res) {
   std::memset(res, 0, sizeof(*res));
   const Sector& s = *b.sec;
-  if (!s.n_reps) return;
+  if (!s.n_reps || b.D == 0) return;  // an empty block has no active representative
   if (s.hv_mode != FTLM_HV_ENTRIES) fail(FTLM_ERR_UNSUPPORTED, "work counts need the entry table");
   DevBuf<uint8_t> d_n;
   d_n.upload(b.n_stab);
@@ -233,6 +233,11 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
   B->D = D;
   B->n_active = n_act;
   B->D_pad = sec->n_reps * (uint64_t)B->dg;
+  if (D == 0) {
+    // an empty block never runs an H.V: no device tables, nothing to wait for
+    B->fpar = parity;
+    return B;
+  }
   // device tables: every copy is asynchronous from host arrays that live to
   // the one synchronization at the end
   // rho^T[g][beta][gamma] = rho(g)[gamma][beta], zero-padded to the kernel's dimension bucket

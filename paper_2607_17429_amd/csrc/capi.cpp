@@ -205,8 +205,12 @@ int ftlm_block_export(const ftlm_block* b, uint64_t* reps, uint16_t* stab_id, ui
     if (norms)
       for (size_t i = 0; i < sid.size(); ++i) norms[i] = B.L_stab[sid[i]];
     if (offsets) {
-      auto m = B.d_meta.download();
-      for (size_t i = 0; i < m.size(); ++i) offsets[i] = m[i] & ((1ull << 48) - 1);
+      if (B.D == 0) {  // an empty block keeps no metadata: every offset is 0
+        std::fill(offsets, offsets + S.n_reps, (uint64_t)0);
+      } else {
+        auto m = B.d_meta.download();
+        for (size_t i = 0; i < m.size(); ++i) offsets[i] = m[i] & ((1ull << 48) - 1);
+      }
     }
   });
 }
