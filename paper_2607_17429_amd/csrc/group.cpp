@@ -255,11 +255,14 @@ std::vector<double> sym_eigh(std::vector<double>& A, int n, std::vector<double>&
 
 double verify_irreps(const Group& G, const std::vector<const Irrep*>& irs) {
   const int n = G.order;
-  double worst = 0.0;
-  for (const Irrep* ir : irs) {
-    const int d = ir->dim;
-    const double* r = ir->rho.data();
-    for (int a = 0; a < n; ++a) {
+  // homomorphism and orthogonality, one group element a per task (the
+  // largest residual does not depend on the split)
+  std::vector<double> worst_a(n, 0.0);
+  parallel_for(n, 8, [&](int64_t a) {
+    double worst = 0.0;
+    for (const Irrep* ir : irs) {
+      const int d = ir->dim;
+      const double* r = ir->rho.data();
       // orthogonality rho(a)^T rho(a) = 1
       for (int i = 0; i < d; ++i)
         for (int j = 0; j < d; ++j) {
@@ -268,7 +271,7 @@ double verify_irreps(const Group& G, const std::vector<const Irrep*>& irs) {
           worst = std::max(worst, std::fabs(s - (i == j ? 1.0 : 0.0)));
         }
       for (int b = 0; b < n; ++b) {
-        const double* ab = r + (size_t)G.idx_mul(a, b) * d * d;
+        const double* ab = r + (size_t)G.idx_mul((int)a, b) * d * d;
         for (int i = 0; i < d; ++i)
           for (int j = 0; j < d; ++j) {
             double s = 0;
@@ -277,7 +280,10 @@ double verify_irreps(const Group& G, const std::vector<const Irrep*>& irs) {
           }
       }
     }
-  }
+    worst_a[a] = worst;
+  });
+  double worst = 0.0;
+  for (double w : worst_a) worst = std::max(worst, w);
   // great orthogonality (d_A/|G|) sum_g rho_A(g)_ij rho_B(g)_kl = delta_AB delta_ik delta_jl
   for (size_t x = 0; x < irs.size(); ++x)
     for (size_t y = x; y < irs.size(); ++y) {
@@ -287,13 +293,13 @@ double verify_irreps(const Group& G, const std::vector<const Irrep*>& irs) {
         for (int j = 0; j < A.dim; ++j)
           for (int k = 0; k < B.dim; ++k)
             for (int l = 0; l < B.dim; ++l) {
+              // a realified pair (kind 2) satisfies the relation within one
+              // row (i == k), which is what the block construction uses
+              if (x == y && A.kind == 2 && i != k) continue;
               double s = 0;
               for (int g = 0; g < n; ++g)
                 s += A.rho[((size_t)g * A.dim + i) * A.dim + j] * B.rho[((size_t)g * B.dim + k) * B.dim + l];
               s *= double(A.dim) / n;
-              // a realified pair (kind 2) satisfies the relation within one
-              // row (i == k), which is what the block construction uses
-              if (x == y && A.kind == 2 && i != k) continue;
               double ref = (x == y && i == k && j == l) ? 1.0 : 0.0;
               worst = std::max(worst, std::fabs(s - ref));
             }
