@@ -117,7 +117,8 @@ WgBatch::WgBatch(std::vector<WgTask> t, hipStream_t st_) : tasks(std::move(t)), 
   out_bytes = off - out_off;
   off = align256(off);
   // vectors in LDS when the tables and both vectors fit, else in the arena
-  std::vector<uint32_t> lds_q(n, 0);
+  std::vector<uint32_t> lds_q(n, 0);  // byte offset of q0 in LDS
+  std::vector<char> in_lds(n, 0);
   std::vector<size_t> shm(n);
   for (size_t i = 0; i < n; ++i) {
     const size_t qb = (size_t)tasks[i].block->D * tasks[i].R * elem_bytes(tasks[i].storage);
@@ -125,6 +126,7 @@ WgBatch::WgBatch(std::vector<WgTask> t, hipStream_t st_) : tasks(std::move(t)), 
     shm[i] = cfg[i].shm;
     oq0[i] = oq1[i] = 0;
     if (oq + 2 * qb <= kWgLdsBytes) {
+      in_lds[i] = 1;
       lds_q[i] = (uint32_t)oq;
       shm[i] = oq + 2 * qb;
       continue;
@@ -160,7 +162,7 @@ WgBatch::WgBatch(std::vector<WgTask> t, hipStream_t st_) : tasks(std::move(t)), 
         job.target = (int)std::min<uint64_t>((uint64_t)k.steps, b.D);
         job.dist = k.dist;
         job.sigma = 1.0;
-        job.lds_vec = lds_q[i] ? 1 : 0;
+        job.lds_vec = in_lds[i];
         job.o_q = lds_q[i];
         if (job.lds_vec) job.q0 = job.q1 = nullptr;
         std::memcpy((uint8_t*)staging.p + pos, &job, sizeof(job));
