@@ -401,7 +401,7 @@ int ftlm_observables(const ftlm_ritz* blocks, int32_t nblocks, const double* T, 
  *
  * Engines: sectors with few representatives (at most fused_max_rounds
  * representatives per lane group of one workgroup; 0 = the library default
- * of 16) run in the fused small-block kernel: one workgroup does every
+ * of 8) run in the fused small-block kernel: one workgroup does every
  * Lanczos step of one block job (R chains, or chains_per_run of them), and
  * all such jobs of the campaign go out as one batch on a stream of the
  * library.  The blocks of larger sectors run with the per-step kernels (the

@@ -179,7 +179,7 @@ bool wg_supported(const Block& b, int R, int storage);
 uint64_t wg_rounds(uint64_t n_reps, int R);
 // automatic engine choice: blocks whose sector needs at most this many
 // representative rounds per lane group and step go to the fused kernel
-constexpr uint64_t kWgAutoMaxRounds = 16;
+constexpr uint64_t kWgAutoMaxRounds = 8;
 struct WgTask {
   const Block* block;            // must outlive the batch
   int R, steps, storage, dist, first_chain;

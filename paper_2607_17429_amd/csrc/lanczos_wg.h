@@ -20,6 +20,11 @@ namespace ftlm {
 namespace hvk {
 
 constexpr int kWgMaxR = 32;
+// threads per job: 512 (two waves per SIMD, so twice the representatives in
+// flight as with 256) for irrep dimension buckets up to 6, whose registers fit
+// the 256 per lane this allows; 256 for the 8 and 12 buckets
+template <int DG>
+constexpr int kWgThreads = DG <= 6 ? 512 : 256;
 
 template <typename T>
 struct WgJob {
@@ -68,11 +73,12 @@ __device__ __forceinline__ void wg_chain_sum(double x, int R, int RB, double* re
 }
 
 template <typename T, int DG, int VPL, int NCH>
-__global__ void __launch_bounds__(kThreads) k_lanczos_wg(const WgJob<T>* __restrict__ jobs) {
+__global__ void __launch_bounds__(kWgThreads<DG>) k_lanczos_wg(const WgJob<T>* __restrict__ jobs) {
+  constexpr int NT = kWgThreads<DG>;
   using W = word_t<NCH>;
   extern __shared__ uint64_t smem_raw[];
   char* sm = (char*)smem_raw;
-  __shared__ double red[kThreads];
+  __shared__ double red[NT];
   __shared__ double scal[2 * kWgMaxR];
   __shared__ double csum[kWgMaxR];
   __shared__ WgChain ch[kWgMaxR];
@@ -97,13 +103,13 @@ __global__ void __launch_bounds__(kThreads) k_lanczos_wg(const WgJob<T>* __restr
                   stage<double>(a.fac, (uint32_t)(2 * a.dloc * a.dloc), sm + a.o_fac),
                   stage<int32_t>(a.bonds, (uint32_t)(2 * a.nbonds), sm + a.o_bonds)};
   const dev::OrbitTabs<W, NCH> otabs = dev::orbit_tabs<W, NCH>((const W*)nullptr, 1, 1);  // entries: unused
-  for (int i = t; i < R * steps; i += kThreads) {
+  for (int i = t; i < R * steps; i += NT) {
     alpha[i] = 0.0;
     beta[i] = 0.0;
   }
 
   // ---- start vectors: FP64 norm of the draw, then the stored q_0 and its norm
-  const int RB = kThreads / R;
+  const int RB = NT / R;
   const int v = t % R, r0 = t / R;
   const bool act = r0 < RB;
   const uint64_t key = J.keys[v];
@@ -137,7 +143,7 @@ __global__ void __launch_bounds__(kThreads) k_lanczos_wg(const WgJob<T>* __restr
   const int GL = a.GL;
   const int lane = t & 63;
   const uint64_t slot = (uint64_t)(t >> 6) * (uint64_t)(64 >> a.log2GL) + (uint64_t)(lane >> a.log2GL);
-  const uint64_t slot_stride = (uint64_t)(kThreads / 64) * (uint64_t)(64 >> a.log2GL);
+  const uint64_t slot_stride = (uint64_t)(NT / 64) * (uint64_t)(64 >> a.log2GL);
 
   for (int j = 0; j < target; ++j) {
     if (t < R) {
@@ -157,7 +163,7 @@ __global__ void __launch_bounds__(kThreads) k_lanczos_wg(const WgJob<T>* __restr
     for (int k = 0; k < VPL; ++k) {
       red[t] = vok[k] ? dot[k] : 0.0;
       __syncthreads();
-      wg_col_sum(red, GL, kThreads / GL);
+      wg_col_sum(red, GL, NT / GL);
       if (t < GL && t + k * GL < R) csum[t + k * GL] = red[t];
       __syncthreads();
     }
@@ -217,9 +223,11 @@ void wg_launch(int dtype, int vpl, bool wide, const void* jobs, int njobs, size_
 template <typename T, int DG, int VPL>
 void wg_launch_t(bool wide, const void* jobs, int njobs, size_t shm, hipStream_t st) {
   if (wide)
-    hipLaunchKernelGGL((k_lanczos_wg<T, DG, VPL, 16>), dim3(njobs), dim3(kThreads), shm, st, (const WgJob<T>*)jobs);
+    hipLaunchKernelGGL((k_lanczos_wg<T, DG, VPL, 16>), dim3(njobs), dim3(kWgThreads<DG>), shm, st,
+                       (const WgJob<T>*)jobs);
   else
-    hipLaunchKernelGGL((k_lanczos_wg<T, DG, VPL, 8>), dim3(njobs), dim3(kThreads), shm, st, (const WgJob<T>*)jobs);
+    hipLaunchKernelGGL((k_lanczos_wg<T, DG, VPL, 8>), dim3(njobs), dim3(kWgThreads<DG>), shm, st,
+                       (const WgJob<T>*)jobs);
 }
 
 template <typename T, int DG>

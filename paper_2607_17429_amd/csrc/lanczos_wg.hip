@@ -62,7 +62,8 @@ bool wg_supported(const Block& b, int R, int storage) {
 }
 
 uint64_t wg_rounds(uint64_t n_reps, int R) {
-  const uint64_t slots = (uint64_t)kThreads / (uint64_t)wg_lanes(R);
+  // workgroups of 512 threads (irrep dimensions up to 6)
+  const uint64_t slots = (uint64_t)kWgThreads<1> / (uint64_t)wg_lanes(R);
   return (n_reps + slots - 1) / slots;
 }
 
