@@ -161,6 +161,8 @@ void hv_setup(const Block& b, int nvec, int64_t ld, int gl, bool pad, const Lanc
   c.wide = s.wide;
   c.nch = s.nch;
   c.vpl = L.VPL;
+  // kernels specialised for the dense gather (table-driven H.V only)
+  c.contig = pad && !otf && b.dg == b.dgp && nvec == L.tile_w * L.tiles;
   const uint64_t tab_words = s.tab_words;
   const uint64_t tab_bytes = tab_words * (s.wide ? 8 : 4);
   const uint64_t DG = (uint64_t)b.dgp;

@@ -12,7 +12,8 @@
 // L = |G| / |Stab|.
 //
 // Lane layout: a group of GL lanes owns one output representative; lane g of
-// the group holds vector columns v = tile + g + j * GL, j < VPL.  Every output
+// the group holds VPL vector columns (v = tile + g + j * GL, or the adjacent
+// v = tile + g * VPL + j in CONTIG launches, see hv_col_lane).  Every output
 // element is written by exactly one lane and the sum over flips runs in a
 // fixed order, so results are deterministic and do not depend on how many
 // vectors share the launch.  Small GL (8) with VPL vectors per lane keeps 64/GL
@@ -108,6 +109,7 @@ struct LaunchCfg {
   dim3 grid;
   size_t shm;
   bool otf, lds_tab, slds, wide;
+  bool contig;  // the dense gather holds: adjacent columns per lane
   int nch, vpl;
 };
 
@@ -135,6 +137,21 @@ __device__ __forceinline__ const E* stage(const E* src, uint32_t count, char* ds
   return dst;
 }
 
+// Whether a launch may take the dense gather (padded rows with d_Gamma equal
+// to the dimension bucket and full column tiles; uniform over the launch).
+template <typename T>
+__device__ __forceinline__ bool hv_dense(const HvArgs<T>& a, int DG, int VPL, int ntiles) {
+  return a.pad && a.dstride == DG && a.nvec == a.tile_w * ntiles && a.tile_w == a.GL * VPL;
+}
+
+// Column layout of a lane group.  Default: lane g holds columns g + j*GL (one
+// coalesced load per column; gathers with clamped addresses and selects do
+// not merge into wide loads).  CONTIG kernels, launched by the host only where
+// the dense gather holds: lane g holds the adjacent columns g*VPL + j, so the
+// gather of one row is one wide load per lane.
+__host__ __device__ constexpr int hv_col_lane(bool contig, int vpl) { return contig ? vpl : 1; }
+__host__ __device__ constexpr int hv_col_step(bool contig, int gl) { return contig ? 1 : gl; }
+
 struct HvTabs {
   const double* rhoT;
   const double* Vt;
@@ -147,7 +164,7 @@ struct HvTabs {
 // The H.V over the representatives p = slot, slot + slot_stride, ... of one
 // column tile: lane group of GL lanes per representative (see the file text).
 // dot[j] accumulates q_j . w of this lane's column j in the Lanczos epilogue.
-template <typename T, int DG, int VPL, bool OTF, int NCH>
+template <typename T, int DG, int VPL, bool OTF, int NCH, bool CONTIG = false>
 __device__ __forceinline__ void hv_pass(const HvArgs<T>& a, const HvTabs& tb,
                                         const dev::OrbitTabs<word_t<NCH>, NCH>& otabs, int tile, int ntiles,
                                         uint64_t slot, uint64_t slot_stride, double (&dot)[VPL], bool (&vok)[VPL]) {
@@ -163,11 +180,13 @@ __device__ __forceinline__ void hv_pass(const HvArgs<T>& a, const HvTabs& tb,
   const int GL = a.GL;
   const int lg = lane & (GL - 1);
   const int gbase = lane - lg;
-  const int vbase = tile * a.tile_w + lg;
-#pragma unroll
-  for (int j = 0; j < VPL; ++j) vok[j] = vbase + j * GL < a.nvec;
   // uniform: the whole launch may gather without clamps (see the gather below)
-  const bool dense = a.pad && a.dstride == DG && a.nvec == a.tile_w * ntiles && a.tile_w == GL * VPL;
+  const bool dense = CONTIG || hv_dense(a, DG, VPL, ntiles);
+  // lane lg of the group owns columns vbase + j * vstep, j < VPL
+  const int vbase = tile * a.tile_w + lg * hv_col_lane(CONTIG, VPL);
+  const int vstep = hv_col_step(CONTIG, GL);
+#pragma unroll
+  for (int j = 0; j < VPL; ++j) vok[j] = vbase + j * vstep < a.nvec;
   const W lmask = (W(1) << a.b) - 1;
   const int ncand = 2 * a.nbonds;
 #pragma unroll
@@ -253,14 +272,14 @@ __device__ __forceinline__ void hv_pass(const HvArgs<T>& a, const HvTabs& tb,
 #pragma unroll
           for (int q = 0; q < DG; ++q)
 #pragma unroll
-            for (int j = 0; j < VPL; ++j) xv[q][j] = xr[q * a.ld + j * GL];
+            for (int j = 0; j < VPL; ++j) xv[q][j] = xr[q * a.ld + j * vstep];
         } else {
 #pragma unroll
           for (int q = 0; q < DG; ++q)
 #pragma unroll
             for (int j = 0; j < VPL; ++j) {
               const bool use = vok[j] && q < nr;
-              const uint64_t at = (offr + (q < nr ? q : 0)) * a.ld + (vok[j] ? vbase + j * GL : 0);
+              const uint64_t at = (offr + (q < nr ? q : 0)) * a.ld + (vok[j] ? vbase + j * vstep : 0);
               const T val = a.X[at];
               xv[q][j] = use ? val : T(0);
             }
@@ -336,7 +355,7 @@ __device__ __forceinline__ void hv_pass(const HvArgs<T>& a, const HvTabs& tb,
         }
         y *= sqL;
         if (vok[j]) {
-          const int v = vbase + j * GL;
+          const int v = vbase + j * vstep;
           const uint64_t at = (offp + k) * a.ld + v;
           const double xv = (double)a.X[at];
           const double hx = y + (ed - a.eshift) * xv;
@@ -354,7 +373,7 @@ __device__ __forceinline__ void hv_pass(const HvArgs<T>& a, const HvTabs& tb,
   }
 }
 
-template <typename T, int DG, int VPL, bool OTF, int NCH, bool LDS_TAB, bool SLDS>
+template <typename T, int DG, int VPL, bool OTF, int NCH, bool LDS_TAB, bool SLDS, bool CONTIG = false>
 __global__ void __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(DG * VPL <= FTLM_HV_FLOOR_WIDTH ? FTLM_HV_WAVES_PER_EU : 1)))
 k_hv(HvArgs<T> a) {
@@ -390,7 +409,7 @@ k_hv(HvArgs<T> a) {
   const uint64_t slot_stride = (uint64_t)gridDim.x * waves * slots_per_wave;
   double dot[VPL];
   bool vok[VPL];
-  hv_pass<T, DG, VPL, OTF, NCH>(a, tb, otabs, (int)blockIdx.y, (int)gridDim.y, slot, slot_stride, dot, vok);
+  hv_pass<T, DG, VPL, OTF, NCH, CONTIG>(a, tb, otabs, (int)blockIdx.y, (int)gridDim.y, slot, slot_stride, dot, vok);
   if (EPI) {
     __shared__ double red[kThreads];
     // one vector slot j at a time: lanes with equal lg hold the same column
@@ -401,7 +420,7 @@ k_hv(HvArgs<T> a) {
       if ((int)threadIdx.x < GL) {
         double s = 0.0;
         for (int q = 0; q < kThreads / GL; ++q) s += red[q * GL + threadIdx.x];
-        const int vv = blockIdx.y * a.tile_w + (int)threadIdx.x + j * GL;
+        const int vv = blockIdx.y * a.tile_w + (int)threadIdx.x * hv_col_lane(CONTIG, VPL) + j * hv_col_step(CONTIG, GL);
         if (vv < a.nvec) a.partials[(size_t)blockIdx.x * a.nvec + vv] = s;
       }
       __syncthreads();
@@ -411,7 +430,9 @@ k_hv(HvArgs<T> a) {
 
 template <typename T, int DG, int VPL, bool OTF, int NCH, bool LDS_TAB>
 void launch_k(const HvArgs<T>& a, const LaunchCfg& c, hipStream_t st) {
-  if (c.slds)
+  if (c.slds && c.contig && !OTF)
+    hipLaunchKernelGGL((k_hv<T, DG, VPL, OTF, NCH, LDS_TAB, true, true>), c.grid, dim3(kThreads), c.shm, st, a);
+  else if (c.slds)
     hipLaunchKernelGGL((k_hv<T, DG, VPL, OTF, NCH, LDS_TAB, true>), c.grid, dim3(kThreads), c.shm, st, a);
   else if constexpr (!OTF)
     hipLaunchKernelGGL((k_hv<T, DG, VPL, OTF, NCH, LDS_TAB, false>), c.grid, dim3(kThreads), c.shm, st, a);
