@@ -126,6 +126,11 @@ int hv_partial_groups(const Block& b, int nvec, int gl);
 // pad: X and Y use the padded row layout (representative i at i * d_Gamma).
 void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t stream,
                  const LanczosEpilogue* lz, int gl, bool pad = false);
+
+// Whether vectors of the block take the padded row layout (d_Gamma rows per
+// representative, zeros beyond n_Gamma): the block's lanczos_layout, or for
+// FTLM_LAYOUT_AUTO blocks of at least 2^20 rows that pad by at most 2%.
+bool padded_vectors(const Block& b);
 // Times every lane layout for (nvec, dtype) on this block, caches the fastest
 // process-wide and returns (lanes per representative, ms per launch) pairs.
 std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dtype, hipStream_t st, int reps);

@@ -21,11 +21,15 @@ namespace ftlm {
 
 namespace {
 
-// thread layout (row r0, chain v) as in the Lanczos kernels
+// thread layout (row r0, chain v) as in the Lanczos kernels; D rows of the
+// stored vectors.  With meta (padded layout) row i * dstride + k is block row
+// offset(i) + k of representative i, and rows k >= n_Gamma(i) are zeros.
 template <typename T>
 __global__ void __launch_bounds__(256) k_kpm_start(const uint64_t* __restrict__ keys, int dist, uint64_t D, int R,
                                                   const double* __restrict__ inv_norm, T* __restrict__ Q,
-                                                  T* __restrict__ Qz, double* __restrict__ partials) {
+                                                  T* __restrict__ Qz, double* __restrict__ partials,
+                                                  const uint64_t* __restrict__ meta,
+                                                  const double* __restrict__ stabf, int dstride) {
   __shared__ double red[256];
   const int t = threadIdx.x;
   const int RB = blockDim.x / R;
@@ -33,7 +37,16 @@ __global__ void __launch_bounds__(256) k_kpm_start(const uint64_t* __restrict__ 
   double acc = 0.0;
   if (r0 < RB)
     for (uint64_t row = (uint64_t)blockIdx.x * RB + r0; row < D; row += (uint64_t)gridDim.x * RB) {
-      const double x = dev::start_value(keys[v], row, dist);
+      uint64_t brow = row;
+      bool live = true;
+      if (meta) {
+        const uint64_t i = row / (uint64_t)dstride;
+        const int k = (int)(row - i * (uint64_t)dstride);
+        const uint64_t m = meta[i];
+        live = k < (int)stabf[4 * (m >> 48)];
+        brow = (m & ((1ull << 48) - 1)) + (uint64_t)k;
+      }
+      const double x = live ? dev::start_value(keys[v], brow, dist) : 0.0;
       if (inv_norm) {
         const T q = (T)(x * inv_norm[v]);
         Q[row * R + v] = q;
@@ -132,7 +145,11 @@ unsigned groups_for(uint64_t rows, int RB) {
 template <typename T>
 void kpm_typed(const Block& b, int R, int M, uint64_t seed, int dist, double center, double half_width,
                double* moments, hipStream_t st) {
-  const uint64_t D = b.D;
+  // the Lanczos run's row layout: padded rows give the H.V its dense gather
+  const bool pad = padded_vectors(b);
+  const uint64_t D = pad ? b.D_pad : b.D;
+  const uint64_t* meta = pad ? b.d_meta.p : nullptr;
+  const double* stabf = b.d_stabf64.p;
   const int TB = R * (256 / R);
   const unsigned nb = groups_for(D, TB / R);
   const int dtype = sizeof(T) == 8 ? FTLM_F64 : FTLM_F32;
@@ -162,10 +179,10 @@ void kpm_typed(const Block& b, int R, int M, uint64_t seed, int dist, double cen
   scal0.upload(s0, st);
   scal1.upload(s1, st);
   hipLaunchKernelGGL((k_kpm_start<T>), dim3(nb), dim3(TB), 0, st, keys.p, dist, D, R, (const double*)nullptr, q0.p,
-                     q1.p, pnrm.p);
+                     q1.p, pnrm.p, meta, stabf, b.dg);
   hipLaunchKernelGGL(k_kpm_init, dim3(R), dim3(256), 0, st, pnrm.p, (int)nb, R, inv_norm.p, rr.p, mu.p, M, 0);
   hipLaunchKernelGGL((k_kpm_start<T>), dim3(nb), dim3(TB), 0, st, keys.p, dist, D, R, inv_norm.p, q0.p, q1.p,
-                     pnrm.p);
+                     pnrm.p, meta, stabf, b.dg);
   hipLaunchKernelGGL(k_kpm_init, dim3(R), dim3(256), 0, st, pnrm.p, (int)nb, R, inv_norm.p, rr.p, mu.p, M, 1);
   FTLM_HIP(hipGetLastError());
   const int steps = M > 1 ? M / 2 : 0;  // step k yields moments 2k+1 and 2k+2
@@ -173,7 +190,7 @@ void kpm_typed(const Block& b, int R, int M, uint64_t seed, int dist, double cen
     T* tk = (k & 1) ? q1.p : q0.p;
     T* tprev = (k & 1) ? q0.p : q1.p;  // t_{k-1} on entry, t_{k+1} on exit
     LanczosEpilogue lz{k == 0 ? scal0.p : scal1.p, pdot.p, ng_hv, center};
-    apply_hv_gl(b, tk, tprev, R, R, dtype, st, &lz, gl, false);
+    apply_hv_gl(b, tk, tprev, R, R, dtype, st, &lz, gl, pad);
     hipLaunchKernelGGL((k_kpm_norm<T>), dim3(nb), dim3(TB), 0, st, D, R, tprev, pnrm.p);
     hipLaunchKernelGGL(k_kpm_moments, dim3(R), dim3(256), 0, st, pdot.p, ng_hv, pnrm.p, (int)nb, R, rr.p, mu.p, M,
                        k);

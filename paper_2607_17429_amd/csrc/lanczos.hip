@@ -309,6 +309,16 @@ uint64_t chain_key(uint64_t seed, int two_M, int irrep, int row, int chain) {
   return h;
 }
 
+bool padded_vectors(const Block& b) {
+  bool pad = false;
+  if (b.lanczos_layout == FTLM_LAYOUT_PADDED)
+    pad = true;
+  else if (b.lanczos_layout == FTLM_LAYOUT_AUTO)
+    pad = b.D >= (1ull << 20) && (double)b.D_pad <= 1.02 * (double)b.D;
+  if (pad && b.D_pad >= (1ull << 48)) fail(FTLM_ERR_UNSUPPORTED, "padded rows above 2^48");
+  return pad;
+}
+
 LanczosRun::LanczosRun(const Block& b, int R_, int steps_, uint64_t seed_, int storage_, int dist_)
     : block(&b), R(R_), steps(steps_), storage(storage_), dist(dist_), seed(seed_) {
   if (R <= 0 || R > 256) fail(FTLM_ERR_INVALID_ARG, "R must be in 1..256");
@@ -318,11 +328,7 @@ LanczosRun::LanczosRun(const Block& b, int R_, int steps_, uint64_t seed_, int s
     fail(FTLM_ERR_INVALID_ARG, "storage must be FTLM_F64, FTLM_F32 or FTLM_F16");
   const uint64_t D = b.D;
   target = (int)std::min<uint64_t>((uint64_t)steps, D);
-  if (b.lanczos_layout == FTLM_LAYOUT_PADDED)
-    pad = true;
-  else if (b.lanczos_layout == FTLM_LAYOUT_AUTO)
-    pad = D >= (1ull << 20) && (double)b.D_pad <= 1.02 * (double)D;
-  if (pad && b.D_pad >= (1ull << 48)) fail(FTLM_ERR_UNSUPPORTED, "padded rows above 2^48");
+  pad = padded_vectors(b);
   rows = pad ? b.D_pad : D;
   // FP16: elements of a unit vector are ~ 1/sqrt(rows); scale them to ~1
   sigma = 1.0;

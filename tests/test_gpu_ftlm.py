@@ -153,6 +153,48 @@ def test_padded_layout_against_oracle_and_block_layout():
     assert np.max(np.abs(b32[:, :15] - b32b[:, :15])) < 1e-6 * np.max(np.abs(b32b))
 
 
+@pytest.mark.parametrize("R", [6, 8, 24])
+def test_adjacent_column_kernel_against_oracle(R):
+    """Padded rows with d_Gamma equal to its dimension bucket and R filling the
+    column tiles (R = 6: 2 lanes x 3 columns, 8: 4 x 2, 24: 8 x 3) take the
+    kernel whose lanes hold adjacent columns.  Irrep dimensions 1, 3, 4 and 5:
+    coefficients of every chain equal the block layout's (the interleaved
+    kernel) and, for two chains, the oracle's Lanczos on the explicit block."""
+    name, two_s, two_M = "dodecahedron", 1, 0
+    _, _, irs = oracle_group(name)
+    sec, H = oracle_sector(name, two_s, two_M)
+    S = lib_block(name, two_s, two_M, 8).sector
+    seen = set()
+    for gi, ir in enumerate(irs):
+        d = ir.rho.shape[1]
+        if d in seen or d not in (1, 3, 4, 5):
+            continue
+        seen.add(d)
+        log(f"[lanczos] adjacent columns R={R} irrep {gi} (d={d})")
+        LP = P.Block(S, gi, 0, user_rho=ir.rho, layout=P.LAYOUT_PADDED)
+        LB = P.Block(S, gi, 0, user_rho=ir.rho, layout=P.LAYOUT_BLOCK)
+        if LP.D == 0:
+            continue
+        a, b, n, info = LP.ftlm(R, 24, 31, storage=P.F64, info=True)
+        assert info["layout"] == P.LAYOUT_PADDED
+        a1, b1, n1 = LB.ftlm(R, 24, 31, storage=P.F64)
+        k = int(min(n.min(), n1.min(), 12))
+        assert np.max(np.abs(a[:, :k] - a1[:, :k])) < 1e-12 * np.max(np.abs(a1[:, :k]))
+        assert np.max(np.abs(b[:, :k] - b1[:, :k])) < 1e-12 * np.max(np.abs(b1[:, :k]))
+        B = oracle_block(name, two_s, two_M, gi)
+        Hb = (B.Psi.T @ H @ B.Psi).tocsr()
+        for r in (0, R - 1):
+            v0 = oftlm.start_vector(B.D, 31, two_M, gi, 0, r, "rademacher")
+            oa, ob = oftlm.lanczos(lambda x: Hb @ x, v0, 24)
+            kk = min(k, len(oa))
+            assert np.max(np.abs(a[r, :kk] - oa[:kk])) < 1e-10 * np.max(np.abs(oa[:kk]))
+        # FP32 storage on the same layout: the stored rows round the same way
+        a32, _, _ = LP.ftlm(R, 12, 31, storage=P.F32)
+        a32b, _, _ = LB.ftlm(R, 12, 31, storage=P.F32)
+        assert np.max(np.abs(a32[:, :8] - a32b[:, :8])) < 1e-5 * np.max(np.abs(a32b[:, :8]))
+    assert seen == {1, 3, 4, 5}
+
+
 @pytest.mark.timeout(600)
 def test_auto_layout_at_scale_matches_block_layout():
     """On the icosidodecahedron H_g block (D = 6,465,762) AUTO picks the padded

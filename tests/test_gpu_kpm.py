@@ -56,6 +56,31 @@ def test_kpm_moments_against_oracle(name, two_s, two_M, gi, M, storage):
         assert np.max(np.abs(mom[r] - want)) < tol, (r, np.max(np.abs(mom[r] - want)))
 
 
+@pytest.mark.parametrize("R,storage", [(3, "f64"), (8, "f64"), (24, "f32")])
+def test_kpm_padded_rows_against_oracle(R, storage):
+    """Blocks whose Lanczos vectors take the padded row layout run KPM in it
+    too (the H.V's dense gather; R = 8 and 24 fill the column tiles): the
+    moments equal the oracle's and the block layout's."""
+    name, two_s, two_M, gi = "dodecahedron", 1, 0, 8
+    log(f"[kpm] padded rows R={R} {storage}")
+    _, _, irs = oracle_group(name)
+    sec, H = oracle_sector(name, two_s, two_M)
+    B = oracle_block(name, two_s, two_M, gi)
+    Hb = hv.block_matrix(B, H)
+    c, w = _bounds(Hb)
+    S = lib_sector(name, two_s, two_M)
+    LP = P.Block(S, gi, 0, user_rho=irs[gi].rho, layout=P.LAYOUT_PADDED)
+    LB = P.Block(S, gi, 0, user_rho=irs[gi].rho, layout=P.LAYOUT_BLOCK)
+    st = P.F64 if storage == "f64" else P.F32
+    mp = LP.kpm(R, 64, 5, c, w, storage=st)
+    mb = LB.kpm(R, 64, 5, c, w, storage=st)
+    tol = 1e-10 if storage == "f64" else 1e-5
+    assert np.max(np.abs(mp - mb)) < tol
+    for r in (0, R - 1):
+        v0 = oftlm.start_vector(B.D, 5, two_M, gi, 0, r, "rademacher")
+        assert np.max(np.abs(mp[r] - okpm.moments(Hb, v0, c, w, 64))) < tol
+
+
 def test_kpm_start_vectors_are_the_lanczos_chains():
     LB = P.Block(lib_sector("icosahedron", 1, 0), 8, 0)
     a, b, n = LB.ftlm(4, 5, 23)
