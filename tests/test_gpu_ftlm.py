@@ -159,7 +159,8 @@ def test_adjacent_column_kernel_against_oracle(R):
     column tiles (R = 6: 2 lanes x 3 columns, 8: 4 x 2, 24: 8 x 3) take the
     kernel whose lanes hold adjacent columns.  Irrep dimensions 1, 3, 4 and 5:
     coefficients of every chain equal the block layout's (the interleaved
-    kernel) and, for two chains, the oracle's Lanczos on the explicit block."""
+    kernel) and, for two chains, the oracle's Lanczos on the explicit block;
+    FP32 and FP16 storage against the block layout at their rounding level."""
     name, two_s, two_M = "dodecahedron", 1, 0
     _, _, irs = oracle_group(name)
     sec, H = oracle_sector(name, two_s, two_M)
@@ -192,6 +193,10 @@ def test_adjacent_column_kernel_against_oracle(R):
         a32, _, _ = LP.ftlm(R, 12, 31, storage=P.F32)
         a32b, _, _ = LB.ftlm(R, 12, 31, storage=P.F32)
         assert np.max(np.abs(a32[:, :8] - a32b[:, :8])) < 1e-5 * np.max(np.abs(a32b[:, :8]))
+        # FP16 storage: a column taken from the wrong chain would differ at the percent level
+        a16, _, _ = LP.ftlm(R, 8, 31, storage=P.F16)
+        a16b, _, _ = LB.ftlm(R, 8, 31, storage=P.F16)
+        assert np.max(np.abs(a16[:, :6] - a16b[:, :6])) < 1e-3 * np.max(np.abs(a16b[:, :6]))
     assert seen == {1, 3, 4, 5}
 
 
