@@ -136,9 +136,12 @@ typedef struct ftlm_block ftlm_block;
  * the reals.  Its row block (any row) is the real form of the complex block
  * of either member of the pair: twice its dimension, every level twice; in
  * the thermal sums it carries the trace weight d = dim / 2 (ftlm_ritz.d_gamma).
- * This replaces the paper's complex-arithmetic path.  Irreps are computed for
- * |G| <= 1024; a group with a quaternionic irrep (indicator -1) builds, but
- * its irreps report COMPLEX_IRREP_UNSUPPORTED. */
+ * An irrep of quaternionic type (indicator -1, d even) is listed as its
+ * realification, a real orthogonal representation of dimension 2d
+ * (indicator reported as -1), irreducible over the reals; its row block is
+ * again the real form of the complex block and carries the trace weight
+ * d / 2 = dim / 4.  This replaces the paper's complex-arithmetic path.
+ * Irreps are computed for |G| <= 1024. */
 int ftlm_group_create(int32_t N, const int32_t* gens, int32_t ngens, ftlm_group** out);
 /* |G|, number of irreps, number of conjugacy classes, number of sites. */
 int ftlm_group_info(const ftlm_group* g, int32_t* order, int32_t* n_irreps, int32_t* n_classes,
@@ -146,7 +149,8 @@ int ftlm_group_info(const ftlm_group* g, int32_t* order, int32_t* n_irreps, int3
 /* Permutation table, |G| x N int32 (host array owned by the caller). */
 int ftlm_group_elements(const ftlm_group* g, int32_t* perms);
 /* Per irrep: dimension, Frobenius-Schur indicator (0 marks a realified
- * complex pair, trace weight dim / 2; +1 a real-type irrep, weight dim),
+ * complex pair, trace weight dim / 2; -1 a realified quaternionic irrep,
+ * weight dim / 4; +1 a real-type irrep, weight dim),
  * characters of the real form by class (n_irreps x n_classes, row-major) and
  * the class of every element (|G|).  Any pointer may be NULL.  Also the
  * largest verification residual. */

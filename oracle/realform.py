@@ -1,4 +1,4 @@
-"""Real forms of irreps of complex type (Frobenius-Schur indicator 0).
+"""Real forms of irreps of complex and quaternionic type (indicators 0, -1).
 
 TEST INFRASTRUCTURE: part of the FP64 CPU oracle; only tests, the smoke
 check and the benchmark's CPU baseline use it.
@@ -26,8 +26,16 @@ real arithmetic instead, and this module states what it computes:
   weight copies of each block's spectrum, which the tests check by exact
   diagonalization.
 
-Quaternionic irreps (indicator -1) are not realified here (the library
-rejects them).
+* An irrep Gamma of quaternionic type (indicator -1, d even) is equivalent to
+  its conjugate; its realification rho_R (same formula, dimension 2d) is
+  irreducible over the reals with a four-dimensional real commutant (the
+  quaternions), character 2 chi, and its rows satisfy the same relation (the
+  commutant's non-identity elements are antisymmetric, so they do not reach
+  the diagonal).  Its row block is again the real form of the complex Gamma
+  block (real dimension 2 D_Gamma, every level of the Gamma block twice, and
+  the Gamma block's levels come in pairs themselves).  Gamma contributes
+  d Tr_Gamma f(H) = (d / 2) Tr_{rho_R block} f(H): trace weight
+  d / 2 = dim(rho_R) / 4.
 """
 from __future__ import annotations
 
@@ -41,24 +49,26 @@ from .irreps import Irrep
 
 @dataclass
 class RealForm:
-    irrep: Irrep        # real orthogonal matrices (dim d for real type, 2d for a realified pair)
+    irrep: Irrep        # real orthogonal matrices (dim d for real type, 2d when realified)
     weight: int         # trace weight in the thermal sums
-    kind: str           # "real" or "complex pair"
+    kind: str           # "real", "complex pair" or "quaternionic"
 
 
 def realify(ir: Irrep) -> Irrep:
-    """rho_R = [[Re rho, -Im rho], [Im rho, Re rho]] of a complex-type irrep."""
-    if ir.indicator != 0:
-        raise ValueError("realification is for irreps of complex type (indicator 0)")
+    """rho_R = [[Re rho, -Im rho], [Im rho, Re rho]] of a complex- or
+    quaternionic-type irrep (the indicator is kept: 0 or -1)."""
+    if ir.indicator not in (0, -1):
+        raise ValueError("realification is for irreps of complex or quaternionic type")
     re, im = ir.rho.real, ir.rho.imag
     rho = np.block([[re, -im], [im, re]])
     chars = np.trace(rho, axis1=1, axis2=2).astype(complex)   # = 2 Re chi
-    return Irrep(2 * ir.dim, rho, chars, 0)
+    return Irrep(2 * ir.dim, rho, chars, ir.indicator)
 
 
 def real_forms(G: Group, irreps) -> list:
-    """One real form per real-type irrep and per conjugate pair of complex-type
-    irreps (the first of the pair in the given order is realified).
+    """One real form per real-type irrep, per conjugate pair of complex-type
+    irreps (the first of the pair in the given order is realified) and per
+    quaternionic irrep (realified, weight d / 2).
 
     Order: dimension of the real form ascending, then its character over the
     canonical class order descending (rounded to 1e-9), as for the irreps."""
@@ -77,7 +87,9 @@ def real_forms(G: Group, irreps) -> list:
             used.add(conj[0])
             out.append(RealForm(realify(ir), ir.dim, "complex pair"))
         else:
-            raise NotImplementedError("quaternionic irreps have no real form here")
+            if ir.dim % 2:
+                raise AssertionError("a quaternionic irrep has even dimension")
+            out.append(RealForm(realify(ir), ir.dim // 2, "quaternionic"))
         used.add(i)
 
     def key(f):

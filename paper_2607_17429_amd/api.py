@@ -45,8 +45,9 @@ class Group:
         res = C.c_double()
         check(lib().ftlm_group_irreps(self._h, dims.ctypes.data_as(L.I32P), ind.ctypes.data_as(L.I32P),
                                       chars.ctypes.data_as(L.F64P), cls.ctypes.data_as(L.I32P), C.byref(res)))
-        # indicator 0 marks a realified complex pair: trace weight dim / 2
-        weights = np.where(ind == 0, dims // 2, dims)
+        # realified irreps: a complex pair (indicator 0) has trace weight
+        # dim / 2, a quaternionic irrep (indicator -1) dim / 4
+        weights = np.where(ind == 0, dims // 2, np.where(ind == -1, dims // 4, dims))
         return dict(dims=dims, indicators=ind, weights=weights, chars=chars, class_of=cls, residual=res.value)
 
     def rho(self, irrep):

@@ -165,7 +165,7 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
     if (!(res < 1e-9)) fail(FTLM_ERR_BAD_RHO, "user rho is not an orthogonal representation (residual " + std::to_string(res) + ")");
   } else {
     if (!G.irreps_computed) fail(FTLM_ERR_UNSUPPORTED, "group irreps not available (|G| > 1024); pass user_rho");
-    if (!G.all_real) fail(FTLM_ERR_COMPLEX_IRREP_UNSUPPORTED, "group has quaternionic irreps (no real form)");
+    if (!G.all_real) fail(FTLM_ERR_COMPLEX_IRREP_UNSUPPORTED, "the group's real irreps are incomplete");
     if (base_irrep >= (int)G.irreps.size()) fail(FTLM_ERR_IRREP_OUT_OF_RANGE, "irrep index out of range");
     const Irrep& ir = G.irreps[base_irrep];
     if (ir.dim > 12) fail(FTLM_ERR_DIM_GT_12, "irrep dimension above 12");

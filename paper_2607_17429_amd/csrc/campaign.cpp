@@ -41,7 +41,7 @@ void run_campaign(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, co
   auto t0 = clk::now();
   auto G = std::make_shared<Group>(build_group(cl->N, gens, ngens));
   compute_irreps(*G);
-  if (!G->all_real) fail(FTLM_ERR_COMPLEX_IRREP_UNSUPPORTED, "group has quaternionic irreps (no real form)");
+  if (!G->all_real) fail(FTLM_ERR_COMPLEX_IRREP_UNSUPPORTED, "the group's real irreps are incomplete");
   // sector and block builds on `stream`, per-step Lanczos runs on the worker
   // streams, batches of fused small-block jobs on `wstream`
   hipStream_t stream = nullptr, wstream = nullptr;

@@ -14,8 +14,12 @@
 // indicator 0 it is a conjugate pair Gamma, Gamma* of complex type in real
 // form (dimension 2 d_Gamma); it is kept as one real irrep of kind 2, whose
 // blocks are the real forms of the complex Gamma blocks (the paper keeps a
-// complex-arithmetic path for these; here everything stays real).  A
-// quaternionic irrep (<chi, chi> = 4) is left out and all_real is false.
+// complex-arithmetic path for these; here everything stays real).  With
+// <chi, chi> = 4 and indicator -2 it is the realification (dimension 2 d_Gamma)
+// of a quaternionic irrep Gamma, kept as one real irrep of kind 4: its real
+// commutant is the quaternions, whose non-identity units are antisymmetric,
+// so each row again satisfies (dim/|G|) sum_g rho_am rho_am' = delta_mm', and
+// its row block is the real form of the Gamma block (trace weight dim / 4).
 #include "group.h"
 
 #include <algorithm>
@@ -293,9 +297,9 @@ double verify_irreps(const Group& G, const std::vector<const Irrep*>& irs) {
         for (int j = 0; j < A.dim; ++j)
           for (int k = 0; k < B.dim; ++k)
             for (int l = 0; l < B.dim; ++l) {
-              // a realified pair (kind 2) satisfies the relation within one
-              // row (i == k), which is what the block construction uses
-              if (x == y && A.kind == 2 && i != k) continue;
+              // a realified irrep (kind 2 or 4) satisfies the relation within
+              // one row (i == k), which is what the block construction uses
+              if (x == y && A.kind >= 2 && i != k) continue;
               double s = 0;
               for (int g = 0; g < n; ++g)
                 s += A.rho[((size_t)g * A.dim + i) * A.dim + j] * B.rho[((size_t)g * B.dim + k) * B.dim + l];
@@ -354,12 +358,13 @@ void compute_irreps(Group& G) {
       double nu = 0;
       for (int g = 0; g < n; ++g) nu += chi[G.idx_mul(g, g)];
       nu /= n;
-      // <chi, chi> = 1: real type; 2 with indicator 0: a complex pair,
-      // irreducible over the reals; anything else (quaternionic, or a
-      // degenerate split) is left out
+      // <chi, chi> = 1: real type; 2 with indicator 0: a complex pair; 4 with
+      // indicator -2: a realified quaternionic irrep (both irreducible over
+      // the reals); anything else (a degenerate split) is left out
       int kind = 0;
       if (std::fabs(nrm / n - 1.0) < 1e-6 && std::fabs(nu - 1.0) < 1e-6) kind = 1;
       if (std::fabs(nrm / n - 2.0) < 1e-6 && std::fabs(nu) < 1e-6 && m % 2 == 0) kind = 2;
+      if (std::fabs(nrm / n - 4.0) < 1e-6 && std::fabs(nu + 2.0) < 1e-6 && m % 4 == 0) kind = 4;
       if (!kind) { complete = false; continue; }
       std::vector<long long> key(nclass);
       for (int cc = 0; cc < nclass; ++cc) key[cc] = std::llround(chi[rep_of_class[cc]] * 1e6);
@@ -380,7 +385,8 @@ void compute_irreps(Group& G) {
       }
       ir.chars.resize(nclass);
       for (int cc = 0; cc < nclass; ++cc) ir.chars[cc] = chi[rep_of_class[cc]];
-      ir.indicator = (int)std::lround(nu);
+      // reported: the Frobenius-Schur indicator of the complex irrep (+1, 0, -1)
+      ir.indicator = kind == 4 ? -1 : (int)std::lround(nu);
       found.emplace(key, std::move(ir));
     }
     std::vector<Irrep> irs;
@@ -393,7 +399,9 @@ void compute_irreps(Group& G) {
       }
       return false;
     });
-    int sumsq = 0;  // sum over complex irreps of d^2: a realified pair holds two of dimension dim / 2
+    // sum over complex irreps of d^2: a realified pair holds two of dimension
+    // dim / 2, a realified quaternionic irrep one of dimension dim / 2
+    int sumsq = 0;
     for (auto& ir : irs) sumsq += ir.dim * ir.weight();
     std::vector<const Irrep*> ptrs;
     for (auto& ir : irs) ptrs.push_back(&ir);

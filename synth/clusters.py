@@ -233,6 +233,46 @@ def complete_graph(N: int) -> Cluster:
     return Cluster(f"K{N}", N, bonds, np.stack([cyc, swap]), group_order=order)
 
 
+def _qmul(p, q):
+    a1, b1, c1, d1 = p
+    a2, b2, c2, d2 = q
+    return (a1 * a2 - b1 * b2 - c1 * c2 - d1 * d2, a1 * b2 + b1 * a2 + c1 * d2 - d1 * c2,
+            a1 * c2 - b1 * d2 + c1 * a2 + d1 * b2, a1 * d2 + b1 * c2 - c1 * b2 + d1 * a2)
+
+
+def dicyclic(n: int) -> Cluster:
+    """Dicyclic group Dic_n (order 4n; Dic_2 is the quaternion group Q8) as
+    unit quaternions generated by a = exp(i pi / n) and x = j, acting on its 4n
+    elements (the sites) by left multiplication.  Bonds: the Cayley graph of
+    right multiplication by a and by x, which left multiplication preserves.
+    Its two-dimensional irreps on which a^n = -1 acts are quaternionic."""
+    gen_q = [(np.cos(np.pi / n), np.sin(np.pi / n), 0.0, 0.0), (0.0, 0.0, 1.0, 0.0)]
+    elems = [(1.0, 0.0, 0.0, 0.0)]
+
+    def find(q):
+        for k, e in enumerate(elems):
+            if max(abs(u - v) for u, v in zip(e, q)) < 1e-9:
+                return k
+        return -1
+
+    k = 0
+    while k < len(elems):
+        for g in gen_q:
+            q = _qmul(elems[k], g)
+            if find(q) < 0:
+                elems.append(q)
+        k += 1
+    N = len(elems)
+    gens = [np.array([find(_qmul(g, e)) for e in elems], dtype=np.int32) for g in gen_q]
+    bonds = set()
+    for g in gen_q:
+        for i, e in enumerate(elems):
+            j = find(_qmul(e, g))
+            if i != j:
+                bonds.add((min(i, j), max(i, j)))
+    return Cluster(f"dic{n}", N, np.array(sorted(bonds), dtype=np.int32), np.stack(gens), group_order=4 * n)
+
+
 BUILTIN = {
     "icosahedron": icosahedron,
     "dodecahedron": dodecahedron,
@@ -251,6 +291,8 @@ def get(name: str) -> Cluster:
         if name.endswith("_C"):      # cyclic group only (translations of the ring)
             return ring(int(name[4:-2]), dihedral=False)
         return ring(int(name[4:]))
+    if name.startswith("dic"):
+        return dicyclic(int(name[3:]))
     if name.startswith("K"):
         return complete_graph(int(name[1:]))
     if name.startswith("square") and "x" in name:

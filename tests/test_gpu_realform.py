@@ -1,12 +1,13 @@
-"""GPU parity of the real forms of complex-type irreps (translation groups).
+"""GPU parity of the real forms of complex-type irreps (translation groups)
+and of quaternionic irreps (dicyclic groups Dic_2 = Q8, Dic_3).
 
 * Blocks built with the oracle's realified irreps (user_rho, trace weight
-  dim/2): dimensions, n_Gamma and offsets bit for bit against the oracle's
+  dim/2 for a complex pair, dim/4 when quaternionic): dimensions, n_Gamma and offsets bit for bit against the oracle's
   block of the same real form, FP64 H.V within 1e-12 of Psi^T H Psi X, and
   the Lanczos coefficients of the fused and the per-step kernels against the
   oracle's recurrence.
 * The whole campaign with the library's own irreps (realified pairs, weight
-  dim/2) against the oracle's FTLM estimator run on the same blocks (the
+  dim/2; realified quaternionic irreps, weight dim/4) against the oracle's FTLM estimator run on the same blocks (the
   library's irrep matrices, the same chain keys and start vectors): E, C,
   chi within 1e-9 relative; ln Z(T -> inf) = N ln(2s+1) exactly.
 """
@@ -22,7 +23,8 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 P = pytest.importorskip("paper_2607_17429_amd")
 
-CASES = [("ring8_C", 1, 0), ("square3x3_T", 1, 1), ("ring6_C", 2, 0), ("ring5_C", 3, 1), ("square4x4_T", 1, 0)]
+CASES = [("ring8_C", 1, 0), ("square3x3_T", 1, 1), ("ring6_C", 2, 0), ("ring5_C", 3, 1), ("square4x4_T", 1, 0),
+         ("dic2", 3, 0), ("dic3", 1, 2), ("dic3", 1, 0)]
 
 
 def _setup(name, two_s, two_M):
@@ -50,7 +52,7 @@ def test_realified_blocks_and_hv_fp64(name, two_s, two_M):
         assert np.array_equal(ex["offsets"].astype(np.int64), B.offsets)
         if B.D == 0:
             continue
-        pairs += f.kind == "complex pair"
+        pairs += f.kind != "real"
         for nvec in (1, 5):
             X = rng.standard_normal((B.D, nvec))
             Y = LB.apply_H(torch.from_numpy(X).cuda()).cpu().numpy()
@@ -58,11 +60,11 @@ def test_realified_blocks_and_hv_fp64(name, two_s, two_M):
     assert pairs > 0
 
 
-@pytest.mark.parametrize("name,two_s,two_M", CASES[:4])
+@pytest.mark.parametrize("name,two_s,two_M", CASES[:4] + CASES[5:7])
 def test_realified_block_lanczos_against_oracle(name, two_s, two_M):
     cl, G, forms, sec, H, S = _setup(name, two_s, two_M)
     for k, f in enumerate(forms):
-        if f.kind != "complex pair":
+        if f.kind == "real":
             continue
         B = basis.build_block(G, f.irrep, sec)
         if B.D < 2:
@@ -83,7 +85,7 @@ def test_realified_block_lanczos_against_oracle(name, two_s, two_M):
                 assert np.max(np.abs(b[r, :m] - ob[:m])) <= 1e-10 * np.max(np.abs(ob)), (k, r)
 
 
-@pytest.mark.parametrize("name,two_s", [("ring8_C", 1), ("square3x3_T", 1), ("ring6_C", 2)])
+@pytest.mark.parametrize("name,two_s", [("ring8_C", 1), ("square3x3_T", 1), ("ring6_C", 2), ("dic2", 2), ("dic3", 1)])
 def test_campaign_with_realified_pairs_matches_oracle_ftlm(name, two_s):
     log(f"[realform] campaign {name} 2s={two_s}")
     cl = clusters.get(name)

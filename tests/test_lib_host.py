@@ -123,10 +123,12 @@ def test_observables_errors():
         P.observables([dict(two_M=0, d_gamma=1, D=1, thetas=[np.zeros(1)], weights=[np.ones(1)])], np.array([-1.0]))
 
 
-@pytest.mark.parametrize("name", ["ring5_C", "ring8_C", "square3x3_T", "square4x4_T", "ring6", "cuboctahedron"])
+@pytest.mark.parametrize("name", ["ring5_C", "ring8_C", "square3x3_T", "square4x4_T", "ring6", "cuboctahedron",
+                                  "dic2", "dic3", "dic5"])
 def test_real_forms_match_oracle(name):
     """Complex-type irreps come as realified pairs (indicator 0, weight dim/2),
-    in the oracle's order and with its real-form characters."""
+    quaternionic ones realified (indicator -1, weight dim/4), in the oracle's
+    order and with its real-form characters."""
     from oracle import realform
     cl = clusters.get(name)
     G = P.Group(cl.N, cl.gens)
@@ -136,7 +138,8 @@ def test_real_forms_match_oracle(name):
     rep_class = [c[0] for c in OG.classes]
     assert list(ir["dims"]) == [f.irrep.dim for f in forms]
     assert list(ir["weights"]) == [f.weight for f in forms]
-    assert list(ir["indicators"]) == [0 if f.kind == "complex pair" else 1 for f in forms]
+    kinds = {"real": 1, "complex pair": 0, "quaternionic": -1}
+    assert list(ir["indicators"]) == [kinds[f.kind] for f in forms]
     assert int((ir["dims"] * ir["weights"]).sum()) == G.order
     assert ir["residual"] < 1e-12
     for k, f in enumerate(forms):
@@ -169,16 +172,27 @@ def _q8_regular():
     return np.stack(gens)
 
 
-def test_quaternionic_group_is_rejected():
+def test_quaternion_group_irreps():
+    """Q8 from its multiplication table (independent of the quaternion
+    arithmetic of the dic2 cluster): four real one-dimensional irreps and the
+    realified two-dimensional quaternionic irrep (dimension 4, weight 1,
+    character 2 chi: 4 at 1, -4 at -1, 0 elsewhere)."""
     gens = _q8_regular()
     G = P.Group(8, gens)
     assert G.order == 8
     ir = G.irreps()
-    assert list(ir["dims"]) == [1, 1, 1, 1]          # the quaternionic 2-dim irrep has no real form here
-    cl = clusters.complete_graph(8)
-    with pytest.raises(P.FtlmError) as e:
-        P.campaign(cl, gens, 1, 2, 5, 1, np.array([1.0]))
-    assert e.value.name == "COMPLEX_IRREP_UNSUPPORTED"
+    assert list(ir["dims"]) == [1, 1, 1, 1, 4]
+    assert list(ir["indicators"]) == [1, 1, 1, 1, -1]
+    assert list(ir["weights"]) == [1, 1, 1, 1, 1]
+    assert ir["residual"] < 1e-12
+    perms = G.elements()
+    ident = np.arange(8)
+    minus = perms[[k for k in range(8) if not np.array_equal(perms[k], ident) and
+                   np.array_equal(perms[k][perms[k]], ident)][0]]
+    rho = G.rho(4)
+    for k in range(8):
+        want = 4.0 if np.array_equal(perms[k], ident) else -4.0 if np.array_equal(perms[k], minus) else 0.0
+        assert abs(np.trace(rho[k]) - want) < 1e-12
 
 
 def test_kpm_observables_match_oracle():

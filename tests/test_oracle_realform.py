@@ -1,18 +1,20 @@
-"""Pins of the real forms of complex-type irreps (oracle/realform.py).
+"""Pins of the real forms of complex- and quaternionic-type irreps (oracle/realform.py).
 
 Checked against what the mathematics fixes, independently of the module:
 
 * every real form is an orthogonal homomorphism; its rows satisfy the
   orthogonality the block construction uses; a realified pair has character
   2 Re chi, indicator 0 and a two-dimensional real commutant (irreducible over
-  the reals, not absolutely irreducible); a real-type irrep has a
-  one-dimensional commutant;
+  the reals, not absolutely irreducible); a realified quaternionic irrep has
+  character 2 chi, indicator -2 and a four-dimensional commutant; a real-type
+  irrep has a one-dimensional commutant;
 * for the cyclic group C_N the real forms are the closed-form rotations by
   2 pi k m / N (characters 2 cos), plus the trivial and (N even) sign irreps;
 * completeness: sum over real forms of weight x dim = |G|;
-* the block of a realified pair has, by exact diagonalization, the spectrum
-  of the complex-arithmetic block of Gamma (built from the complex irrep)
-  with every eigenvalue twice, and twice its dimension;
+* the block of a realified pair or quaternionic irrep has, by exact
+  diagonalization, the spectrum of the complex-arithmetic block of Gamma
+  (built from the complex irrep) with every eigenvalue twice, and twice its
+  dimension; a quaternionic Gamma block has its levels in pairs;
 * the union over real forms of weight copies of each block spectrum is the
   spectrum of the whole sector (full exact diagonalization of the sector),
   and the block dimensions equal the character formula.
@@ -23,7 +25,7 @@ import pytest
 from oracle import basis, counting, group, irreps, realform, sector
 from synth import clusters
 
-GROUPS = ["ring5_C", "ring8_C", "square3x3_T", "ring6", "icosahedron"]
+GROUPS = ["ring5_C", "ring8_C", "square3x3_T", "ring6", "icosahedron", "dic2", "dic3", "dic5"]
 
 
 def _group(name):
@@ -56,6 +58,9 @@ def test_real_forms_are_real_orthogonal_representations(name):
         if f.kind == "complex pair":
             assert f.weight * 2 == dim and abs(nu) < 1e-9 and null == 2
             assert abs(np.dot(chi, chi) / n - 2.0) < 1e-9
+        elif f.kind == "quaternionic":
+            assert f.weight * 4 == dim and abs(nu + 2) < 1e-9 and null == 4
+            assert abs(np.dot(chi, chi) / n - 4.0) < 1e-9
         else:
             assert f.weight == dim and abs(nu - 1) < 1e-9 and null == 1
 
@@ -74,7 +79,8 @@ def test_cyclic_real_forms_closed_form(N):
     assert sum(f.kind == "complex pair" for f in forms) == (N - 1) // 2
 
 
-CASES = [("ring8_C", 1, 0), ("ring8_C", 1, 2), ("square3x3_T", 1, 1), ("ring6_C", 2, 0), ("ring5_C", 3, 1)]
+CASES = [("ring8_C", 1, 0), ("ring8_C", 1, 2), ("square3x3_T", 1, 1), ("ring6_C", 2, 0), ("ring5_C", 3, 1),
+         ("dic2", 2, 0), ("dic2", 1, 2), ("dic3", 1, 0), ("dic3", 1, 2)]
 
 
 def _hblock(Bk, H):
@@ -89,7 +95,7 @@ def test_realified_block_is_doubled_complex_block(name, two_s, two_M):
     H = sector.hamiltonian(sec.labels, cl.N, two_s, cl.bonds, cl.J)
     pairs = 0
     for ir in irs:
-        if ir.indicator != 0:
+        if ir.indicator not in (0, -1):
             continue
         BR = basis.build_block(G, realform.realify(ir), sec)
         BC = basis.build_block(G, ir, sec)
@@ -102,6 +108,8 @@ def test_realified_block_is_doubled_complex_block(name, two_s, two_M):
         eR = np.linalg.eigvalsh(_hblock(BR, H))
         eC = np.linalg.eigvalsh(_hblock(BC, H))
         assert np.allclose(eR, np.sort(np.concatenate([eC, eC])), atol=1e-10)
+        if ir.indicator == -1:
+            assert np.allclose(eC[0::2], eC[1::2], atol=1e-10)
     assert pairs > 0
 
 
