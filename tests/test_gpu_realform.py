@@ -125,9 +125,11 @@ def test_campaign_with_realified_pairs_matches_oracle_ftlm(name, two_s):
     assert res["stats"]["blocks"] == len(blocks)
 
 
-@pytest.mark.parametrize("name,two_s", [("ring8_C", 1), ("square4x4_T", 1)])
+@pytest.mark.parametrize("name,two_s", [("ring8_C", 1), ("square4x4_T", 1), ("dic2", 2), ("dic3", 1)])
 def test_realified_pairs_with_spin_flip(name, two_s):
-    """G x Z2 at M = 0 over real forms: Gamma^+ and Gamma^- of every form."""
+    """G x Z2 at M = 0 over real forms: Gamma^+ and Gamma^- of every form
+    (complex pairs and quaternionic irreps); a campaign with the flip keeps
+    ln Z(T -> inf) = N ln(2s + 1), so the trace weights add up."""
     from oracle import spinflip
     cl = clusters.get(name)
     G = group.close(cl.gens, cl.N)
@@ -148,3 +150,5 @@ def test_realified_pairs_with_spin_flip(name, two_s):
         X = rng.standard_normal((B.D, 3))
         Y = LB.apply_H(torch.from_numpy(X).cuda()).cpu().numpy()
         assert rel_err_cols(Y, hv.apply(B, H, X)) <= 1e-12, gi2
+    hi = P.campaign(cl, cl.gens, two_s, 4, 20, 5, np.array([1e9]), storage=P.F64, spin_flip=True)
+    assert abs(hi["logZ"][0] - cl.N * np.log(two_s + 1)) < 1e-6
