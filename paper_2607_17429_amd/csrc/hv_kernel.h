@@ -430,9 +430,15 @@ k_hv(HvArgs<T> a) {
 
 template <typename T, int DG, int VPL, bool OTF, int NCH, bool LDS_TAB>
 void launch_k(const HvArgs<T>& a, const LaunchCfg& c, hipStream_t st) {
-  if (c.slds && c.contig && !OTF)
-    hipLaunchKernelGGL((k_hv<T, DG, VPL, OTF, NCH, LDS_TAB, true, true>), c.grid, dim3(kThreads), c.shm, st, a);
-  else if (c.slds)
+  // adjacent-column kernels for the dimension buckets 1-6 (a dense launch of
+  // bucket 8 or 12 needs d_Gamma exactly 8 or 12; it takes the default layout)
+  if constexpr (!OTF && DG <= 6) {
+    if (c.slds && c.contig) {
+      hipLaunchKernelGGL((k_hv<T, DG, VPL, OTF, NCH, LDS_TAB, true, true>), c.grid, dim3(kThreads), c.shm, st, a);
+      return;
+    }
+  }
+  if (c.slds)
     hipLaunchKernelGGL((k_hv<T, DG, VPL, OTF, NCH, LDS_TAB, true>), c.grid, dim3(kThreads), c.shm, st, a);
   else if constexpr (!OTF)
     hipLaunchKernelGGL((k_hv<T, DG, VPL, OTF, NCH, LDS_TAB, false>), c.grid, dim3(kThreads), c.shm, st, a);
