@@ -204,7 +204,8 @@ def test_adjacent_column_kernel_against_oracle(R):
 def test_auto_layout_at_scale_matches_block_layout():
     """On the icosidodecahedron H_g block (D = 6,465,762) AUTO picks the padded
     layout (0.16% extra rows); its FP64 coefficients agree with the block
-    layout's over the first steps."""
+    layout's over the first steps, and so do those of the benchmark's
+    configuration (24 Gaussian chains, FP32 storage) to FP32 rounding."""
     log("[lanczos] auto layout at scale")
     cl = clusters.get("icosidodecahedron")
     G = P.Group(cl.N, cl.gens)
@@ -217,6 +218,14 @@ def test_auto_layout_at_scale_matches_block_layout():
     assert info1["layout"] == P.LAYOUT_BLOCK and info1["rows"] == 6465762
     assert np.max(np.abs(a - a1)) < 1e-11 * np.max(np.abs(a1))
     assert np.max(np.abs(b - b1)) < 1e-11 * np.max(np.abs(b1))
+    # the benchmark's launch configuration: 24 Gaussian chains in FP32 storage
+    # (padded rows, adjacent columns per lane) against the block layout
+    log("[lanczos] bench configuration, padded against block rows")
+    a, b, n, info = BA.ftlm(24, 6, 0x5EED0003, storage=P.F32, dist=P.GAUSSIAN, info=True)
+    a1, b1, n1, info1 = BB.ftlm(24, 6, 0x5EED0003, storage=P.F32, dist=P.GAUSSIAN, info=True)
+    assert info["layout"] == P.LAYOUT_PADDED and info1["layout"] == P.LAYOUT_BLOCK
+    assert np.max(np.abs(a - a1)) < 1e-6 * np.max(np.abs(a1))
+    assert np.max(np.abs(b - b1)) < 1e-6 * np.max(np.abs(b1))
 
 
 def test_graph_replayed_steps_equal_direct_launches():
