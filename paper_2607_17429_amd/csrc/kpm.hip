@@ -87,6 +87,40 @@ __global__ void __launch_bounds__(256) k_kpm_norm(uint64_t D, int R, const T* __
   }
 }
 
+// <t, t> per column with NV adjacent columns per thread (one 16-byte load):
+// CPR = R / NV column groups per row, blockDim.x / CPR rows per block pass;
+// partial sums per column as in k_kpm_norm.
+template <typename T, int NV>
+__global__ void __launch_bounds__(256) k_kpm_norm_vec(uint64_t D, int R, const T* __restrict__ Q,
+                                                     double* __restrict__ partials) {
+  typedef T vec_t __attribute__((ext_vector_type(NV)));
+  __shared__ double red[256];
+  const int t = threadIdx.x;
+  const int CPR = R / NV;
+  const int RB = blockDim.x / CPR;
+  const int cg = t % CPR, r0 = t / CPR;
+  double acc[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+  if (r0 < RB)
+    for (uint64_t row = (uint64_t)blockIdx.x * RB + r0; row < D; row += (uint64_t)gridDim.x * RB) {
+      const vec_t q = *(const vec_t*)(Q + row * R + (uint64_t)cg * NV);
+#pragma unroll
+      for (int k = 0; k < NV; ++k) acc[k] += (double)q[k] * (double)q[k];
+    }
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    red[t] = acc[k];
+    __syncthreads();
+    if (t < CPR) {
+      double s = 0.0;
+      for (int q = 0; q < RB; ++q) s += red[q * CPR + t];
+      partials[(size_t)blockIdx.x * R + t * NV + k] = s;
+    }
+    __syncthreads();
+  }
+}
+
 __device__ __forceinline__ double group_sum(const double* __restrict__ partials, int ngroups, int R, int v) {
   __shared__ double red[256];
   double s = 0.0;
@@ -191,7 +225,14 @@ void kpm_typed(const Block& b, int R, int M, uint64_t seed, int dist, double cen
     T* tprev = (k & 1) ? q0.p : q1.p;  // t_{k-1} on entry, t_{k+1} on exit
     LanczosEpilogue lz{k == 0 ? scal0.p : scal1.p, pdot.p, ng_hv, center};
     apply_hv_gl(b, tk, tprev, R, R, dtype, st, &lz, gl, pad);
-    hipLaunchKernelGGL((k_kpm_norm<T>), dim3(nb), dim3(TB), 0, st, D, R, tprev, pnrm.p);
+    constexpr int NV = 16 / (int)sizeof(T);
+    if (R % NV == 0 && ((uintptr_t)tprev & 15) == 0) {
+      // rows of whole 16-byte column groups, every row 16-byte aligned
+      const int cpr = R / NV;
+      hipLaunchKernelGGL((k_kpm_norm_vec<T, NV>), dim3(nb), dim3(cpr * (256 / cpr)), 0, st, D, R, tprev, pnrm.p);
+    } else {
+      hipLaunchKernelGGL((k_kpm_norm<T>), dim3(nb), dim3(TB), 0, st, D, R, tprev, pnrm.p);
+    }
     hipLaunchKernelGGL(k_kpm_moments, dim3(R), dim3(256), 0, st, pdot.p, ng_hv, pnrm.p, (int)nb, R, rr.p, mu.p, M,
                        k);
     FTLM_HIP(hipGetLastError());
