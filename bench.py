@@ -345,8 +345,8 @@ def main():
     if args.hw_queues:
         os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 32))
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only "
-                                   "(see DESIGN.md), so --gpus must be 1"}))
+        print(json.dumps({"error": "the library runs on one GPU (sharding across GPUs is not implemented), "
+                                   "so --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np
