@@ -114,7 +114,7 @@ def main():
     with open(os.path.join(args.out, f"hv_traffic_{args.workload}.json"), "w") as f:
         json.dump(rec, f, indent=1)
     md = [f"# k_hv on {args.workload}: rocprofv3 summary", "",
-          "Commands (from the repository root of the GPU box):", "", "```", args.cmd, "```", "",
+          "Commands (from the repository root):", "", "```", args.cmd, "```", "",
           "## Kernel trace statistics (one bench step, `bench.py --steps 1 --warmup 0 --no-cpu-baseline`)", "",
           kernel_stats_markdown(args.stats), ""]
     if args.trace:
