@@ -89,16 +89,19 @@ def test_kpm_start_vectors_are_the_lanczos_chains():
     assert np.allclose(mom[:, 1], (a[:, 0] - c) / w, rtol=1e-12, atol=1e-14)
 
 
-def test_kpm_realified_pair_against_oracle():
-    cl = clusters.get("ring8_C")
+@pytest.mark.parametrize("name,two_s", [("ring8_C", 1), ("dic2", 3), ("dic3", 1)])
+def test_kpm_realified_pair_against_oracle(name, two_s):
+    """Realified complex pairs (C_8, Dic_3) and quaternionic irreps (Dic_2, Dic_3)."""
+    log(f"[kpm] realified forms {name} 2s={two_s}")
+    cl = clusters.get(name)
     G = group.close(cl.gens, cl.N)
     forms = realform.real_forms(G, irreps.compute_irreps(G))
-    sec = basis.sector_reps(G, cl.N, 1, 0)
-    H = sector.hamiltonian(sec.labels, cl.N, 1, cl.bonds, cl.J)
-    S = P.Sector(cl, lib_group("ring8_C"), 0, two_s=1)
+    sec = basis.sector_reps(G, cl.N, two_s, 0)
+    H = sector.hamiltonian(sec.labels, cl.N, two_s, cl.bonds, cl.J)
+    S = P.Sector(cl, lib_group(name), 0, two_s=two_s)
     done = 0
     for k, f in enumerate(forms):
-        if f.kind != "complex pair":
+        if f.kind == "real":
             continue
         B = basis.build_block(G, f.irrep, sec)
         if B.D == 0:
