@@ -50,7 +50,7 @@ enum ftlm_status {
   FTLM_ERR_IRREP_OUT_OF_RANGE = -5,
   FTLM_ERR_ROW_OUT_OF_RANGE = -6,
   FTLM_ERR_DIM_GT_12 = -7,
-  FTLM_ERR_COMPLEX_IRREP_UNSUPPORTED = -8,
+  FTLM_ERR_COMPLEX_IRREP_UNSUPPORTED = -8, /* the group's real irreps do not cover all of its irreps */
   FTLM_ERR_OUT_OF_MEMORY = -9,
   FTLM_ERR_HIP = -10,
   FTLM_ERR_BAD_RHO = -11,
