@@ -75,32 +75,34 @@ def start_vector(D: int, seed: int, two_M: int, irrep: int, row: int, chain: int
 
 
 def lanczos(matvec, v0, steps: int):
+    """Three-term Lanczos recurrence on unit vectors (Section 2.2), no
+    reorthogonalisation.  v_0 = v0 / |v0|; for j = 0, 1, ...:
+    w = H v_j - beta_j v_{j-1};  alpha_j = <v_j, w>;  w -= alpha_j v_j;
+    beta_{j+1} = |w|;  v_{j+1} = w / beta_{j+1}.
+    n = min(steps, D) products; the chain stops early when
+    beta_{j+1} <= 1e-10 * max_{i<=j}(|alpha_i| + beta_i + beta_{i+1}).
+    Returns alpha_0..alpha_{n-1} and beta_1..beta_n."""
     D = len(v0)
     n_target = min(steps, D)
     alphas, betas = [], []
     if n_target == 0:
         return np.zeros(0), np.zeros(0)
-    q_prev = np.zeros_like(v0)
-    q = np.array(v0, dtype=np.float64)
-    s = 1.0 / np.linalg.norm(q)
-    s_prev, beta_j = 0.0, 0.0
+    v = np.array(v0, dtype=np.float64)
+    v = v / np.linalg.norm(v)
+    v_prev = np.zeros_like(v)
+    beta_j = 0.0
     scale = 0.0
     for j in range(n_target):
-        w = s * matvec(q)
-        if j > 0:
-            w = w - beta_j * s_prev * q_prev
-        a = s * float(np.dot(q, w))
-        w = w - a * s * q
+        w = matvec(v) - beta_j * v_prev
+        a = float(np.dot(v, w))
+        w = w - a * v
         b = float(np.linalg.norm(w))
         alphas.append(a)
         betas.append(b)
         scale = max(scale, abs(a) + beta_j + b)
-        if j + 1 == n_target:
+        if j + 1 == n_target or b <= 1e-10 * scale:
             break
-        if b <= 1e-10 * scale:
-            break
-        q_prev, s_prev = q, s
-        q, s, beta_j = w, 1.0 / b, b
+        v_prev, v, beta_j = v, w / b, b
     return np.array(alphas), np.array(betas)
 
 

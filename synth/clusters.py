@@ -233,6 +233,23 @@ def complete_graph(N: int) -> Cluster:
     return Cluster(f"K{N}", N, bonds, np.stack([cyc, swap]), group_order=order)
 
 
+def petersen() -> Cluster:
+    """Petersen graph: sites are the 2-subsets of {0..4} (lexicographic), bonds
+    join disjoint subsets (15 bonds, 3 per site); its automorphism group is S5
+    (order 120, irreps of dimension 1, 1, 4, 4, 5, 5, 6), generated by the
+    transposition (0 1) and the 5-cycle (0 1 2 3 4) acting on the subsets."""
+    subsets = list(itertools.combinations(range(5), 2))
+    index = {s: k for k, s in enumerate(subsets)}
+    bonds = np.array([(a, b) for a in range(10) for b in range(a + 1, 10)
+                      if not set(subsets[a]) & set(subsets[b])], dtype=np.int32)
+
+    def perm_of(p):
+        return np.array([index[tuple(sorted((p[i], p[j])))] for i, j in subsets], dtype=np.int32)
+
+    gens = np.stack([perm_of([1, 0, 2, 3, 4]), perm_of([1, 2, 3, 4, 0])])
+    return Cluster("petersen", 10, bonds, gens, group_order=120)
+
+
 def _qmul(p, q):
     a1, b1, c1, d1 = p
     a2, b2, c2, d2 = q
@@ -281,6 +298,7 @@ BUILTIN = {
     "square4": lambda: square_torus(4),
     "square6": lambda: square_torus(6),
     "dimer": dimer,
+    "petersen": petersen,
 }
 
 

@@ -23,7 +23,8 @@ def _block_spectra(cl, G, irs, two_s, two_M, alpha=0):
 
 
 @pytest.mark.parametrize("name,two_s", [("icosahedron", 1), ("cuboctahedron", 1), ("ring6", 1),
-                                        ("ring6", 2), ("ring5", 1), ("square4", 1), ("K4", 3)])
+                                        ("ring6", 2), ("ring5", 1), ("square4", 1), ("K4", 3),
+                                        ("petersen", 1), ("petersen", 2)])
 def test_union_of_block_spectra_is_sector_spectrum(name, two_s):
     """Section 4.1: every block against the dense reference of the full M sector."""
     cl, G, irs = _setup(name)
@@ -180,3 +181,57 @@ def test_free_orbit_counts():
         for i in free:
             assert B.n_stab[i] == ir.dim
             assert np.allclose(B.V_stab[i], np.eye(ir.dim))
+
+
+def _image_loop(label, perm, N, d, flip):
+    """Label of U(g) F^f |a> by loops over sites: digit k moves to site perm[k]."""
+    dig = []
+    x = int(label)
+    for _ in range(N):
+        x, r = divmod(x, d)
+        dig.append(r)
+    if flip:
+        dig = [d - 1 - a for a in dig]
+    new = [0] * N
+    for k in range(N):
+        new[perm[k]] = dig[k]
+    return sum(a * d ** k for k, a in enumerate(new))
+
+
+@pytest.mark.parametrize("name,two_s,flip", [("icosahedron", 1, False), ("cuboctahedron", 2, False),
+                                             ("icosahedron", 1, True), ("ring6", 3, False)])
+def test_connecting_element_is_smallest_minimiser(name, two_s, flip):
+    """The connecting element h of a label a is the smallest group index among
+    all g with U(g) a = min O(a) (the reading of the choice the paper leaves
+    free, Section 2.4): every g applied by loops over sites, the minimisers
+    collected, and their count equal to the stabilizer order of the
+    representative.  Labels with non-trivial stabilizers, where several
+    minimisers tie, are sampled on purpose."""
+    from oracle import spinflip
+    cl = clusters.get(name)
+    G = group.close(cl.gens, cl.N)
+    GG = spinflip.FlipGroup(G) if flip else G
+    d = two_s + 1
+    rng = np.random.default_rng(5)
+    ties = 0
+    twoMs = [0] if flip else range((cl.N * two_s) % 2, cl.N * two_s + 1, 2)
+    for two_M in twoMs:
+        labels = sector.enumerate_sector(cl.N, two_s, two_M)
+        sec = basis.sector_reps(GG, cl.N, two_s, two_M)
+        # representatives with non-trivial stabilizers and a few members of their orbits
+        big = [int(r) for r, s in zip(sec.reps, sec.stab_id) if len(sec.stab_sets[s]) > 1]
+        picks = set(rng.choice(labels, size=min(len(labels), 12), replace=False).tolist())
+        for r in big[:6]:
+            orbit = basis.apply_all(GG, np.array([r]), cl.N, d)[0]
+            picks.update(int(x) for x in rng.choice(orbit, size=3))
+        picks = sorted(picks)
+        rep, h = basis.canonicalize(GG, np.array(picks, dtype=np.int64), cl.N, d)
+        for a, r0, h0 in zip(picks, rep, h):
+            imgs = [_image_loop(a, G.perms[g % G.order], cl.N, d, g >= G.order) for g in range(GG.order)]
+            m = min(imgs)
+            mins = [g for g, x in enumerate(imgs) if x == m]
+            assert r0 == m and h0 == mins[0], (a, r0, h0, mins[:4])
+            ridx = int(np.searchsorted(sec.reps, m))
+            assert len(mins) == len(sec.stab_sets[sec.stab_id[ridx]])
+            ties += len(mins) > 1
+    assert ties >= 5

@@ -171,3 +171,46 @@ def test_ed_observables_high_T_expansion():
     T = np.array([200.0])
     _, C, _ = ftlm.ed_observables(spectra, T)
     assert abs(C[0] * T[0] ** 2 / (30 * 0.75 ** 2 / 3) - 1) < 0.02
+
+
+def test_lanczos_reproduces_a_jacobi_matrix():
+    """Started from e_1, the recurrence on a symmetric tridiagonal matrix with
+    positive off-diagonal returns exactly its diagonal (alpha) and off-diagonal
+    (beta): the Lanczos tridiagonalisation of a Jacobi matrix is the matrix
+    itself.  Under an orthogonal similarity Q T Q^T started from Q e_1 the
+    coefficients are unchanged.  A dropped term, a wrong sign or a shifted
+    index in the recurrence breaks one of these."""
+    rng = np.random.default_rng(17)
+    n = 12
+    diag = rng.standard_normal(n)
+    off = rng.uniform(0.5, 2.0, n - 1)
+    T = np.diag(diag) + np.diag(off, 1) + np.diag(off, -1)
+    e1 = np.zeros(n)
+    e1[0] = 1.0
+    a, b = ftlm.lanczos(lambda x: T @ x, e1, n)
+    assert len(a) == n
+    assert np.max(np.abs(a - diag)) < 1e-13
+    assert np.max(np.abs(b[: n - 1] - off)) < 1e-13
+    assert abs(b[n - 1]) < 1e-12              # the Krylov space is exhausted
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = Q @ T @ Q.T
+    a2, b2 = ftlm.lanczos(lambda x: A @ x, 3.0 * (Q @ e1), n)   # any start norm
+    assert np.max(np.abs(a2 - diag)) < 1e-12
+    assert np.max(np.abs(b2[: n - 1] - off)) < 1e-12
+    # fewer steps: the leading part of the same coefficients
+    a3, b3 = ftlm.lanczos(lambda x: A @ x, Q @ e1, 5)
+    assert len(a3) == 5 and np.max(np.abs(a3 - diag[:5])) < 1e-12 and np.max(np.abs(b3 - off[:5])) < 1e-12
+
+
+def test_gaussian_start_values_are_standard_normal():
+    """Box-Muller values before normalisation: the standard normal law by a
+    Kolmogorov-Smirnov test, with its third and fourth moments (0 and 3)."""
+    import scipy.stats as st
+    D = 200000
+    g = ftlm.start_vector(D, 11, 0, 2, 0, 3, "gaussian")
+    # the unit vector times sqrt(D): the raw draws up to their sample RMS (1 +- 0.3%)
+    x = g * np.sqrt(D)
+    ks = st.kstest(x, "norm")
+    assert ks.pvalue > 1e-3, ks
+    assert abs(np.mean(x ** 3)) < 0.05
+    assert abs(np.mean(x ** 4) - 3.0) < 0.1

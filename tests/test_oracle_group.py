@@ -19,7 +19,7 @@ def ih():
 @pytest.mark.parametrize("name,order", [
     ("icosahedron", 120), ("dodecahedron", 120), ("icosidodecahedron", 120),
     ("cuboctahedron", 48), ("square4", 128), ("square6", 288), ("ring6", 12),
-    ("dimer", 2), ("K4", 24)])
+    ("dimer", 2), ("K4", 24), ("petersen", 120)])
 def test_group_order_and_bond_invariance(name, order):
     cl = clusters.get(name)
     G = group.close(cl.gens, cl.N)
@@ -60,7 +60,7 @@ def test_ih_classes_and_cycle_types():
         assert got == exp, name
 
 
-@pytest.mark.parametrize("name", ["icosahedron", "cuboctahedron", "square4", "ring6", "K4"])
+@pytest.mark.parametrize("name", ["icosahedron", "cuboctahedron", "square4", "ring6", "K4", "petersen"])
 def test_irreps_invariants(name):
     cl = clusters.get(name)
     G = group.close(cl.gens, cl.N)
@@ -129,6 +129,20 @@ def test_oh_dims():
     irs = irreps.compute_irreps(G)
     assert sorted(ir.dim for ir in irs) == [1, 1, 1, 1, 2, 2, 3, 3, 3, 3]
     assert all(ir.indicator == 1 for ir in irs)
+
+
+def test_petersen_group_is_s5():
+    """The Petersen graph's automorphism group is S5: irreps of dimension
+    1, 1, 4, 4, 5, 5, 6 (the partitions of 5), all of real type, and the
+    6-dimensional one has character 0 on transpositions (hook partition)."""
+    cl = clusters.get("petersen")
+    G = group.close(cl.gens, cl.N)
+    irs = irreps.compute_irreps(G)
+    assert [ir.dim for ir in irs] == [1, 1, 4, 4, 5, 5, 6]
+    assert all(ir.indicator == 1 for ir in irs)
+    # the transposition (0 1) is the first generator: chi_6 = 0 there
+    t = next(i for i, p in enumerate(G.perms) if np.array_equal(p, cl.gens[0]))
+    assert abs(irs[6].chars[t]) < 1e-12
 
 
 def test_square_lattice_group_5x8_has_28_irreps():
