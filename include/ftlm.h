@@ -149,13 +149,15 @@ int ftlm_group_info(const ftlm_group* g, int32_t* order, int32_t* n_irreps, int3
 /* Permutation table, |G| x N int32 (host array owned by the caller). */
 int ftlm_group_elements(const ftlm_group* g, int32_t* perms);
 /* Per irrep: dimension, Frobenius-Schur indicator (0 marks a realified
- * complex pair, trace weight dim / 2; -1 a realified quaternionic irrep,
- * weight dim / 4; +1 a real-type irrep, weight dim),
+ * complex pair, -1 a realified quaternionic irrep, +1 a real-type irrep),
+ * trace weight in the thermal sums of Eq. (14) (the d_Gamma factor: dim for
+ * a real-type irrep, dim / 2 for a realified complex pair, dim / 4 for a
+ * realified quaternionic irrep; the block's ftlm_block_info.trace_weight),
  * characters of the real form by class (n_irreps x n_classes, row-major) and
  * the class of every element (|G|).  Any pointer may be NULL.  Also the
  * largest verification residual. */
-int ftlm_group_irreps(const ftlm_group* g, int32_t* dims, int32_t* indicators, double* chars,
-                      int32_t* class_of, double* max_residual);
+int ftlm_group_irreps(const ftlm_group* g, int32_t* dims, int32_t* indicators, int32_t* weights,
+                      double* chars, int32_t* class_of, double* max_residual);
 /* Irrep matrices rho(g), |G| x d x d row-major. */
 int ftlm_group_rho(const ftlm_group* g, int32_t irrep, double* rho);
 void ftlm_group_free(ftlm_group* g);
@@ -258,14 +260,54 @@ int ftlm_block_hv_stats(const ftlm_block* b, ftlm_hv_stats* stats);
 int ftlm_apply_H(ftlm_block* b, const void* X, void* Y, int32_t nvec, int64_t ld, int32_t dtype,
                  void* stream);
 
+/* Options of ftlm_apply_H_ex: the row layout and the fused Lanczos step of
+ * the H.V that ftlm_run launches (Eqs. 15-16; the recurrence of Section 2.2).
+ * A zeroed struct asks for the row layout ftlm_run takes on this block, the
+ * tuned or default lane layout, no epilogue and no shift. */
+typedef struct ftlm_hv_opts {
+  int32_t layout;         /* enum ftlm_layout of X and Y.  BLOCK: D rows in block order.
+                             PADDED: n_reps * d_Gamma rows, representative i at row
+                             i * d_Gamma; rows k >= n_Gamma(i) of X must hold zeros, and
+                             those rows of Y are not written.  AUTO: the layout ftlm_run
+                             takes for this block (ftlm_run_info.layout). */
+  int32_t lanes;          /* lanes per output representative: a power of two 1..64, or 0
+                             for the autotuned or default choice of ftlm_run */
+  const double* scale;    /* device, nvec pairs (s_v, b_v), or NULL.  With it the call is
+                             the first half of a Lanczos step: Y[:, v] <- s_v (H - shift)
+                             X[:, v] - b_v Y[:, v] (Y read, then overwritten; FP64
+                             arithmetic, one rounding to storage) */
+  double* dots;           /* device, nvec doubles, or NULL (needs scale): sum over rows of
+                             X[:, v] Y[:, v], Y as stored by this call, summed in FP64 in
+                             a fixed order (bitwise reproducible) */
+  double shift;           /* the call applies H - shift (0: H) */
+  int32_t lanes_used;     /* out: lanes per representative of the launch */
+  int32_t adjacent_columns; /* out: 1 when the launch ran the kernel whose lanes hold
+                             adjacent columns (padded rows, d_Gamma equal to its kernel
+                             bucket 1..6, nvec a whole number of column tiles): the
+                             kernel of ftlm_run's large blocks */
+  int64_t reserved[4];
+} ftlm_hv_opts;
+
+/* ftlm_apply_H with the options above (opts == NULL: exactly ftlm_apply_H).
+ * dtype F64, F32 or F16 (storage; FP64 arithmetic).  X and Y must not
+ * overlap.  With scale, device scratch of one FP64 partial sum per workgroup
+ * and vector is allocated (stream-ordered) for the call.  Enqueued on stream
+ * (asynchronous).  Errors: INVALID_ARG (bad layout, lanes, nvec or ld, dots
+ * without scale), UNSUPPORTED (padded rows above 2^48), HIP. */
+int ftlm_apply_H_ex(ftlm_block* b, const void* X, void* Y, int32_t nvec, int64_t ld, int32_t dtype,
+                    ftlm_hv_opts* opts, void* stream);
+
 /* Autotuner: times every lane layout of the H.V kernel (lanes per output
  * representative 1..64, vectors per lane) for nvec columns of dtype on this
- * block, on stream, and keeps the fastest in a process-wide cache keyed by
- * (N, 2s, |G|, irrep dimension, nvec, dtype, H.V mode); later apply and run
- * calls with that key use it.  Outputs (may be NULL): the chosen lanes per
- * representative and its time per launch in ms; up to 8 (lanes, ms) pairs in
- * tried/tried_ms with their count in n_tried.  Allocates two D x nvec
- * scratch arrays for the duration of the call.  Synchronous. */
+ * block, on stream, first for the launch ftlm_run and ftlm_kpm make on this
+ * block (its row layout, with the Lanczos epilogue), then for the plain
+ * launch of ftlm_apply_H (block rows), and keeps the fastest of each in a
+ * process-wide cache keyed by (N, 2s, |G|, irrep dimension, nvec, dtype, H.V
+ * mode, row layout, epilogue); later calls with that key use it.  Outputs
+ * (may be NULL) describe the first: the chosen lanes per representative and
+ * its time per launch in ms; up to 8 (lanes, ms) pairs in tried/tried_ms
+ * with their count in n_tried.  Allocates two rows x nvec scratch arrays for
+ * the duration of the call.  Synchronous. */
 int ftlm_block_autotune(ftlm_block* b, int32_t nvec, int32_t dtype, void* stream, int32_t* best_lanes,
                         double* best_ms, int32_t* tried, double* tried_ms, int32_t* n_tried);
 

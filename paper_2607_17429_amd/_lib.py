@@ -67,6 +67,12 @@ class HvStats(C.Structure):
                 ("reserved", C.c_int32)]
 
 
+class HvOpts(C.Structure):
+    _fields_ = [("layout", C.c_int32), ("lanes", C.c_int32), ("scale", C.c_void_p), ("dots", C.c_void_p),
+                ("shift", C.c_double), ("lanes_used", C.c_int32), ("adjacent_columns", C.c_int32),
+                ("reserved", C.c_int64 * 4)]
+
+
 class CampaignOpts(C.Structure):
     _fields_ = [("R", C.c_int32), ("steps", C.c_int32), ("seed", C.c_uint64), ("storage", C.c_int32),
                 ("dist", C.c_int32), ("all_M", C.c_int32), ("two_M", C.c_int32), ("spin_flip", C.c_int32),
@@ -126,7 +132,7 @@ SIGNATURES = {
     "ftlm_group_create": (C.c_int, [C.c_int32, I32P, C.c_int32, C.POINTER(VP)]),
     "ftlm_group_info": (C.c_int, [VP, I32P, I32P, I32P, I32P]),
     "ftlm_group_elements": (C.c_int, [VP, I32P]),
-    "ftlm_group_irreps": (C.c_int, [VP, I32P, I32P, F64P, I32P, F64P]),
+    "ftlm_group_irreps": (C.c_int, [VP, I32P, I32P, I32P, F64P, I32P, F64P]),
     "ftlm_group_rho": (C.c_int, [VP, C.c_int32, F64P]),
     "ftlm_group_free": (None, [VP]),
     "ftlm_sector_create": (C.c_int, [C.POINTER(Cluster), VP, C.c_int32, C.POINTER(Opts), C.POINTER(VP)]),
@@ -142,6 +148,7 @@ SIGNATURES = {
                                     F64P, C.POINTER(C.c_uint64)]),
     "ftlm_block_hv_stats": (C.c_int, [VP, C.POINTER(HvStats)]),
     "ftlm_apply_H": (C.c_int, [VP, VP, VP, C.c_int32, C.c_int64, C.c_int32, VP]),
+    "ftlm_apply_H_ex": (C.c_int, [VP, VP, VP, C.c_int32, C.c_int64, C.c_int32, C.POINTER(HvOpts), VP]),
     "ftlm_block_autotune": (C.c_int, [VP, C.c_int32, C.c_int32, VP, I32P, F64P, I32P, F64P, I32P]),
     "ftlm_run": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, F64P, F64P, I32P, VP]),
     "ftlm_run_ex": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, F64P, F64P, I32P, VP,

@@ -40,14 +40,13 @@ class Group:
         n = self.n_irreps
         dims = np.empty(n, np.int32)
         ind = np.empty(n, np.int32)
+        weights = np.empty(n, np.int32)
         chars = np.empty((n, self.n_classes))
         cls = np.empty(self.order, np.int32)
         res = C.c_double()
         check(lib().ftlm_group_irreps(self._h, dims.ctypes.data_as(L.I32P), ind.ctypes.data_as(L.I32P),
-                                      chars.ctypes.data_as(L.F64P), cls.ctypes.data_as(L.I32P), C.byref(res)))
-        # realified irreps: a complex pair (indicator 0) has trace weight
-        # dim / 2, a quaternionic irrep (indicator -1) dim / 4
-        weights = np.where(ind == 0, dims // 2, np.where(ind == -1, dims // 4, dims))
+                                      weights.ctypes.data_as(L.I32P), chars.ctypes.data_as(L.F64P),
+                                      cls.ctypes.data_as(L.I32P), C.byref(res)))
         return dict(dims=dims, indicators=ind, weights=weights, chars=chars, class_of=cls, residual=res.value)
 
     def rho(self, irrep):
@@ -188,6 +187,40 @@ class Block:
         check(lib().ftlm_apply_H(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), X.shape[1],
                                  X.stride(0), dtype, L.stream_handle(stream)))
         return Y
+
+    @property
+    def D_pad(self):
+        """Rows of the padded layout: n_reps * d_Gamma."""
+        return self.n_reps * self.d_gamma
+
+    def apply_H_ex(self, X, Y=None, layout=0, lanes=0, scale=None, dots=None, shift=0.0, stream=None):
+        """ftlm_apply_H_ex on (rows, nvec) torch CUDA tensors: rows = D (LAYOUT_BLOCK) or
+        n_reps * d_Gamma (LAYOUT_PADDED; AUTO = the layout ftlm_run takes).  scale:
+        float64 CUDA tensor (nvec, 2) of (s, b) pairs, Y <- s (H - shift) X - b Y;
+        dots: float64 CUDA tensor (nvec,) receiving sum_rows X * Y.  Returns Y and the launch's (lanes_used, adjacent_columns)."""
+        import torch
+        if X.dim() == 1:
+            X = X[:, None]
+        assert X.is_cuda
+        if Y is None:
+            Y = torch.zeros_like(X)
+        dtype = {torch.float64: F64, torch.float32: F32, torch.float16: F16}[X.dtype]
+        assert Y.dtype == X.dtype and Y.shape == X.shape
+        assert X.stride(1) == 1 and Y.stride(1) == 1 and X.stride(0) == Y.stride(0)
+        o = L.HvOpts()
+        o.layout = int(layout)
+        o.lanes = int(lanes)
+        if scale is not None:
+            assert scale.dtype == torch.float64 and scale.is_cuda and scale.is_contiguous()
+            assert scale.numel() == 2 * X.shape[1]
+            o.scale = scale.data_ptr()
+        if dots is not None:
+            assert dots.dtype == torch.float64 and dots.is_cuda and dots.numel() >= X.shape[1]
+            o.dots = dots.data_ptr()
+        o.shift = float(shift)
+        check(lib().ftlm_apply_H_ex(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), X.shape[1],
+                                    X.stride(0), dtype, C.byref(o), L.stream_handle(stream)))
+        return Y, dict(lanes_used=o.lanes_used, adjacent_columns=o.adjacent_columns)
 
     def kpm(self, R, n_moments, seed, center, half_width, storage=F64, dist=RADEMACHER, stream=None):
         """Chebyshev moments (ftlm_kpm): R x n_moments."""

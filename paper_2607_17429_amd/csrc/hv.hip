@@ -68,25 +68,51 @@ dim3 hv_grid(const Block& b, const Layout& L) {
 
 uint32_t align16(uint64_t x) { return (uint32_t)((x + 15u) & ~uint64_t(15)); }
 
-// Process-wide autotuner cache: lanes per representative for a kernel shape.
+// Process-wide autotuner cache: lanes per representative for a kernel shape,
+// keyed also by the row layout (block or padded rows) and by whether the
+// Lanczos epilogue runs, since both change which kernel instantiation a lane
+// layout selects.
 struct TuneKey {
-  int N, two_s, G, dgp, nvec, dtype, mode;
+  int N, two_s, G, dgp, nvec, dtype, mode, pad, epi;
   bool operator<(const TuneKey& o) const {
-    return std::tie(N, two_s, G, dgp, nvec, dtype, mode) < std::tie(o.N, o.two_s, o.G, o.dgp, o.nvec, o.dtype, o.mode);
+    return std::tie(N, two_s, G, dgp, nvec, dtype, mode, pad, epi) <
+           std::tie(o.N, o.two_s, o.G, o.dgp, o.nvec, o.dtype, o.mode, o.pad, o.epi);
   }
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, int> g_tune;
 
-TuneKey tune_key(const Block& b, int nvec, int dtype) {
+TuneKey tune_key(const Block& b, int nvec, int dtype, bool pad, bool epi) {
   const Sector& s = *b.sec;
-  return TuneKey{s.N, s.two_s, s.gorder, b.dgp, nvec, dtype, s.hv_mode};
+  return TuneKey{s.N, s.two_s, s.gorder, b.dgp, nvec, dtype, s.hv_mode, pad ? 1 : 0, epi ? 1 : 0};
 }
 
-int tuned_gl(const Block& b, int nvec, int dtype) {
+int tuned_gl(const Block& b, int nvec, int dtype, bool pad, bool epi) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tune.find(tune_key(b, nvec, dtype));
+  auto it = g_tune.find(tune_key(b, nvec, dtype, pad, epi));
   return it == g_tune.end() ? 0 : it->second;
+}
+
+// Column sums of a (ng x nvec) array of per-workgroup partials, one workgroup
+// per column, in a fixed order.
+__global__ void __launch_bounds__(256) k_col_sums(const double* __restrict__ partials, int ng, int nvec,
+                                                 double* __restrict__ out) {
+  __shared__ double red[256];
+  const int v = blockIdx.x;
+  double s = 0.0;
+  for (int g = threadIdx.x; g < ng; g += blockDim.x) s += partials[(size_t)g * nvec + v];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = blockDim.x / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[v] = red[0];
+}
+
+__global__ void k_fill_f64(double* __restrict__ p, int n, double x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = x;
 }
 
 }  // namespace
@@ -98,8 +124,8 @@ int irrep_dim_bucket(int d) {
   return -1;
 }
 
-int hv_layout_lanes(const Block& b, int nvec, int dtype) {
-  return choose_layout(nvec, b.sec->hv_mode == FTLM_HV_ONTHEFLY, tuned_gl(b, nvec, dtype)).GL;
+int hv_layout_lanes(const Block& b, int nvec, int dtype, bool pad, bool epi) {
+  return choose_layout(nvec, b.sec->hv_mode == FTLM_HV_ONTHEFLY, tuned_gl(b, nvec, dtype, pad, epi)).GL;
 }
 
 int hv_partial_groups(const Block& b, int nvec, int gl) {
@@ -108,17 +134,29 @@ int hv_partial_groups(const Block& b, int nvec, int gl) {
 
 void apply_hv(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t st,
               const LanczosEpilogue* lz) {
-  apply_hv_gl(b, X, Y, nvec, ld, dtype, st, lz, tuned_gl(b, nvec, dtype));
+  apply_hv_gl(b, X, Y, nvec, ld, dtype, st, lz, tuned_gl(b, nvec, dtype, false, lz != nullptr));
 }
 
-std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dtype, hipStream_t st, int reps) {
+std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dtype, hipStream_t st, int reps, bool pad,
+                                                bool epi) {
   std::vector<std::pair<int, double>> out;
   if (b.D == 0 || b.sec->n_reps == 0) return out;
   const size_t elem = dtype == FTLM_F64 ? 8 : dtype == FTLM_F32 ? 4 : 2;
+  const uint64_t rows = pad ? b.D_pad : b.D;
   DevBuf<uint8_t> X, Y;
-  X.alloc((size_t)b.D * nvec * elem);
-  Y.alloc((size_t)b.D * nvec * elem);
+  DevBuf<double> scal, partials;
+  X.alloc((size_t)rows * nvec * elem);
+  Y.alloc((size_t)rows * nvec * elem);
   FTLM_HIP(hipMemsetAsync(X.p, 0, X.bytes(), st));
+  FTLM_HIP(hipMemsetAsync(Y.p, 0, Y.bytes(), st));
+  if (epi) {
+    // the Lanczos epilogue with s = b = 0 (the work of a step; the values do not matter)
+    scal.alloc(2 * (size_t)nvec);
+    hipLaunchKernelGGL(k_fill_f64, dim3((2 * nvec + 255) / 256), dim3(256), 0, st, scal.p, 2 * nvec, 0.0);
+    size_t most = 0;
+    for (int gl = 1; gl <= 64; gl <<= 1) most = std::max<size_t>(most, (size_t)hv_partial_groups(b, nvec, gl));
+    partials.alloc(most * nvec);
+  }
   hipEvent_t e0, e1;
   FTLM_HIP(hipEventCreate(&e0));
   FTLM_HIP(hipEventCreate(&e1));
@@ -126,9 +164,11 @@ std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dt
   double best_ms = 1e300;
   for (int gl = 1; gl <= 64; gl <<= 1) {
     if (gl * 8 < nvec || gl > pow2_at_least(nvec)) continue;  // VPL <= 8, no empty lanes beyond one pow2
-    apply_hv_gl(b, X.p, Y.p, nvec, nvec, dtype, st, nullptr, gl);  // warm
+    LanczosEpilogue lz{scal.p, partials.p, hv_partial_groups(b, nvec, gl)};
+    const LanczosEpilogue* lzp = epi ? &lz : nullptr;
+    apply_hv_gl(b, X.p, Y.p, nvec, nvec, dtype, st, lzp, gl, pad);  // warm
     FTLM_HIP(hipEventRecord(e0, st));
-    for (int r = 0; r < reps; ++r) apply_hv_gl(b, X.p, Y.p, nvec, nvec, dtype, st, nullptr, gl);
+    for (int r = 0; r < reps; ++r) apply_hv_gl(b, X.p, Y.p, nvec, nvec, dtype, st, lzp, gl, pad);
     FTLM_HIP(hipEventRecord(e1, st));
     FTLM_HIP(hipEventSynchronize(e1));
     float ms = 0;
@@ -144,9 +184,65 @@ std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dt
   (void)hipEventDestroy(e1);
   if (best) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[tune_key(b, nvec, dtype)] = best;
+    g_tune[tune_key(b, nvec, dtype, pad, epi)] = best;
   }
   return out;
+}
+
+HvExPlan plan_hv_ex(const Block& b, int nvec, int dtype, const ftlm_hv_opts* o) {
+  HvExPlan p{};
+  if (nvec <= 0) fail(FTLM_ERR_INVALID_ARG, "need 0 < nvec <= ld");
+  const int layout = o ? o->layout : FTLM_LAYOUT_BLOCK;
+  if (layout == FTLM_LAYOUT_AUTO)
+    p.pad = padded_vectors(b);
+  else if (layout == FTLM_LAYOUT_PADDED)
+    p.pad = true;
+  else if (layout == FTLM_LAYOUT_BLOCK)
+    p.pad = false;
+  else
+    fail(FTLM_ERR_INVALID_ARG, "layout must be FTLM_LAYOUT_AUTO, _BLOCK or _PADDED");
+  if (p.pad && b.D_pad >= (1ull << 48)) fail(FTLM_ERR_UNSUPPORTED, "padded rows above 2^48");
+  p.rows = p.pad ? b.D_pad : b.D;
+  p.epi = o && o->scale;
+  if (o && o->dots && !o->scale) fail(FTLM_ERR_INVALID_ARG, "dots need scale");
+  const int lanes = o ? o->lanes : 0;
+  if (lanes != 0 && (lanes < 0 || lanes > 64 || (lanes & (lanes - 1))))
+    fail(FTLM_ERR_INVALID_ARG, "lanes must be 0 or a power of two up to 64");
+  const bool otf = b.sec->hv_mode == FTLM_HV_ONTHEFLY;
+  const Layout L = choose_layout(nvec, otf, lanes ? lanes : tuned_gl(b, nvec, dtype, p.pad, p.epi));
+  p.gl = L.GL;
+  p.ng = (b.D && b.sec->n_reps) ? hv_partial_groups(b, nvec, p.gl) : 0;
+  if (b.D && b.sec->n_reps) {
+    LaunchCfg c{};
+    HvArgs<double> a{};
+    hv_setup(b, nvec, nvec, p.gl, p.pad, nullptr, c, a);
+    p.adjacent = c.contig && c.slds && !c.otf && b.dgp <= 6;
+  }
+  return p;
+}
+
+void apply_hv_ex(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, const ftlm_hv_opts* o,
+                 const HvExPlan& p, double* partials, hipStream_t st) {
+  if (ld < nvec) fail(FTLM_ERR_INVALID_ARG, "need 0 < nvec <= ld");
+  if (p.epi && p.ng > 0 && !partials) fail(FTLM_ERR_INVALID_ARG, "no scratch for the partial sums");
+  if (p.rows == 0 || b.sec->n_reps == 0) {
+    if (o && o->dots) hipLaunchKernelGGL(k_fill_f64, dim3((nvec + 255) / 256), dim3(256), 0, st, o->dots, nvec, 0.0);
+    FTLM_HIP(hipGetLastError());
+    return;
+  }
+  if (!X || !Y) fail(FTLM_ERR_INVALID_ARG, "null vector");
+  LanczosEpilogue lz{p.epi ? o->scale : nullptr, partials, p.ng, o ? o->shift : 0.0};
+  if (p.epi) {
+    apply_hv_gl(b, X, Y, nvec, ld, dtype, st, &lz, p.gl, p.pad);
+    if (o->dots) hipLaunchKernelGGL(k_col_sums, dim3(nvec), dim3(256), 0, st, partials, p.ng, nvec, o->dots);
+  } else if (lz.eshift != 0.0) {
+    // a shift without the epilogue: the same kernel with scale (1, 0) would
+    // need a scale array; the plain pass takes the shift directly
+    apply_hv_gl(b, X, Y, nvec, ld, dtype, st, nullptr, p.gl, p.pad, lz.eshift);
+  } else {
+    apply_hv_gl(b, X, Y, nvec, ld, dtype, st, nullptr, p.gl, p.pad);
+  }
+  FTLM_HIP(hipGetLastError());
 }
 
 template <typename T>
@@ -259,7 +355,7 @@ template void hv_setup<_Float16>(const Block&, int, int64_t, int, bool, const La
                                  HvArgs<_Float16>&);
 
 void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t st,
-                 const LanczosEpilogue* lz, int gl, bool pad) {
+                 const LanczosEpilogue* lz, int gl, bool pad, double shift) {
   const Sector& s = *b.sec;
   if (nvec <= 0 || ld < nvec) fail(FTLM_ERR_INVALID_ARG, "need 0 < nvec <= ld");
   if (b.D == 0 || s.n_reps == 0) return;
@@ -275,16 +371,19 @@ void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
     hv_setup(b, nvec, ld, gl, pad, lz, c, a64);
     a64.X = (const double*)X;
     a64.Y = (double*)Y;
+    if (!lz) a64.eshift = shift;
     p64 = &a64;
   } else if (dtype == FTLM_F32) {
     hv_setup(b, nvec, ld, gl, pad, lz, c, a32);
     a32.X = (const float*)X;
     a32.Y = (float*)Y;
+    if (!lz) a32.eshift = shift;
     p32 = &a32;
   } else if (dtype == FTLM_F16) {
     hv_setup(b, nvec, ld, gl, pad, lz, c, a16);
     a16.X = (const _Float16*)X;
     a16.Y = (_Float16*)Y;
+    if (!lz) a16.eshift = shift;
     p16 = &a16;
   } else {
     fail(FTLM_ERR_INVALID_ARG, "dtype must be FTLM_F64, FTLM_F32 or FTLM_F16");

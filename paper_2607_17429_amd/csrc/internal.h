@@ -121,11 +121,27 @@ void apply_hv(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int 
               const LanczosEpilogue* lz = nullptr);
 // Lane layout: lanes per output representative for (nvec, dtype) (autotuned
 // or default), the partial-sum groups of that layout, and H.V with it fixed.
-int hv_layout_lanes(const Block& b, int nvec, int dtype);
+// The autotuner keys its choice by the row layout (pad) and by whether the
+// Lanczos epilogue runs (epi).
+int hv_layout_lanes(const Block& b, int nvec, int dtype, bool pad, bool epi);
 int hv_partial_groups(const Block& b, int nvec, int gl);
 // pad: X and Y use the padded row layout (representative i at i * d_Gamma).
+// shift: the plain pass (lz == nullptr) applies H - shift.
 void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t stream,
-                 const LanczosEpilogue* lz, int gl, bool pad = false);
+                 const LanczosEpilogue* lz, int gl, bool pad = false, double shift = 0.0);
+
+// ftlm_apply_H_ex: the launch decided on the host (row layout, lane layout,
+// partial-sum groups of the epilogue, whether the adjacent-column kernel runs)
+// and the enqueue with caller-provided scratch for the partials (p.ng * nvec
+// doubles when p.epi).
+struct HvExPlan {
+  bool pad = false, epi = false, adjacent = false;
+  int gl = 0, ng = 0;
+  uint64_t rows = 0;
+};
+HvExPlan plan_hv_ex(const Block& b, int nvec, int dtype, const ftlm_hv_opts* o);
+void apply_hv_ex(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, const ftlm_hv_opts* o,
+                 const HvExPlan& p, double* partials, hipStream_t st);
 
 // Whether vectors of the block take the padded row layout (d_Gamma rows per
 // representative, zeros beyond n_Gamma): the block's lanczos_layout, or for
@@ -133,7 +149,8 @@ void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
 bool padded_vectors(const Block& b);
 // Times every lane layout for (nvec, dtype) on this block, caches the fastest
 // process-wide and returns (lanes per representative, ms per launch) pairs.
-std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dtype, hipStream_t st, int reps);
+std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dtype, hipStream_t st, int reps, bool pad,
+                                                bool epi);
 int irrep_dim_bucket(int d);
 
 // One batched Lanczos run of R chains on a block: device state, an enqueue of

@@ -187,7 +187,7 @@ void kpm_typed(const Block& b, int R, int M, uint64_t seed, int dist, double cen
   const int TB = R * (256 / R);
   const unsigned nb = groups_for(D, TB / R);
   const int dtype = sizeof(T) == 8 ? FTLM_F64 : FTLM_F32;
-  const int gl = hv_layout_lanes(b, R, dtype);
+  const int gl = hv_layout_lanes(b, R, dtype, pad, true);
   const int ng_hv = hv_partial_groups(b, R, gl);
   DevBuf<T> q0, q1;
   q0.alloc(D * R);

@@ -336,7 +336,7 @@ LanczosRun::LanczosRun(const Block& b, int R_, int steps_, uint64_t seed_, int s
   TB = R * (256 / R);
   nb_vec = (int)blocks_for(std::max<uint64_t>(rows, 1), TB / R);
   // one lane layout for the whole run (the partial-sum buffer is sized for it)
-  gl = hv_layout_lanes(b, R, storage);
+  gl = hv_layout_lanes(b, R, storage, pad, true);
   ng_hv = D ? hv_partial_groups(b, R, gl) : 1;
 }
 

@@ -70,3 +70,23 @@ def rel_err_cols(Y, Yref):
     num = np.max(np.abs(Y - Yref), axis=0)
     den = np.maximum(np.max(np.abs(Yref), axis=0), 1e-300)
     return np.max(num / den)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_real_forms(name):
+    """The oracle's real forms (with their trace weights) of the cluster's group."""
+    from oracle import realform
+    cl, G, irs = oracle_group(name)
+    return realform.real_forms(G, irs)
+
+
+def oracle_weight(name, rho):
+    """Trace weight of the real form whose character equals that of the
+    matrices rho (|G| x d x d, the group's element order): the oracle's rule
+    (dim, dim / 2 for a complex pair, dim / 4 for a quaternionic irrep),
+    matched by character, never read from the library."""
+    ch = np.trace(np.asarray(rho), axis1=1, axis2=2)
+    hits = [f.weight for f in oracle_real_forms(name)
+            if f.irrep.dim == rho.shape[1] and np.allclose(np.trace(f.irrep.rho, axis1=1, axis2=2).real, ch, atol=1e-8)]
+    assert len(hits) == 1, "no unique real form with this character"
+    return int(hits[0])

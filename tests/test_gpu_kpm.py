@@ -15,7 +15,7 @@
 import numpy as np
 import pytest
 
-from gpu_helpers import lib_group, lib_sector, log, oracle_block, oracle_group, oracle_sector
+from gpu_helpers import lib_group, lib_sector, log, oracle_block, oracle_group, oracle_sector, oracle_weight
 from oracle import basis, ftlm as oftlm, group, hv, irreps, kpm as okpm, realform, sector
 from synth import clusters
 
@@ -145,9 +145,9 @@ def test_kpm_thermodynamics_of_the_icosahedron():
             if B.D == 0:
                 continue
             mom = B.kpm(R, M, 0x5EED0009, c, w)
-            blocks.append(dict(two_M=two_M, d_gamma=int(info["weights"][k]), D=B.D, moments=mom, center=c,
-                               half_width=w))
-            oblocks.append(okpm.KpmBlock(two_M, int(info["weights"][k]), B.D, mom, c, w))
+            wt = oracle_weight(name, LG.rho(k))
+            blocks.append(dict(two_M=two_M, d_gamma=wt, D=B.D, moments=mom, center=c, half_width=w))
+            oblocks.append(okpm.KpmBlock(two_M, wt, B.D, mom, c, w))
     # above T ~ 0.8 the Jackson broadening (pi w / M ~ 0.09) is negligible
     T = np.geomspace(0.8, 10, 30)
     E, C, chi, lz = P.kpm_observables(blocks, T)

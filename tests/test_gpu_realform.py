@@ -14,7 +14,7 @@ and of quaternionic irreps (dicyclic groups Dic_2 = Q8, Dic_3).
 import numpy as np
 import pytest
 
-from gpu_helpers import lib_group, log, rel_err_cols
+from gpu_helpers import lib_group, log, oracle_weight, rel_err_cols
 from oracle import basis, ftlm as oftlm, group, hv, irreps, realform, sector
 from synth import clusters
 
@@ -115,7 +115,7 @@ def test_campaign_with_realified_pairs_matches_oracle_ftlm(name, two_s):
                 th, w = oftlm.ritz(*oftlm.lanczos(lambda x: Hb @ x, v0, steps))
                 ths.append(th)
                 ws.append(w)
-            blocks.append(oftlm.BlockRitz(two_M, int(info["weights"][k]), B.D, ths, ws))
+            blocks.append(oftlm.BlockRitz(two_M, oracle_weight(name, ir.rho), B.D, ths, ws))
     E, C, chi, lz = oftlm.observables(blocks, T, with_logZ=True)
     for out in (res, fused):
         for got, want in ((out["E"], E), (out["C"], C), (out["chi"], chi), (out["logZ"], lz)):
