@@ -177,13 +177,21 @@ _lib = None
 
 
 def lib():
+    """The library: ``libftlm.so`` of this package, which must export every
+    call, or the library named by FTLM_LIBRARY (the sanitizer build of the
+    host-only part exports the host calls only; the others stay unbound)."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
-        L = C.CDLL(LIB_PATH)
+        path = os.environ.get("FTLM_LIBRARY") or LIB_PATH
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+        L = C.CDLL(path)
         for name, (res, args) in SIGNATURES.items():
-            fn = getattr(L, name)
+            fn = getattr(L, name, None)
+            if fn is None:
+                if path != LIB_PATH:
+                    continue
+                raise ImportError(f"{path} does not export {name}")
             fn.restype = res
             fn.argtypes = args
         _lib = L

@@ -74,5 +74,62 @@ def build(jobs: int | None = None, verbose: bool = True, incremental: bool = Fal
     return OUT
 
 
+# host-only sources: groups and irreps, Ritz data and thermal sums, their C entry points
+HOST_ONLY = ("group.cpp", "thermo.cpp", "capi_host.cpp")
+
+
+SANITIZERS = {"address": ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"],
+              "thread": ["-fsanitize=thread"]}
+
+
+def build_host_sanitized(out_dir: str | None = None, verbose: bool = False, kind: str = "address") -> str:
+    """The host-only part of the library (HOST_ONLY) built by g++ with the
+    address and undefined-behaviour sanitizers (kind "address") or the
+    thread sanitizer (kind "thread"), HIP headers for declarations only (no
+    device code), as ``libftlm_host_<kind>.so`` in out_dir (default
+    _build/sanitize).  Load it with the sanitizer runtime preloaded (see
+    sanitizer_env) and FTLM_LIBRARY pointing at it."""
+    out_dir = out_dir or os.path.join(BUILD, "sanitize", kind)
+    os.makedirs(out_dir, exist_ok=True)
+    san = SANITIZERS[kind]
+    flags = ["-std=c++17", "-O1", "-g", "-fPIC", "-pthread", "-fno-omit-frame-pointer"] + san + [
+             "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+    objs = []
+    for f in HOST_ONLY:
+        obj = os.path.join(out_dir, f + ".o")
+        cmd = ["g++"] + flags + ["-c", os.path.join(CSRC, f), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        objs.append(obj)
+    out = os.path.join(out_dir, f"libftlm_host_{kind}.so")
+    cmd = ["g++", "-shared", "-pthread", san[0], "-Wl,-z,defs", "-o", out] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print(f"built {out}", file=sys.stderr)
+    return out
+
+
+def sanitizer_env(lib_path: str, kind: str = "address") -> dict:
+    """Environment for a Python process that loads the sanitized host library:
+    the sanitizer runtime preloaded (Python itself is not instrumented), leak
+    checking off (the interpreter keeps its allocations), every finding fatal."""
+    def lib_of(name):
+        return subprocess.run(["g++", f"-print-file-name={name}"], capture_output=True, text=True).stdout.strip()
+
+    env = dict(os.environ)
+    # libstdc++ right behind the runtime, so that ASan finds the C++ runtime's
+    # functions it intercepts (exceptions) when it starts
+    runtime = "libasan.so" if kind == "address" else "libtsan.so"
+    env["LD_PRELOAD"] = lib_of(runtime) + ":" + lib_of("libstdc++.so")
+    env["FTLM_LIBRARY"] = lib_path
+    env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=0:halt_on_error=1:alloc_dealloc_mismatch=0"
+    env["UBSAN_OPTIONS"] = "halt_on_error=1:print_stacktrace=1"
+    env["TSAN_OPTIONS"] = "halt_on_error=1:report_signal_unsafe=0"
+    return env
+
+
 if __name__ == "__main__":
     build(incremental="--incremental" in sys.argv)
