@@ -4,11 +4,18 @@
  * A job is one block run (Section 3 of the paper: R chains, N_L steps, on one
  * (M, Gamma, row) block): cluster, generators, 2M, irrep, row, R, steps, seed,
  * storage and start-vector distribution.  Jobs wait in a FIFO queue and are
- * admitted while fewer than max_active are running and their estimated
+ * admitted while a slot is free (max_active slots) and their estimated
  * device footprint (vectors of the run, block tables, and the sector tables
  * unless already resident) fits in hbm_budget_bytes; a later job that fits may
  * overtake one that does not, until that one has been overtaken 64 times and
- * then holds back the queue behind it.  A job whose estimate alone exceeds
+ * then holds back the queue behind it (nothing behind it is admitted until it
+ * is).  Small jobs (sectors of a few hundred representatives, R <= 32, FP64
+ * or FP32 storage) admitted in the same pass over the queue run together as
+ * one batch of the fused small-block kernel (ftlm_run_fused: one launch per
+ * kernel shape, one workgroup per job, up to 64 jobs), which takes one slot;
+ * a small job admitted alone runs the per-step kernels, which are faster for
+ * one job.  Sector tables are built with the entry table (FTLM_HV_ENTRIES),
+ * whose size the admission estimate counts.  A job whose estimate alone exceeds
  * hbm_budget_bytes ends with FTLM_ERR_OUT_OF_MEMORY.  Sector tables are cached and shared by all
  * jobs with the same (cluster, generators, 2M); unused ones are evicted when
  * memory is needed.  Groups and sector tables are built by a builder thread
@@ -18,9 +25,10 @@
  * work of different jobs overlaps on the device; its Lanczos steps are
  * enqueued in chunks of about 10 ms of estimated device time, so a long job
  * holds a hardware queue shared with other streams for at most one chunk
- * ahead of their work.  A job may ask to run instead as one launch of the
- * fused small-block kernel (ftlm_run_fused) on its stream.  A job's result does not depend on the other jobs
- * (no shared reductions, deterministic kernels).  The two server threads own
+ * ahead of their work.  A job may ask for the fused small-block kernel
+ * (ftlm_run_fused); it then joins the batch of its pass.  A job's result does
+ * not depend on the other jobs (no shared reductions, deterministic kernels,
+ * and a job's result in a fused batch does not depend on the batch).  The two server threads own
  * every HIP call of the server; the calls below are thread-safe.
  */
 #ifndef FTLM_SERVER_H
@@ -46,11 +54,11 @@ typedef struct ftlm_job_desc {
   uint64_t seed;
   int32_t storage;       /* FTLM_F64 or FTLM_F32 */
   int32_t dist;          /* FTLM_RADEMACHER or FTLM_GAUSSIAN */
-  int32_t engine;        /* enum ftlm_engine: AUTO and STEPS run the per-step kernels (a single
-                            job gains nothing from the fused kernel, whose gain is many jobs per
-                            launch); FUSED runs the whole recurrence as one launch of the fused
-                            small-block kernel (INVALID_ARG where it does not apply, see
-                            ftlm_run_fused) */
+  int32_t engine;        /* enum ftlm_engine: AUTO batches small jobs admitted together into the
+                            fused small-block kernel and runs every other job with the per-step
+                            kernels; STEPS always runs the per-step kernels; FUSED always runs
+                            the fused kernel, batched with the small jobs of its pass
+                            (INVALID_ARG where it does not apply, see ftlm_run_fused) */
   int32_t reserved;
 } ftlm_job_desc;
 

@@ -202,6 +202,8 @@ uint64_t wg_rounds(uint64_t n_reps, int R);
 // automatic engine choice: blocks whose sector needs at most this many
 // representative rounds per lane group and step go to the fused kernel
 constexpr uint64_t kWgAutoMaxRounds = 8;
+// chains one fused job can hold (one column per lane group slot)
+constexpr int kWgMaxChains = 32;
 struct WgTask {
   const Block* block;            // must outlive the batch
   int R, steps, storage, dist, first_chain;
@@ -233,6 +235,10 @@ struct WgBatch {
   // of contiguous host arrays R x steps, R x steps, R) into host memory
   // (pinned for an asynchronous copy); the caller synchronizes st.
   void enqueue_download(void* host, size_t bytes);
+  // Any number of jobs: enqueue the copy of the whole output region
+  // (out_bytes) into host memory; job i's alpha, beta and nsteps then sit at
+  // byte offsets res[i][0..2] of it once st has passed the copy.
+  void enqueue_download_all(void* host, size_t bytes);
   template <typename Groups, typename Offsets, typename Shm>
   void launch_groups(const Groups& groups, const Offsets& goff, const Shm& shm);
   ~WgBatch();

@@ -19,7 +19,7 @@
 namespace ftlm {
 namespace hvk {
 
-constexpr int kWgMaxR = 32;
+constexpr int kWgMaxR = kWgMaxChains;
 // threads per job: 512 (two waves per SIMD, so twice the representatives in
 // flight as with 256) for irrep dimension buckets up to 6, whose registers fit
 // the 256 per lane this allows; 256 for the 8 and 12 buckets

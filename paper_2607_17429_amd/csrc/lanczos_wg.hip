@@ -214,6 +214,13 @@ void WgBatch::enqueue_download(void* host, size_t bytes) {
   launched = false;
 }
 
+void WgBatch::enqueue_download_all(void* host, size_t bytes) {
+  if (!launched) fail(FTLM_ERR_INVALID_ARG, "fused batch: nothing to download");
+  if (bytes < out_bytes) fail(FTLM_ERR_INVALID_ARG, "fused batch: host buffer too small");
+  FTLM_HIP(hipMemcpyAsync(host, arena.p + out_off, out_bytes, hipMemcpyDeviceToHost, st));
+  launched = false;
+}
+
 void WgBatch::finish() {
   if (!launched) return;
   launched = false;

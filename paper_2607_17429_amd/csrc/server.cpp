@@ -3,16 +3,22 @@
 // Two threads own all HIP work of a server.  The builder thread builds groups
 // (closure and irreps, host) and sector tables (GPU, on its own stream) one at
 // a time.  The worker thread loops: (1) take finished builds into the caches,
-// (2) retire running jobs whose completion event has fired, (3) walk the queue
-// in FIFO order: a job whose group or sector is missing asks the builder for
-// it (sector memory is reserved against the budget first) and waits without
-// holding anyone up; a job whose tables are resident is admitted when fewer
-// than max_active run and its block and Lanczos footprint fits, a later job
-// may overtake one that does not fit; (4) sleep briefly or until woken.
-// Admission builds the block on the worker's stream and enqueues the start
-// vectors on a pooled non-blocking stream; the worker then feeds the job's
-// Lanczos steps in chunks (two in flight, each followed by an event) and
-// finally the copy of its coefficients and a completion event.
+// (2) retire running jobs and fused batches whose completion events have
+// fired, (3) walk the queue in FIFO order: a job whose group or sector is
+// missing asks the builder for it (sector memory is reserved against the
+// budget first) and waits without holding anyone up; a job whose tables are
+// resident is admitted when a slot is free and its block and Lanczos
+// footprint fits; a later job may overtake one that does not fit, until that
+// one has been overtaken kMaxOvertake times and stops the walk in front of
+// it; (4) launch the small jobs admitted in this walk together as one fused
+// batch, or alone with the per-step kernels when only one came; (5) sleep
+// briefly or until woken.
+// Admission builds the block on the worker's stream.  A per-step job gets a
+// pooled non-blocking stream; the worker feeds its Lanczos steps in chunks
+// (two in flight, each followed by an event) and finally the copy of its
+// coefficients and a completion event.  A fused batch is one launch per
+// kernel shape of the fused small-block kernel on a pooled stream, one copy
+// of all its jobs' coefficients and one event; it takes one slot.
 #include <algorithm>
 #include <atomic>
 #include <chrono>
@@ -28,6 +34,7 @@
 #include <tuple>
 #include <unordered_map>
 
+#include "capi_guard.h"
 #include "ftlm_server.h"
 #include "internal.h"
 
@@ -77,6 +84,7 @@ struct Job {
 };
 
 constexpr int kMaxOvertake = 64;
+constexpr size_t kMaxBatchJobs = 64;  // jobs of one fused batch
 constexpr double kChunkSeconds = 0.01;
 constexpr double kHbmBytesPerSecond = 4.0e12;  // sustained gather rate assumed for chunk sizing
 
@@ -115,6 +123,17 @@ long double sector_dim(int N, int two_s, int two_M) {
 
 }  // namespace
 
+// Small jobs admitted together and run as one launch of the fused
+// small-block kernel per kernel shape.
+struct FusedBatch {
+  std::vector<std::shared_ptr<Job>> jobs;
+  std::unique_ptr<WgBatch> wg;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev = nullptr;
+  void* h_buf = nullptr;  // pinned: the batch's output region
+  size_t h_bytes = 0;
+};
+
 struct Server {
   int64_t budget = 0;
   int max_active = 1;
@@ -150,7 +169,9 @@ struct Server {
   std::map<std::string, int64_t> sector_building;  // key -> reserved bytes
   uint64_t tick = 0;
   hipStream_t build = nullptr;
-  std::vector<std::shared_ptr<Job>> running;
+  std::vector<std::shared_ptr<Job>> running;    // per-step jobs, one slot each
+  std::vector<std::unique_ptr<FusedBatch>> batches;  // one slot each
+  std::vector<std::shared_ptr<Job>> forming;    // small jobs admitted in this walk
   // Streams, events and pinned result buffers are recycled: creating and
   // freeing them per job would add driver calls that can serialize the device.
   std::vector<std::pair<hipStream_t, hipEvent_t>> free_streams;
@@ -164,7 +185,15 @@ struct Server {
   void take_builds();
   // 1: admitted or ended, 0: waits for memory or a slot, -1: waits for a build
   int try_admit(const std::shared_ptr<Job>& j);
-  void launch(const std::shared_ptr<Job>& j, SecEntry& se);
+  void launch(const std::shared_ptr<Job>& j, SecEntry& se, bool small);
+  void start_steps(const std::shared_ptr<Job>& j);
+  void flush_forming();
+  void finish_batch(FusedBatch& b);
+  void take_stream(hipStream_t& s, hipEvent_t& e);
+  void* take_pinned(size_t& bytes);
+  int slots_in_use() const {
+    return (int)running.size() + (int)batches.size() + (forming.empty() ? 0 : 1);
+  }
   void retire(const std::shared_ptr<Job>& j, int status);
   int64_t estimate_sector(const Job& j, const Group& G) const;
   int64_t estimate_job(const Job& j, const Group& G, const Sector& S) const;
@@ -192,6 +221,12 @@ int64_t Server::estimate_job(const Job& j, const Group& G, const Sector& S) cons
 }
 
 void Server::evict_unused(int64_t need, const std::string& keep) {
+  // evict only when that makes room: a job that cannot fit even with every
+  // unused sector gone keeps the caches (other queued jobs may need them)
+  int64_t freeable = 0;
+  for (auto& kv : sectors)
+    if (kv.second.users == 0 && kv.first != keep) freeable += kv.second.bytes;
+  if (used - freeable + need > budget) return;
   while (used + need > budget) {
     auto victim = sectors.end();
     for (auto it = sectors.begin(); it != sectors.end(); ++it)
@@ -233,8 +268,11 @@ void Server::builder_loop() {
       } else {
         AllocStreamScope scope(bstream);
         ftlm_cluster cl{j.N, j.two_s, (int32_t)(j.bonds.size() / 2), j.bonds.data(), j.J.data()};
+        // entry tables always: their size is in the sector estimate the
+        // budget admitted, and the decision must not depend on what other
+        // jobs happen to hold on the device (the free memory AUTO looks at)
         ftlm_opts o{};
-        o.hv_mode = FTLM_HV_AUTO;
+        o.hv_mode = FTLM_HV_ENTRIES;
         res.S = build_sector(&cl, r.G, j.two_M, &o);  // synchronizes bstream before returning
       }
     } catch (const Error& e) {
@@ -337,7 +375,14 @@ int Server::try_admit(const std::shared_ptr<Job>& j) {
     return -1;
   }
   SecEntry& se = sit->second;
-  if ((int)running.size() >= max_active) return 0;
+  // a small job under the automatic engine joins the batch of this walk
+  // (no slot of its own once the batch has one)
+  const bool small = j->engine == FTLM_ENGINE_AUTO && j->R <= kWgMaxChains &&
+                     (j->storage == FTLM_F64 || j->storage == FTLM_F32) &&
+                     wg_rounds(se.sec->n_reps, j->R) <= kWgAutoMaxRounds;
+  const bool room = forming.size() < kMaxBatchJobs;
+  const bool joins = small && room && !forming.empty();
+  if (!joins && slots_in_use() >= max_active) return 0;
   const int64_t est = estimate_job(*j, G, *se.sec);
   if (est > budget) {
     j->msg = "estimated job footprint of " + std::to_string(est) + " bytes exceeds the server budget";
@@ -346,11 +391,34 @@ int Server::try_admit(const std::shared_ptr<Job>& j) {
   }
   if (used + est > budget) evict_unused(est, j->sector_key);
   if (used + est > budget) return 0;
-  launch(j, se);
+  launch(j, se, small && room);
   return 1;
 }
 
-void Server::launch(const std::shared_ptr<Job>& j, SecEntry& se) {
+void Server::take_stream(hipStream_t& st, hipEvent_t& ev) {
+  if (!free_streams.empty()) {
+    std::tie(st, ev) = free_streams.back();
+    free_streams.pop_back();
+  } else {
+    FTLM_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    FTLM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  }
+}
+
+void* Server::take_pinned(size_t& bytes) {
+  auto pit = free_pinned.lower_bound(bytes);
+  if (pit != free_pinned.end() && pit->first <= 2 * bytes) {
+    bytes = pit->first;
+    void* p = pit->second;
+    free_pinned.erase(pit);
+    return p;
+  }
+  void* p = nullptr;
+  FTLM_HIP(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+  return p;
+}
+
+void Server::launch(const std::shared_ptr<Job>& j, SecEntry& se, bool small) {
   try {
     AllocStreamScope scope(build);
     se.users++;
@@ -364,76 +432,22 @@ void Server::launch(const std::shared_ptr<Job>& j, SecEntry& se) {
     j->footprint = blk + lz;
     used += j->footprint;
     FTLM_HIP(hipStreamSynchronize(build));
-    if (!free_streams.empty()) {
-      std::tie(j->stream, j->ev) = free_streams.back();
-      free_streams.pop_back();
-    } else {
-      FTLM_HIP(hipStreamCreateWithFlags(&j->stream, hipStreamNonBlocking));
-      FTLM_HIP(hipEventCreateWithFlags(&j->ev, hipEventDisableTiming));
-    }
-    const size_t nab = (size_t)j->R * j->steps;
-    j->h_bytes = 2 * nab * sizeof(double) + j->R * sizeof(int32_t);
-    auto pit = free_pinned.lower_bound(j->h_bytes);
-    if (pit != free_pinned.end() && pit->first <= 2 * j->h_bytes) {
-      j->h_bytes = pit->first;
-      j->h_buf = pit->second;
-      free_pinned.erase(pit);
-    } else {
-      FTLM_HIP(hipHostMalloc(&j->h_buf, j->h_bytes, hipHostMallocDefault));
-    }
-    j->h_alpha = static_cast<double*>(j->h_buf);
-    j->h_beta = j->h_alpha + nab;
-    j->h_n = reinterpret_cast<int32_t*>(j->h_beta + nab);
     const Block& B = *j->block;
     const bool fits = B.D > 0 && wg_supported(B, j->R, j->storage);
     if (j->engine == FTLM_ENGINE_FUSED && !fits)
       fail(FTLM_ERR_INVALID_ARG, "the job does not fit the fused small-block kernel");
-    // AUTO keeps the per-step kernels: one job alone gains nothing from the
-    // fused kernel (its gain is many jobs per launch), measured on the serving
-    // mix: small jobs ran 0.7 ms per-step against 1.4 ms fused
-    if (fits && j->engine == FTLM_ENGINE_FUSED) {
-      // the whole recurrence in one launch; coefficients straight into the pinned buffer
-      AllocStreamScope js(j->stream);
-      std::vector<WgTask> t{WgTask{&B, j->R, j->steps, j->storage, j->dist, 0, j->seed, j->h_alpha, j->h_beta,
-                                   j->h_n}};
-      j->fused = std::make_unique<WgBatch>(std::move(t), j->stream);
-      j->fused->enqueue_download(j->h_buf, j->h_bytes);
-      FTLM_HIP(hipEventRecord(j->ev, j->stream));
-      j->engine = FTLM_ENGINE_FUSED;
-      j->enqueued_all = true;
-      j->running = true;
-      j->t_start = now_s(t0);
-      running.push_back(j);
-      std::lock_guard<std::mutex> lk(mu);
-      n_running++;
-      return;
-    }
-    j->engine = FTLM_ENGINE_STEPS;
-    {
-      AllocStreamScope js(j->stream);
-      j->run = std::make_unique<LanczosRun>(*j->block, j->R, j->steps, j->seed, j->storage, j->dist);
-      j->run->allocate();
-      j->run->enqueue_begin(j->stream);
-    }
-    // Steps go to the stream in chunks of about kChunkSeconds of estimated
-    // HBM time, so a long run never holds a shared hardware queue for more
-    // than one chunk ahead of other jobs' work.
-    {
-      const Sector& S = *j->block->sec;
-      const double elem = j->storage == FTLM_F64 ? 8.0 : j->storage == FTLM_F32 ? 4.0 : 2.0;
-      const double rows = S.n_reps ? (double)j->D / (double)S.n_reps : 0.0;
-      const double step_bytes = (double)S.n_entries * (rows * j->R * elem + 8.0) + 6.0 * (double)j->D * j->R * elem;
-      const double step_s = step_bytes / kHbmBytesPerSecond;
-      j->chunk = (int)std::max(1.0, std::min((double)std::max(j->run->target, 1), kChunkSeconds / std::max(step_s, 1e-9)));
-    }
-    j->next_step = 0;
-    j->enqueued_all = false;
-    feed(*j);
     j->running = true;
     j->t_start = now_s(t0);
-    running.push_back(j);
-    std::lock_guard<std::mutex> lk(mu);
-    n_running++;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      n_running++;
+    }
+    if (fits && (j->engine == FTLM_ENGINE_FUSED || small)) {
+      // launched with the other small jobs of this walk (flush_forming)
+      forming.push_back(j);
+      return;
+    }
+    start_steps(j);
   } catch (const Error& e) {
     j->msg = e.what();
     retire(j, e.code);
@@ -441,6 +455,119 @@ void Server::launch(const std::shared_ptr<Job>& j, SecEntry& se) {
     j->msg = e.what();
     retire(j, FTLM_ERR_INVALID_ARG);
   }
+}
+
+// The per-step kernels on a pooled stream of the job, steps fed in chunks.
+void Server::start_steps(const std::shared_ptr<Job>& j) {
+  take_stream(j->stream, j->ev);
+  const size_t nab = (size_t)j->R * j->steps;
+  j->h_bytes = 2 * nab * sizeof(double) + j->R * sizeof(int32_t);
+  j->h_buf = take_pinned(j->h_bytes);
+  j->h_alpha = static_cast<double*>(j->h_buf);
+  j->h_beta = j->h_alpha + nab;
+  j->h_n = reinterpret_cast<int32_t*>(j->h_beta + nab);
+  j->engine = FTLM_ENGINE_STEPS;
+  {
+    AllocStreamScope js(j->stream);
+    j->run = std::make_unique<LanczosRun>(*j->block, j->R, j->steps, j->seed, j->storage, j->dist);
+    j->run->allocate();
+    j->run->enqueue_begin(j->stream);
+  }
+  // Steps go to the stream in chunks of about kChunkSeconds of estimated
+  // HBM time, so a long run never holds a shared hardware queue for more
+  // than one chunk ahead of other jobs' work.
+  {
+    const Sector& S = *j->block->sec;
+    const double elem = j->storage == FTLM_F64 ? 8.0 : j->storage == FTLM_F32 ? 4.0 : 2.0;
+    const double rows = S.n_reps ? (double)j->D / (double)S.n_reps : 0.0;
+    const double step_bytes = (double)S.n_entries * (rows * j->R * elem + 8.0) + 6.0 * (double)j->D * j->R * elem;
+    const double step_s = step_bytes / kHbmBytesPerSecond;
+    j->chunk = (int)std::max(1.0, std::min((double)std::max(j->run->target, 1), kChunkSeconds / std::max(step_s, 1e-9)));
+  }
+  j->next_step = 0;
+  j->enqueued_all = false;
+  feed(*j);
+  running.push_back(j);
+}
+
+// The small jobs admitted in one walk: two or more run as one fused batch
+// (one launch per kernel shape), a lone job runs the per-step kernels, which
+// are faster for one job (measured on the serving mix: 0.7 ms against
+// 1.4 ms fused) unless it asked for the fused engine.
+void Server::flush_forming() {
+  if (forming.empty()) return;
+  std::vector<std::shared_ptr<Job>> js;
+  js.swap(forming);
+  if (js.size() == 1 && js[0]->engine != FTLM_ENGINE_FUSED) {
+    try {
+      start_steps(js[0]);
+    } catch (const Error& e) {
+      js[0]->msg = e.what();
+      retire(js[0], e.code);
+    }
+    return;
+  }
+  auto b = std::make_unique<FusedBatch>();
+  try {
+    take_stream(b->stream, b->ev);
+    std::vector<WgTask> tasks;
+    for (auto& j : js) {
+      j->engine = FTLM_ENGINE_FUSED;
+      j->alpha.assign((size_t)j->R * j->steps, 0.0);
+      j->beta.assign((size_t)j->R * j->steps, 0.0);
+      j->nsteps.assign(j->R, 0);
+      tasks.push_back(WgTask{j->block.get(), j->R, j->steps, j->storage, j->dist, 0, j->seed, j->alpha.data(),
+                             j->beta.data(), j->nsteps.data()});
+    }
+    {
+      AllocStreamScope bs(b->stream);
+      b->wg = std::make_unique<WgBatch>(std::move(tasks), b->stream);
+    }
+    b->h_bytes = std::max<size_t>(b->wg->out_bytes, 8);
+    b->h_buf = take_pinned(b->h_bytes);
+    b->wg->enqueue_download_all(b->h_buf, b->h_bytes);
+    FTLM_HIP(hipEventRecord(b->ev, b->stream));
+    b->jobs = std::move(js);
+    batches.push_back(std::move(b));
+  } catch (const Error& e) {
+    for (auto& j : js) {
+      j->msg = e.what();
+      retire(j, e.code);
+    }
+    if (b->wg) b->wg.reset();
+    if (b->stream) {
+      (void)hipStreamSynchronize(b->stream);
+      free_streams.emplace_back(b->stream, b->ev);
+    }
+    if (b->h_buf) free_pinned.emplace(b->h_bytes, b->h_buf);
+  }
+}
+
+// A batch whose event has fired: every job's coefficients from the pinned
+// copy, the jobs retired, the stream, event and buffer back to the pools.
+void Server::finish_batch(FusedBatch& b) {
+  for (size_t i = 0; i < b.jobs.size(); ++i) {
+    auto& j = b.jobs[i];
+    const auto& off = b.wg->res[i];
+    const size_t rs = (size_t)j->R * j->steps;
+    const uint8_t* h = static_cast<const uint8_t*>(b.h_buf);
+    std::memcpy(j->alpha.data(), h + off[0], 8 * rs);
+    std::memcpy(j->beta.data(), h + off[1], 8 * rs);
+    std::memcpy(j->nsteps.data(), h + off[2], 4 * (size_t)j->R);
+    bool c;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      c = j->cancel;
+    }
+    if (c) j->msg = "cancelled";
+    retire(j, c ? FTLM_ERR_CANCELLED : FTLM_OK);
+  }
+  b.wg.reset();  // stream-ordered free of the arena; waits for the pinned staging buffer
+  free_streams.emplace_back(b.stream, b.ev);
+  free_pinned.emplace(b.h_bytes, b.h_buf);
+  b.stream = nullptr;
+  b.ev = nullptr;
+  b.h_buf = nullptr;
 }
 
 // Keeps up to two chunks of steps in flight; after the last step enqueues the
@@ -484,7 +611,7 @@ void Server::feed(Job& j) {
 
 void Server::retire(const std::shared_ptr<Job>& j, int status) {
   if (j->stream) (void)hipStreamSynchronize(j->stream);
-  if (status == FTLM_OK && j->h_alpha) {
+  if (status == FTLM_OK && j->h_alpha) {  // per-step jobs (fused-batch jobs hold theirs already)
     j->alpha.assign(j->h_alpha, j->h_alpha + (size_t)j->R * j->steps);
     j->beta.assign(j->h_beta, j->h_beta + (size_t)j->R * j->steps);
     j->nsteps.assign(j->h_n, j->h_n + j->R);
@@ -549,19 +676,30 @@ void Server::loop() {
         ++i;
       }
     }
+    for (size_t i = 0; i < batches.size();) {
+      if (hipEventQuery(batches[i]->ev) == hipSuccess) {
+        std::unique_ptr<FusedBatch> b = std::move(batches[i]);
+        batches.erase(batches.begin() + i);
+        finish_batch(*b);
+      } else {
+        ++i;
+      }
+    }
     // walk the queue
     std::vector<std::shared_ptr<Job>> pending;
     {
       std::lock_guard<std::mutex> lk(mu);
-      if (stop && queue.empty() && running.empty()) break;
+      if (stop && queue.empty() && running.empty() && batches.empty()) break;
       for (int64_t id : queue) pending.push_back(jobs[id]);
     }
-    bool head_blocked = false;
     std::vector<Job*> refused;
     for (auto& j : pending) {
       // A job that has been overtaken kMaxOvertake times holds back the
-      // queue behind it until it is admitted, so large jobs are not starved.
-      if (head_blocked) break;
+      // queue behind it until it is admitted: nothing behind it is tried, so
+      // the memory and slots that running jobs free reach it first and large
+      // jobs are not starved.
+      if (std::any_of(refused.begin(), refused.end(), [](const Job* q) { return q->overtaken >= kMaxOvertake; }))
+        break;
       bool cancelled;
       {
         std::lock_guard<std::mutex> lk(mu);
@@ -579,13 +717,13 @@ void Server::loop() {
         refused.push_back(j.get());
       } else if (r == 1) {
         if (j->running)
-          for (Job* q : refused)
-            if (++q->overtaken >= kMaxOvertake) head_blocked = true;
+          for (Job* q : refused) ++q->overtaken;
         dequeue(j->id);
       }
     }
+    flush_forming();
     std::unique_lock<std::mutex> lk(mu);
-    if (running.empty() && queue.empty()) {
+    if (running.empty() && batches.empty() && queue.empty()) {
       if (stop) break;
       cv_work.wait(lk, [&] { return stop || !queue.empty(); });
     } else {
@@ -628,26 +766,10 @@ struct ftlm_server {
 
 using namespace ftlm;
 
-namespace {
-template <typename F>
-int guarded_s(F&& f) {
-  try {
-    f();
-    return FTLM_OK;
-  } catch (const Error& e) {
-    set_last_error(e.what());
-    return e.code;
-  } catch (const std::exception& e) {
-    set_last_error(e.what());
-    return FTLM_ERR_INVALID_ARG;
-  }
-}
-}  // namespace
-
 extern "C" {
 
 int ftlm_server_create(int64_t hbm_budget_bytes, int32_t max_active, ftlm_server** out) {
-  return guarded_s([&] {
+  return guarded([&] {
     if (!out || hbm_budget_bytes <= 0 || max_active <= 0) fail(FTLM_ERR_INVALID_ARG, "bad server arguments");
     auto* h = new ftlm_server{std::make_unique<Server>()};
     Server& S = *h->s;
@@ -661,7 +783,7 @@ int ftlm_server_create(int64_t hbm_budget_bytes, int32_t max_active, ftlm_server
 }
 
 int ftlm_server_submit(ftlm_server* h, const ftlm_job_desc* d, int64_t* job_id) {
-  return guarded_s([&] {
+  return guarded([&] {
     if (!h || !d || !job_id) fail(FTLM_ERR_INVALID_ARG, "null argument");
     const ftlm_cluster& c = d->cluster;
     if (c.N <= 0 || c.N > 64 || c.nbonds < 0 || (c.nbonds && !c.bonds) || d->ngens < 0 || (d->ngens && !d->gens))
@@ -702,7 +824,7 @@ int ftlm_server_submit(ftlm_server* h, const ftlm_job_desc* d, int64_t* job_id) 
 }
 
 int ftlm_server_poll(ftlm_server* h, int64_t id, int32_t* done) {
-  return guarded_s([&] {
+  return guarded([&] {
     if (!h || !done) fail(FTLM_ERR_INVALID_ARG, "null argument");
     std::lock_guard<std::mutex> lk(h->s->mu);
     auto it = h->s->jobs.find(id);
@@ -713,7 +835,7 @@ int ftlm_server_poll(ftlm_server* h, int64_t id, int32_t* done) {
 
 int ftlm_server_wait(ftlm_server* h, int64_t id, ftlm_job_result* res, double* alpha, double* beta, int32_t* nsteps) {
   int status = FTLM_OK;
-  int rc = guarded_s([&] {
+  int rc = guarded([&] {
     if (!h) fail(FTLM_ERR_INVALID_ARG, "null server");
     Server& S = *h->s;
     std::unique_lock<std::mutex> lk(S.mu);
@@ -747,7 +869,7 @@ int ftlm_server_wait(ftlm_server* h, int64_t id, ftlm_job_result* res, double* a
 }
 
 int ftlm_server_cancel(ftlm_server* h, int64_t id) {
-  return guarded_s([&] {
+  return guarded([&] {
     if (!h) fail(FTLM_ERR_INVALID_ARG, "null server");
     std::lock_guard<std::mutex> lk(h->s->mu);
     auto it = h->s->jobs.find(id);
@@ -758,7 +880,7 @@ int ftlm_server_cancel(ftlm_server* h, int64_t id) {
 }
 
 int ftlm_server_stats(ftlm_server* h, int64_t* used_bytes, int32_t* running, int32_t* queued) {
-  return guarded_s([&] {
+  return guarded([&] {
     if (!h) fail(FTLM_ERR_INVALID_ARG, "null server");
     std::lock_guard<std::mutex> lk(h->s->mu);
     if (used_bytes) *used_bytes = h->s->used;

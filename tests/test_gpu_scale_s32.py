@@ -117,3 +117,50 @@ def test_hg_block_sampled_rows_s32(dodeca32):
         assert np.max(np.abs(got - yref)) <= 2e-7 * scale, (i, np.max(np.abs(got - yref)) / scale)
     del Y
 
+
+
+# Section 4.3: the ground-state energy of the s=3/2 dodecahedron, E0 = -62.4388
+# (FP32 vector storage, converged to better than 1e-4 between 60 and 200
+# Lanczos steps), the lowest level over the ten M = 0 irrep blocks of Table 2.
+E0_PAPER = -62.4388
+_lowest = {}
+
+
+def _table2():
+    """(d_Gamma, inversion character / d_Gamma) -> D from the paper's Table 2."""
+    from conftest import golden
+    out = {}
+    for name, d, D, par in golden("table2_dodeca_s32_blocks.txt"):
+        out.setdefault((int(d), int(par)), set()).add(int(D))
+    return out
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("gi", range(10))
+def test_m0_block_dimension_and_lowest_ritz_value_s32(dodeca32, gi):
+    """Every M = 0 block: its dimension from the GPU build against Table 2
+    (matched by irrep dimension and inversion parity), then one Rademacher
+    chain of 60 Lanczos steps in FP32 storage, whose lowest Ritz value is kept
+    for the ground-state pin below."""
+    cl, G, irs, S = dodeca32
+    ir = irs[gi]
+    inv = next(k for k, p in enumerate(G.perms) if np.array_equal(p, cl.gens[2]))
+    par = int(round(ir.chars[inv].real / ir.dim))
+    B = P.Block(S, gi, 0, user_rho=ir.rho)
+    log(f"[scale32] M=0 irrep {gi} (d={ir.dim}, parity {par:+d}): D = {B.D}")
+    assert B.D in _table2()[(ir.dim, par)]
+    a, b, n = B.ftlm(1, 60, 0x5EED0005 + gi, storage=P.F32, dist=P.RADEMACHER)
+    assert int(n[0]) == 60
+    th, w = P.tridiag_ritz(a[0], b[0, :59])
+    _lowest[gi] = float(th.min())
+    log(f"  lowest Ritz value {th.min():.6f}")
+    del B
+    gc.collect()
+
+
+def test_ground_state_energy_s32():
+    """min over the ten blocks of the lowest Ritz value = E0 of the paper."""
+    assert sorted(_lowest) == list(range(10)), "the per-block runs above did not all run"
+    e0 = min(_lowest.values())
+    log(f"[scale32] E0 = {e0:.6f} (irrep {min(_lowest, key=_lowest.get)}); paper {E0_PAPER}")
+    assert abs(e0 - E0_PAPER) <= 1e-4
