@@ -297,6 +297,21 @@ typedef struct ftlm_hv_opts {
 int ftlm_apply_H_ex(ftlm_block* b, const void* X, void* Y, int32_t nvec, int64_t ld, int32_t dtype,
                     ftlm_hv_opts* opts, void* stream);
 
+/* ftlm_apply_H_ex that allocates nothing, for callers that cannot allocate
+ * device memory: work captured into a HIP graph, tight serving loops,
+ * harnesses that forbid allocation.  Same arguments, results bit for bit
+ * equal to ftlm_apply_H_ex.  Its one scratch buffer (the per-workgroup FP64
+ * partial sums behind scale/dots) is a static device array of 4 MiB per GPU
+ * (8192 x 64 doubles), held until the process ends; INVALID_ARG when a call
+ * would need more (nvec x workgroups above that).  The first call on a
+ * device looks up the array's device address (hipGetSymbolAddress): make it
+ * outside stream capture.  Every call on one GPU shares that GPU's array:
+ * calls that overlap in time on one GPU (several streams or host threads)
+ * race on it and must be serialized by the caller; each call writes every
+ * partial it reads, so nothing needs clearing between calls. */
+int ftlm_apply_H_ex_noalloc(ftlm_block* b, const void* X, void* Y, int32_t nvec, int64_t ld, int32_t dtype,
+                            ftlm_hv_opts* opts, void* stream);
+
 /* Autotuner: times every lane layout of the H.V kernel (lanes per output
  * representative 1..64, vectors per lane) for nvec columns of dtype on this
  * block, on stream, first for the launch ftlm_run and ftlm_kpm make on this

@@ -149,6 +149,7 @@ SIGNATURES = {
     "ftlm_block_hv_stats": (C.c_int, [VP, C.POINTER(HvStats)]),
     "ftlm_apply_H": (C.c_int, [VP, VP, VP, C.c_int32, C.c_int64, C.c_int32, VP]),
     "ftlm_apply_H_ex": (C.c_int, [VP, VP, VP, C.c_int32, C.c_int64, C.c_int32, C.POINTER(HvOpts), VP]),
+    "ftlm_apply_H_ex_noalloc": (C.c_int, [VP, VP, VP, C.c_int32, C.c_int64, C.c_int32, C.POINTER(HvOpts), VP]),
     "ftlm_block_autotune": (C.c_int, [VP, C.c_int32, C.c_int32, VP, I32P, F64P, I32P, F64P, I32P]),
     "ftlm_run": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, F64P, F64P, I32P, VP]),
     "ftlm_run_ex": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, F64P, F64P, I32P, VP,

@@ -193,11 +193,14 @@ class Block:
         """Rows of the padded layout: n_reps * d_Gamma."""
         return self.n_reps * self.d_gamma
 
-    def apply_H_ex(self, X, Y=None, layout=0, lanes=0, scale=None, dots=None, shift=0.0, stream=None):
+    def apply_H_ex(self, X, Y=None, layout=0, lanes=0, scale=None, dots=None, shift=0.0, stream=None,
+                   noalloc=False):
         """ftlm_apply_H_ex on (rows, nvec) torch CUDA tensors: rows = D (LAYOUT_BLOCK) or
         n_reps * d_Gamma (LAYOUT_PADDED; AUTO = the layout ftlm_run takes).  scale:
         float64 CUDA tensor (nvec, 2) of (s, b) pairs, Y <- s (H - shift) X - b Y;
-        dots: float64 CUDA tensor (nvec,) receiving sum_rows X * Y.  Returns Y and the launch's (lanes_used, adjacent_columns)."""
+        dots: float64 CUDA tensor (nvec,) receiving sum_rows X * Y.  noalloc: the
+        entry point whose scratch is a static device array (ftlm_apply_H_ex_noalloc).
+        Returns Y and the launch's (lanes_used, adjacent_columns)."""
         import torch
         if X.dim() == 1:
             X = X[:, None]
@@ -218,8 +221,9 @@ class Block:
             assert dots.dtype == torch.float64 and dots.is_cuda and dots.numel() >= X.shape[1]
             o.dots = dots.data_ptr()
         o.shift = float(shift)
-        check(lib().ftlm_apply_H_ex(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), X.shape[1],
-                                    X.stride(0), dtype, C.byref(o), L.stream_handle(stream)))
+        fn = lib().ftlm_apply_H_ex_noalloc if noalloc else lib().ftlm_apply_H_ex
+        check(fn(self._h, C.c_void_p(X.data_ptr()), C.c_void_p(Y.data_ptr()), X.shape[1], X.stride(0), dtype,
+                 C.byref(o), L.stream_handle(stream)))
         return Y, dict(lanes_used=o.lanes_used, adjacent_columns=o.adjacent_columns)
 
     def kpm(self, R, n_moments, seed, center, half_width, storage=F64, dist=RADEMACHER, stream=None):
