@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libftlm.so")
 F64, F32, F16 = 0, 1, 2
 RADEMACHER, GAUSSIAN = 0, 1
 HV_AUTO, HV_ENTRIES, HV_ONTHEFLY = 0, 1, 2
-LAYOUT_AUTO, LAYOUT_BLOCK, LAYOUT_PADDED = 0, 1, 2
+LAYOUT_AUTO, LAYOUT_BLOCK, LAYOUT_PADDED, LAYOUT_PACKED = 0, 1, 2, 3
 ENTRIES_AUTO, ENTRIES_WIDE, ENTRIES_COMPACT = 0, 1, 2
 ENGINE_AUTO, ENGINE_STEPS, ENGINE_FUSED = 0, 1, 2
 
@@ -151,10 +151,20 @@ SIGNATURES = {
     "ftlm_apply_H_ex": (C.c_int, [VP, VP, VP, C.c_int32, C.c_int64, C.c_int32, C.POINTER(HvOpts), VP]),
     "ftlm_apply_H_ex_noalloc": (C.c_int, [VP, VP, VP, C.c_int32, C.c_int64, C.c_int32, C.POINTER(HvOpts), VP]),
     "ftlm_block_autotune": (C.c_int, [VP, C.c_int32, C.c_int32, VP, I32P, F64P, I32P, F64P, I32P]),
+    "ftlm_device_arch": (C.c_int, [C.c_char_p, C.c_int32]),
+    "ftlm_autotune_save": (C.c_int, [C.c_char_p, C.c_char_p, I32P]),
+    "ftlm_autotune_load": (C.c_int, [C.c_char_p, C.c_char_p, I32P]),
+    "ftlm_autotune_clear": (C.c_int, []),
     "ftlm_run": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, F64P, F64P, I32P, VP]),
     "ftlm_run_ex": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, F64P, F64P, I32P, VP,
                               C.POINTER(RunInfo)]),
     "ftlm_run_fused": (C.c_int, [C.POINTER(FusedJob), C.c_int32, VP]),
+    "ftlm_run_begin": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, VP, C.POINTER(VP)]),
+    "ftlm_run_advance": (C.c_int, [VP, C.c_int32, I32P]),
+    "ftlm_run_save": (C.c_int, [VP, C.c_char_p]),
+    "ftlm_run_load": (C.c_int, [VP, C.c_char_p, VP, C.POINTER(VP)]),
+    "ftlm_run_finish": (C.c_int, [VP, F64P, F64P, I32P]),
+    "ftlm_run_state_free": (None, [VP]),
     "ftlm_kpm": (C.c_int, [VP, C.c_int32, C.c_int32, C.c_uint64, C.c_int32, C.c_int32, C.c_double, C.c_double,
                            F64P, VP]),
     "ftlm_kpm_observables": (C.c_int, [C.POINTER(KpmBlock), C.c_int32, F64P, C.c_int32, C.c_double, C.c_int32,

@@ -251,6 +251,53 @@ class Block:
         return alpha, beta, ns
 
 
+class LanczosRunState:
+    """ftlm_run in stages with checkpoints (ftlm_run_begin / advance / save / load / finish)."""
+
+    def __init__(self, block, handle, R, steps):
+        self.block, self._h, self.R, self.steps = block, handle, R, steps
+        self._free = lib().ftlm_run_state_free
+
+    @classmethod
+    def begin(cls, block, R, steps, seed, storage=F64, dist=RADEMACHER, stream=None):
+        h = C.c_void_p()
+        check(lib().ftlm_run_begin(block._h, int(R), int(steps), C.c_uint64(seed), int(storage), int(dist),
+                                   L.stream_handle(stream) if stream is not None else None, C.byref(h)))
+        return cls(block, h, int(R), int(steps))
+
+    @classmethod
+    def load(cls, block, path, R, steps, stream=None):
+        """R and steps size the outputs of finish(); they must be the saved run's."""
+        h = C.c_void_p()
+        check(lib().ftlm_run_load(block._h, str(path).encode(),
+                                  L.stream_handle(stream) if stream is not None else None, C.byref(h)))
+        return cls(block, h, int(R), int(steps))
+
+    def advance(self, n):
+        done = C.c_int32()
+        check(lib().ftlm_run_advance(self._h, int(n), C.byref(done)))
+        return done.value
+
+    def save(self, path):
+        check(lib().ftlm_run_save(self._h, str(path).encode()))
+
+    def finish(self):
+        alpha = np.zeros((self.R, self.steps))
+        beta = np.zeros((self.R, self.steps))
+        ns = np.zeros(self.R, np.int32)
+        check(lib().ftlm_run_finish(self._h, alpha.ctypes.data_as(L.F64P), beta.ctypes.data_as(L.F64P),
+                                    ns.ctypes.data_as(L.I32P)))
+        return alpha, beta, ns
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
 def run_fused(jobs, stream=None):
     """ftlm_run_fused: the fused small-block Lanczos kernel over many jobs.
 
@@ -270,6 +317,31 @@ def run_fused(jobs, stream=None):
                             alpha.ctypes.data_as(L.F64P), beta.ctypes.data_as(L.F64P), ns.ctypes.data_as(L.I32P))
     check(lib().ftlm_run_fused(arr, len(jobs), L.stream_handle(stream) if stream is not None else None))
     return out
+
+
+def device_arch():
+    """Architecture name of the current device (the autotuner keys carry it)."""
+    buf = C.create_string_buffer(256)
+    check(lib().ftlm_device_arch(buf, 256))
+    return buf.value.decode()
+
+
+def autotune_save(path, arch=None):
+    """Write the autotuner's cached choices of `arch` (None: all) to path; returns their number."""
+    n = C.c_int32()
+    check(lib().ftlm_autotune_save(str(path).encode(), arch.encode() if arch else None, C.byref(n)))
+    return n.value
+
+
+def autotune_load(path, arch=None):
+    """Add the choices of `arch` (None: all) from path to the cache; returns their number."""
+    n = C.c_int32()
+    check(lib().ftlm_autotune_load(str(path).encode(), arch.encode() if arch else None, C.byref(n)))
+    return n.value
+
+
+def autotune_clear():
+    check(lib().ftlm_autotune_clear())
 
 
 def kpm_observables(blocks, T, g=1.0, n_nodes=0):

@@ -75,7 +75,7 @@ def build(jobs: int | None = None, verbose: bool = True, incremental: bool = Fal
 
 
 # host-only sources: groups and irreps, Ritz data and thermal sums, their C entry points
-HOST_ONLY = ("group.cpp", "thermo.cpp", "capi_host.cpp")
+HOST_ONLY = ("group.cpp", "thermo.cpp", "tune_cache.cpp", "capi_host.cpp")
 
 
 SANITIZERS = {"address": ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"],

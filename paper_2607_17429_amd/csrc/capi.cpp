@@ -154,7 +154,7 @@ int ftlm_apply_H_ex(ftlm_block* b, const void* X, void* Y, int32_t nvec, int64_t
     if (!b) fail(FTLM_ERR_INVALID_ARG, "null block");
     if (X == Y && X) fail(FTLM_ERR_INVALID_ARG, "X and Y must not overlap");
     const Block& B = *b->b;
-    const HvExPlan p = plan_hv_ex(B, nvec, dtype, opts);
+    const HvExPlan p = plan_hv_ex(B, nvec, ld, dtype, opts);
     hipStream_t st = (hipStream_t)stream;
     AllocStreamScope scope(st ? st : tl_alloc_stream);  // stream-ordered scratch: no device-wide sync on free
     DevBuf<double> partials;
@@ -167,6 +167,15 @@ int ftlm_apply_H_ex(ftlm_block* b, const void* X, void* Y, int32_t nvec, int64_t
   });
 }
 
+int ftlm_device_arch(char* buf, int32_t len) {
+  return guarded([&] {
+    if (!buf || len <= 0) fail(FTLM_ERR_INVALID_ARG, "null or empty buffer");
+    const std::string a = device_arch();
+    if ((int32_t)a.size() >= len) fail(FTLM_ERR_INVALID_ARG, "buffer too small for the architecture name");
+    std::memcpy(buf, a.c_str(), a.size() + 1);
+  });
+}
+
 int ftlm_block_autotune(ftlm_block* b, int32_t nvec, int32_t dtype, void* stream, int32_t* best_lanes,
                         double* best_ms, int32_t* tried, double* tried_ms, int32_t* n_tried) {
   return guarded([&] {
@@ -176,8 +185,9 @@ int ftlm_block_autotune(ftlm_block* b, int32_t nvec, int32_t dtype, void* stream
     const Block& B = *b->b;
     // the launch of ftlm_run and ftlm_kpm (their row layout, Lanczos epilogue),
     // whose times are reported, then the plain launch of ftlm_apply_H
-    auto res = autotune_hv(B, nvec, dtype, (hipStream_t)stream, 5, padded_vectors(B), true);
-    (void)autotune_hv(B, nvec, dtype, (hipStream_t)stream, 5, false, false);
+    const int64_t elem = dtype == FTLM_F64 ? 8 : dtype == FTLM_F32 ? 4 : 2;
+    auto res = autotune_hv(B, nvec, dtype, (hipStream_t)stream, 5, run_layout(B, nvec * elem), true);
+    (void)autotune_hv(B, nvec, dtype, (hipStream_t)stream, 5, VecLayout{}, false);
     int bi = -1;
     for (size_t i = 0; i < res.size(); ++i)
       if (bi < 0 || res[i].second < res[bi].second) bi = (int)i;
@@ -207,6 +217,72 @@ int ftlm_run_ex(ftlm_block* b, int32_t R, int32_t steps, uint64_t seed, int32_t 
     if (info) std::memset(info, 0, sizeof(*info));
     run_lanczos(*b->b, R, steps, seed, storage, dist, alpha, beta, nsteps, (hipStream_t)stream, info);
   });
+}
+
+int ftlm_run_begin(ftlm_block* b, int32_t R, int32_t steps, uint64_t seed, int32_t storage, int32_t dist, void* stream,
+                   ftlm_run_state** out) {
+  return guarded([&] {
+    if (!b || !out) fail(FTLM_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    auto s = std::make_unique<ftlm_run_state>();
+    s->block = b->b.get();
+    s->st = (hipStream_t)stream;
+    AllocStreamScope scope(s->st ? s->st : tl_alloc_stream);
+    s->run = std::make_unique<LanczosRun>(*s->block, R, steps, seed, storage, dist);
+    s->run->allocate();
+    s->run->enqueue_begin(s->st);
+    s->next_step = 0;
+    *out = s.release();
+  });
+}
+
+int ftlm_run_advance(ftlm_run_state* s, int32_t n, int32_t* done) {
+  return guarded([&] {
+    if (!s || n < 0) fail(FTLM_ERR_INVALID_ARG, "bad arguments");
+    const int j1 = std::min(s->run->target, s->next_step + n);
+    s->run->enqueue_steps(s->st, s->next_step, j1);
+    s->next_step = std::max(s->next_step, j1);
+    if (done) *done = s->next_step;
+  });
+}
+
+int ftlm_run_save(ftlm_run_state* s, const char* path) {
+  return guarded([&] {
+    if (!s) fail(FTLM_ERR_INVALID_ARG, "null run");
+    s->run->save(path, s->st, s->next_step);
+  });
+}
+
+int ftlm_run_load(ftlm_block* b, const char* path, void* stream, ftlm_run_state** out) {
+  return guarded([&] {
+    if (!b || !out) fail(FTLM_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    auto s = std::make_unique<ftlm_run_state>();
+    s->block = b->b.get();
+    s->st = (hipStream_t)stream;
+    AllocStreamScope scope(s->st ? s->st : tl_alloc_stream);
+    s->run = LanczosRun::load(*s->block, path, s->st, s->next_step);
+    *out = s.release();
+  });
+}
+
+int ftlm_run_finish(ftlm_run_state* s, double* alpha, double* beta, int32_t* nsteps) {
+  return guarded([&] {
+    if (!s) fail(FTLM_ERR_INVALID_ARG, "null run");
+    if (!alpha || !beta || !nsteps) fail(FTLM_ERR_INVALID_ARG, "null output");
+    s->run->enqueue_steps(s->st, s->next_step, s->run->target);
+    s->next_step = std::max(s->next_step, s->run->target);
+    s->run->enqueue_end(s->st);
+    s->run->download(s->st, alpha, beta, nsteps);
+    FTLM_HIP(hipStreamSynchronize(s->st));
+  });
+}
+
+void ftlm_run_state_free(ftlm_run_state* s) {
+  if (!s) return;
+  AllocStreamScope scope(s->st ? s->st : tl_alloc_stream);
+  s->run.reset();
+  delete s;
 }
 
 int ftlm_run_fused(const ftlm_fused_job* jobs, int32_t n, void* stream) {

@@ -10,6 +10,7 @@
 #include "capi_guard.h"
 #include "group.h"
 #include "internal.h"
+#include "tune_cache.h"
 
 namespace ftlm {
 
@@ -109,6 +110,24 @@ int ftlm_observables(const ftlm_ritz* blocks, int32_t nblocks, const double* T, 
       if (!(T[i] > 0)) fail(FTLM_ERR_INVALID_ARG, "temperatures must be positive");
     observables(blocks, nblocks, T, nT, g, E, C, chi, logZ);
   });
+}
+
+int ftlm_autotune_save(const char* path, const char* arch, int32_t* n_saved) {
+  return guarded([&] {
+    const int n = tune_save(path, arch);
+    if (n_saved) *n_saved = n;
+  });
+}
+
+int ftlm_autotune_load(const char* path, const char* arch, int32_t* n_loaded) {
+  return guarded([&] {
+    const int n = tune_load(path, arch);
+    if (n_loaded) *n_loaded = n;
+  });
+}
+
+int ftlm_autotune_clear(void) {
+  return guarded([&] { tune_clear(); });
 }
 
 }  // extern "C"

@@ -17,6 +17,37 @@
 namespace ftlm {
 namespace dev {
 
+// Row map of the padded vector layouts: representative i starts at row
+// (i / rpl) * rpline + (i % rpl) * dstride, i.e. i * dstride when rpl = 1;
+// with rpl > 1 (rpl representatives packed into one 128-byte line of rpline
+// rows) representatives are counted in 32 bits.
+struct PadMap {
+  uint32_t dstride, rpl, rpline;
+  uint64_t n_reps;
+};
+
+__host__ __device__ __forceinline__ uint64_t padded_row(uint32_t dstride, uint32_t rpl, uint32_t rpline, uint64_t i) {
+  if (rpl <= 1) return i * (uint64_t)dstride;
+  const uint32_t i32 = (uint32_t)i;
+  return (uint64_t)(i32 / rpl) * rpline + (uint64_t)(i32 % rpl) * dstride;
+}
+
+// The representative i and row k within it that stored row `row` holds;
+// false for the rows between packed representatives and past the last one.
+__host__ __device__ __forceinline__ bool padded_rep_of(const PadMap& m, uint64_t row, uint64_t& i, int& k) {
+  if (m.rpl <= 1) {
+    i = row / m.dstride;
+    k = (int)(row - i * m.dstride);
+    return i < m.n_reps;
+  }
+  const uint64_t g = row / m.rpline;
+  const uint32_t w = (uint32_t)(row - g * m.rpline);
+  const uint32_t slot = w / m.dstride;
+  k = (int)(w - slot * m.dstride);
+  i = g * m.rpl + slot;
+  return slot < m.rpl && i < m.n_reps;
+}
+
 template <typename W>
 __device__ __forceinline__ int digit(W x, int k, int b, W mask) {
   return (int)((x >> (k * b)) & mask);

@@ -3,9 +3,10 @@
 // kernel instantiations in hv_dg*.hip.  The kernel itself is in hv_kernel.h.
 #include <map>
 #include <mutex>
-#include <tuple>
+#include <string>
 
 #include "hv_kernel.h"
+#include "tune_cache.h"
 
 namespace ftlm {
 
@@ -68,29 +69,41 @@ dim3 hv_grid(const Block& b, const Layout& L) {
 
 uint32_t align16(uint64_t x) { return (uint32_t)((x + 15u) & ~uint64_t(15)); }
 
-// Process-wide autotuner cache: lanes per representative for a kernel shape,
-// keyed also by the row layout (block or padded rows) and by whether the
-// Lanczos epilogue runs, since both change which kernel instantiation a lane
-// layout selects.
-struct TuneKey {
-  int N, two_s, G, dgp, nvec, dtype, mode, pad, epi;
-  bool operator<(const TuneKey& o) const {
-    return std::tie(N, two_s, G, dgp, nvec, dtype, mode, pad, epi) <
-           std::tie(o.N, o.two_s, o.G, o.dgp, o.nvec, o.dtype, o.mode, o.pad, o.epi);
-  }
-};
-std::mutex g_tune_mu;
-std::map<TuneKey, int> g_tune;
-
-TuneKey tune_key(const Block& b, int nvec, int dtype, bool pad, bool epi) {
-  const Sector& s = *b.sec;
-  return TuneKey{s.N, s.two_s, s.gorder, b.dgp, nvec, dtype, s.hv_mode, pad ? 1 : 0, epi ? 1 : 0};
+// Architecture name of the current device (cached per device ordinal): part
+// of every autotuner key, so that a cache loaded from a file tuned on other
+// hardware is never used here.
+std::string current_arch() {
+  static std::mutex mu;
+  static std::map<int, std::string> names;
+  int dev = 0;
+  FTLM_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = names.find(dev);
+  if (it != names.end()) return it->second;
+  hipDeviceProp_t prop{};
+  FTLM_HIP(hipGetDeviceProperties(&prop, dev));
+  return names[dev] = std::string(prop.gcnArchName);
 }
 
-int tuned_gl(const Block& b, int nvec, int dtype, bool pad, bool epi) {
-  std::lock_guard<std::mutex> lk(g_tune_mu);
-  auto it = g_tune.find(tune_key(b, nvec, dtype, pad, epi));
-  return it == g_tune.end() ? 0 : it->second;
+TuneKey tune_key(const Block& b, int nvec, int dtype, const VecLayout& vl, bool epi) {
+  const Sector& s = *b.sec;
+  TuneKey k;
+  k.arch = current_arch();
+  k.cluster = s.cluster_hash;
+  k.N = s.N;
+  k.two_s = s.two_s;
+  k.G = s.gorder;
+  k.dgp = b.dgp;
+  k.nvec = nvec;
+  k.dtype = dtype;
+  k.mode = s.hv_mode;
+  k.pad = vl.kind();
+  k.epi = epi ? 1 : 0;
+  return k;
+}
+
+int tuned_gl(const Block& b, int nvec, int dtype, const VecLayout& vl, bool epi) {
+  return tune_lookup(tune_key(b, nvec, dtype, vl, epi));
 }
 
 // Column sums of a (ng x nvec) array of per-workgroup partials, one workgroup
@@ -117,6 +130,8 @@ __global__ void k_fill_f64(double* __restrict__ p, int n, double x) {
 
 }  // namespace
 
+std::string device_arch() { return current_arch(); }
+
 int irrep_dim_bucket(int d) {
   if (d >= 1 && d <= 6) return d;
   if (d <= 8) return 8;
@@ -124,8 +139,8 @@ int irrep_dim_bucket(int d) {
   return -1;
 }
 
-int hv_layout_lanes(const Block& b, int nvec, int dtype, bool pad, bool epi) {
-  return choose_layout(nvec, b.sec->hv_mode == FTLM_HV_ONTHEFLY, tuned_gl(b, nvec, dtype, pad, epi)).GL;
+int hv_layout_lanes(const Block& b, int nvec, int dtype, const VecLayout& vl, bool epi) {
+  return choose_layout(nvec, b.sec->hv_mode == FTLM_HV_ONTHEFLY, tuned_gl(b, nvec, dtype, vl, epi)).GL;
 }
 
 int hv_partial_groups(const Block& b, int nvec, int gl) {
@@ -134,15 +149,15 @@ int hv_partial_groups(const Block& b, int nvec, int gl) {
 
 void apply_hv(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t st,
               const LanczosEpilogue* lz) {
-  apply_hv_gl(b, X, Y, nvec, ld, dtype, st, lz, tuned_gl(b, nvec, dtype, false, lz != nullptr));
+  apply_hv_gl(b, X, Y, nvec, ld, dtype, st, lz, tuned_gl(b, nvec, dtype, VecLayout{}, lz != nullptr));
 }
 
-std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dtype, hipStream_t st, int reps, bool pad,
-                                                bool epi) {
+std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dtype, hipStream_t st, int reps,
+                                                const VecLayout& vl, bool epi) {
   std::vector<std::pair<int, double>> out;
   if (b.D == 0 || b.sec->n_reps == 0) return out;
   const size_t elem = dtype == FTLM_F64 ? 8 : dtype == FTLM_F32 ? 4 : 2;
-  const uint64_t rows = pad ? b.D_pad : b.D;
+  const uint64_t rows = vec_rows(b, vl);
   DevBuf<uint8_t> X, Y;
   DevBuf<double> scal, partials;
   X.alloc((size_t)rows * nvec * elem);
@@ -166,9 +181,9 @@ std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dt
     if (gl * 8 < nvec || gl > pow2_at_least(nvec)) continue;  // VPL <= 8, no empty lanes beyond one pow2
     LanczosEpilogue lz{scal.p, partials.p, hv_partial_groups(b, nvec, gl)};
     const LanczosEpilogue* lzp = epi ? &lz : nullptr;
-    apply_hv_gl(b, X.p, Y.p, nvec, nvec, dtype, st, lzp, gl, pad);  // warm
+    apply_hv_gl(b, X.p, Y.p, nvec, nvec, dtype, st, lzp, gl, vl);  // warm
     FTLM_HIP(hipEventRecord(e0, st));
-    for (int r = 0; r < reps; ++r) apply_hv_gl(b, X.p, Y.p, nvec, nvec, dtype, st, lzp, gl, pad);
+    for (int r = 0; r < reps; ++r) apply_hv_gl(b, X.p, Y.p, nvec, nvec, dtype, st, lzp, gl, vl);
     FTLM_HIP(hipEventRecord(e1, st));
     FTLM_HIP(hipEventSynchronize(e1));
     float ms = 0;
@@ -182,40 +197,35 @@ std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dt
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (best) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[tune_key(b, nvec, dtype, pad, epi)] = best;
-  }
+  if (best) tune_store(tune_key(b, nvec, dtype, vl, epi), best);
   return out;
 }
 
-HvExPlan plan_hv_ex(const Block& b, int nvec, int dtype, const ftlm_hv_opts* o) {
+HvExPlan plan_hv_ex(const Block& b, int nvec, int64_t ld, int dtype, const ftlm_hv_opts* o) {
   HvExPlan p{};
-  if (nvec <= 0) fail(FTLM_ERR_INVALID_ARG, "need 0 < nvec <= ld");
+  if (nvec <= 0 || ld < nvec) fail(FTLM_ERR_INVALID_ARG, "need 0 < nvec <= ld");
+  const int64_t elem = dtype == FTLM_F64 ? 8 : dtype == FTLM_F32 ? 4 : 2;
   const int layout = o ? o->layout : FTLM_LAYOUT_BLOCK;
   if (layout == FTLM_LAYOUT_AUTO)
-    p.pad = padded_vectors(b);
-  else if (layout == FTLM_LAYOUT_PADDED)
-    p.pad = true;
-  else if (layout == FTLM_LAYOUT_BLOCK)
-    p.pad = false;
+    p.vl = run_layout(b, ld * elem);
+  else if (layout == FTLM_LAYOUT_BLOCK || layout == FTLM_LAYOUT_PADDED || layout == FTLM_LAYOUT_PACKED)
+    p.vl = vec_layout(b, layout, ld * elem);
   else
-    fail(FTLM_ERR_INVALID_ARG, "layout must be FTLM_LAYOUT_AUTO, _BLOCK or _PADDED");
-  if (p.pad && b.D_pad >= (1ull << 48)) fail(FTLM_ERR_UNSUPPORTED, "padded rows above 2^48");
-  p.rows = p.pad ? b.D_pad : b.D;
+    fail(FTLM_ERR_INVALID_ARG, "layout must be FTLM_LAYOUT_AUTO, _BLOCK, _PADDED or _PACKED");
+  p.rows = vec_rows(b, p.vl);
   p.epi = o && o->scale;
   if (o && o->dots && !o->scale) fail(FTLM_ERR_INVALID_ARG, "dots need scale");
   const int lanes = o ? o->lanes : 0;
   if (lanes != 0 && (lanes < 0 || lanes > 64 || (lanes & (lanes - 1))))
     fail(FTLM_ERR_INVALID_ARG, "lanes must be 0 or a power of two up to 64");
   const bool otf = b.sec->hv_mode == FTLM_HV_ONTHEFLY;
-  const Layout L = choose_layout(nvec, otf, lanes ? lanes : tuned_gl(b, nvec, dtype, p.pad, p.epi));
+  const Layout L = choose_layout(nvec, otf, lanes ? lanes : tuned_gl(b, nvec, dtype, p.vl, p.epi));
   p.gl = L.GL;
   p.ng = (b.D && b.sec->n_reps) ? hv_partial_groups(b, nvec, p.gl) : 0;
   if (b.D && b.sec->n_reps) {
     LaunchCfg c{};
     HvArgs<double> a{};
-    hv_setup(b, nvec, nvec, p.gl, p.pad, nullptr, c, a);
+    hv_setup(b, nvec, nvec, p.gl, p.vl, nullptr, c, a);
     p.adjacent = c.contig && c.slds && !c.otf && b.dgp <= 6;
   }
   return p;
@@ -223,7 +233,6 @@ HvExPlan plan_hv_ex(const Block& b, int nvec, int dtype, const ftlm_hv_opts* o) 
 
 void apply_hv_ex(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, const ftlm_hv_opts* o,
                  const HvExPlan& p, double* partials, hipStream_t st) {
-  if (ld < nvec) fail(FTLM_ERR_INVALID_ARG, "need 0 < nvec <= ld");
   if (p.epi && p.ng > 0 && !partials) fail(FTLM_ERR_INVALID_ARG, "no scratch for the partial sums");
   if (p.rows == 0 || b.sec->n_reps == 0) {
     if (o && o->dots) hipLaunchKernelGGL(k_fill_f64, dim3((nvec + 255) / 256), dim3(256), 0, st, o->dots, nvec, 0.0);
@@ -233,21 +242,22 @@ void apply_hv_ex(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
   if (!X || !Y) fail(FTLM_ERR_INVALID_ARG, "null vector");
   LanczosEpilogue lz{p.epi ? o->scale : nullptr, partials, p.ng, o ? o->shift : 0.0};
   if (p.epi) {
-    apply_hv_gl(b, X, Y, nvec, ld, dtype, st, &lz, p.gl, p.pad);
+    apply_hv_gl(b, X, Y, nvec, ld, dtype, st, &lz, p.gl, p.vl);
     if (o->dots) hipLaunchKernelGGL(k_col_sums, dim3(nvec), dim3(256), 0, st, partials, p.ng, nvec, o->dots);
   } else if (lz.eshift != 0.0) {
     // a shift without the epilogue: the same kernel with scale (1, 0) would
     // need a scale array; the plain pass takes the shift directly
-    apply_hv_gl(b, X, Y, nvec, ld, dtype, st, nullptr, p.gl, p.pad, lz.eshift);
+    apply_hv_gl(b, X, Y, nvec, ld, dtype, st, nullptr, p.gl, p.vl, lz.eshift);
   } else {
-    apply_hv_gl(b, X, Y, nvec, ld, dtype, st, nullptr, p.gl, p.pad);
+    apply_hv_gl(b, X, Y, nvec, ld, dtype, st, nullptr, p.gl, p.vl);
   }
   FTLM_HIP(hipGetLastError());
 }
 
 template <typename T>
-void hv_setup(const Block& b, int nvec, int64_t ld, int gl, bool pad, const LanczosEpilogue* lz, LaunchCfg& c,
-              HvArgs<T>& a) {
+void hv_setup(const Block& b, int nvec, int64_t ld, int gl, const VecLayout& vl, const LanczosEpilogue* lz,
+              LaunchCfg& c, HvArgs<T>& a) {
+  const bool pad = vl.pad;
   const Sector& s = *b.sec;
   const bool otf = s.hv_mode == FTLM_HV_ONTHEFLY;
   const Layout L = choose_layout(nvec, otf, gl);
@@ -298,6 +308,8 @@ void hv_setup(const Block& b, int nvec, int64_t ld, int gl, bool pad, const Lanc
     a.hbits = s.ent_hbits;
     a.pad = pad ? 1 : 0;
     a.dstride = b.dg;
+    a.rpl = vl.rpl;
+    a.rpline = vl.rpl > 1 ? vl.rpline : (uint32_t)b.dg;
     a.triv_sid = s.trivial_sid;
     a.sid = s.d_stab_id.p;
     a.meta = b.d_meta.p;
@@ -347,15 +359,15 @@ void hv_setup(const Block& b, int nvec, int64_t ld, int gl, bool pad, const Lanc
   }
 }
 
-template void hv_setup<double>(const Block&, int, int64_t, int, bool, const LanczosEpilogue*, LaunchCfg&,
-                               HvArgs<double>&);
-template void hv_setup<float>(const Block&, int, int64_t, int, bool, const LanczosEpilogue*, LaunchCfg&,
+template void hv_setup<double>(const Block&, int, int64_t, int, const VecLayout&, const LanczosEpilogue*,
+                               LaunchCfg&, HvArgs<double>&);
+template void hv_setup<float>(const Block&, int, int64_t, int, const VecLayout&, const LanczosEpilogue*, LaunchCfg&,
                               HvArgs<float>&);
-template void hv_setup<_Float16>(const Block&, int, int64_t, int, bool, const LanczosEpilogue*, LaunchCfg&,
-                                 HvArgs<_Float16>&);
+template void hv_setup<_Float16>(const Block&, int, int64_t, int, const VecLayout&, const LanczosEpilogue*,
+                                 LaunchCfg&, HvArgs<_Float16>&);
 
 void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t st,
-                 const LanczosEpilogue* lz, int gl, bool pad, double shift) {
+                 const LanczosEpilogue* lz, int gl, const VecLayout& vl, double shift) {
   const Sector& s = *b.sec;
   if (nvec <= 0 || ld < nvec) fail(FTLM_ERR_INVALID_ARG, "need 0 < nvec <= ld");
   if (b.D == 0 || s.n_reps == 0) return;
@@ -368,19 +380,19 @@ void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
   const HvArgs<float>* p32 = nullptr;
   const HvArgs<_Float16>* p16 = nullptr;
   if (dtype == FTLM_F64) {
-    hv_setup(b, nvec, ld, gl, pad, lz, c, a64);
+    hv_setup(b, nvec, ld, gl, vl, lz, c, a64);
     a64.X = (const double*)X;
     a64.Y = (double*)Y;
     if (!lz) a64.eshift = shift;
     p64 = &a64;
   } else if (dtype == FTLM_F32) {
-    hv_setup(b, nvec, ld, gl, pad, lz, c, a32);
+    hv_setup(b, nvec, ld, gl, vl, lz, c, a32);
     a32.X = (const float*)X;
     a32.Y = (float*)Y;
     if (!lz) a32.eshift = shift;
     p32 = &a32;
   } else if (dtype == FTLM_F16) {
-    hv_setup(b, nvec, ld, gl, pad, lz, c, a16);
+    hv_setup(b, nvec, ld, gl, vl, lz, c, a16);
     a16.X = (const _Float16*)X;
     a16.Y = (_Float16*)Y;
     if (!lz) a16.eshift = shift;

@@ -66,9 +66,11 @@ struct HvArgs {
   const uint16_t* ehc;
   int hbits;
   // vector layout: pad == 0: block rows (representative i at meta offset);
-  // pad != 0: padded rows, representative i at i * dstride (= d_Gamma), and a
+  // pad != 0: padded rows, representative i at dev::padded_row (i * dstride,
+  // dstride = d_Gamma, or packed rpl to a line of rpline rows), and a
   // target's stabilizer id comes from the entry's trivial bit or sid[]
   int pad, dstride, triv_sid;
+  uint32_t rpl, rpline;
   const uint16_t* sid;
   const uint64_t* meta;
   const double* ediag;
@@ -197,7 +199,7 @@ __device__ __forceinline__ void hv_pass(const HvArgs<T>& a, const HvTabs& tb,
     const int sp = (int)(mp >> 48);
     const int np_ = (int)stabf[4 * sp];
     if (np_ == 0) continue;
-    const uint64_t offp = a.pad ? p * (uint64_t)a.dstride : (mp & kOffMask);
+    const uint64_t offp = a.pad ? dev::padded_row((uint32_t)a.dstride, a.rpl, a.rpline, p) : (mp & kOffMask);
     const W plab = (W)a.reps[p];
     double acc[DG][VPL];
 #pragma unroll
@@ -244,7 +246,7 @@ __device__ __forceinline__ void hv_pass(const HvArgs<T>& a, const HvTabs& tb,
       if (myidx != kInvalid) {
         if (a.pad) {
           const uint64_t sr = (my >> 63) ? (uint64_t)a.triv_sid : (uint64_t)a.sid[myidx];
-          mm = (uint64_t)myidx * (uint64_t)a.dstride | (sr << 48);
+          mm = dev::padded_row((uint32_t)a.dstride, a.rpl, a.rpline, myidx) | (sr << 48);
         } else {
           mm = a.meta[myidx];
         }
@@ -504,7 +506,7 @@ void launch_dg(const HvArgs<double>* a64, const HvArgs<float>* a32, const HvArgs
 // over nvec vectors of leading dimension ld with gl lanes per representative
 // (0: the default or autotuned layout).
 template <typename T>
-void hv_setup(const Block& b, int nvec, int64_t ld, int gl, bool pad, const LanczosEpilogue* lz, hvk::LaunchCfg& c,
-              hvk::HvArgs<T>& a);
+void hv_setup(const Block& b, int nvec, int64_t ld, int gl, const VecLayout& vl, const LanczosEpilogue* lz,
+              hvk::LaunchCfg& c, hvk::HvArgs<T>& a);
 
 }  // namespace ftlm

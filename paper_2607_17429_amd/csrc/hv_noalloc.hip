@@ -49,7 +49,7 @@ extern "C" int ftlm_apply_H_ex_noalloc(ftlm_block* b, const void* X, void* Y, in
     if (!b) fail(FTLM_ERR_INVALID_ARG, "null block");
     if (X == Y && X) fail(FTLM_ERR_INVALID_ARG, "X and Y must not overlap");
     const Block& B = *b->b;
-    const HvExPlan p = plan_hv_ex(B, nvec, dtype, opts);
+    const HvExPlan p = plan_hv_ex(B, nvec, ld, dtype, opts);
     double* partials = nullptr;
     if (p.epi && p.ng > 0) {
       if ((size_t)p.ng * (size_t)nvec > kNoallocScratchDoubles)

@@ -32,6 +32,7 @@ struct Sector {
   int gorder = 0;               // |G|, or 2|G| with the spin flip (element (g, f) = f|G| + g)
   uint64_t D_M = 0, n_reps = 0, n_words = 0;
   int hv_mode = FTLM_HV_ENTRIES;
+  uint64_t cluster_hash = 0;    // sizes, bonds, couplings, group elements, spin flip (autotuner key)
   // host copies of small tables
   std::vector<uint64_t> cnt;    // (N+1) x (Amax+1) digit-sum counts
   int cnt_stride = 0;
@@ -119,27 +120,50 @@ struct LanczosEpilogue {
 };
 void apply_hv(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t stream,
               const LanczosEpilogue* lz = nullptr);
+
+// Row layout of stored vectors: the block's rows, or d_Gamma rows per
+// representative (padded), optionally packed p = rpl representatives to a
+// 128-byte line of rpline rows (enum ftlm_layout).
+struct VecLayout {
+  bool pad = false;
+  uint32_t rpl = 1;     // representatives per line (1: plain padded)
+  uint32_t rpline = 0;  // rows per line when rpl > 1
+  int kind() const { return !pad ? FTLM_LAYOUT_BLOCK : rpl > 1 ? FTLM_LAYOUT_PACKED : FTLM_LAYOUT_PADDED; }
+};
+// kind BLOCK, PADDED or PACKED (PACKED falls back to PADDED where it does
+// not apply) for rows of row_bytes bytes
+VecLayout vec_layout(const Block& b, int kind, int64_t row_bytes);
+// the layout ftlm_run and ftlm_kpm take for this block and row size
+VecLayout run_layout(const Block& b, int64_t row_bytes);
+uint64_t vec_rows(const Block& b, const VecLayout& v);
+namespace dev {
+struct PadMap;
+}
+// the device row map of a padded layout
+dev::PadMap pad_map(const Block& b, const VecLayout& v);
+
 // Lane layout: lanes per output representative for (nvec, dtype) (autotuned
 // or default), the partial-sum groups of that layout, and H.V with it fixed.
 // The autotuner keys its choice by the row layout (pad) and by whether the
 // Lanczos epilogue runs (epi).
-int hv_layout_lanes(const Block& b, int nvec, int dtype, bool pad, bool epi);
+int hv_layout_lanes(const Block& b, int nvec, int dtype, const VecLayout& vl, bool epi);
 int hv_partial_groups(const Block& b, int nvec, int gl);
-// pad: X and Y use the padded row layout (representative i at i * d_Gamma).
+// vl: row layout of X and Y (default: block rows).
 // shift: the plain pass (lz == nullptr) applies H - shift.
 void apply_hv_gl(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, hipStream_t stream,
-                 const LanczosEpilogue* lz, int gl, bool pad = false, double shift = 0.0);
+                 const LanczosEpilogue* lz, int gl, const VecLayout& vl = VecLayout{}, double shift = 0.0);
 
 // ftlm_apply_H_ex: the launch decided on the host (row layout, lane layout,
 // partial-sum groups of the epilogue, whether the adjacent-column kernel runs)
 // and the enqueue with caller-provided scratch for the partials (p.ng * nvec
 // doubles when p.epi).
 struct HvExPlan {
-  bool pad = false, epi = false, adjacent = false;
+  VecLayout vl;
+  bool epi = false, adjacent = false;
   int gl = 0, ng = 0;
   uint64_t rows = 0;
 };
-HvExPlan plan_hv_ex(const Block& b, int nvec, int dtype, const ftlm_hv_opts* o);
+HvExPlan plan_hv_ex(const Block& b, int nvec, int64_t ld, int dtype, const ftlm_hv_opts* o);
 void apply_hv_ex(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int dtype, const ftlm_hv_opts* o,
                  const HvExPlan& p, double* partials, hipStream_t st);
 
@@ -149,9 +173,11 @@ void apply_hv_ex(const Block& b, const void* X, void* Y, int nvec, int64_t ld, i
 bool padded_vectors(const Block& b);
 // Times every lane layout for (nvec, dtype) on this block, caches the fastest
 // process-wide and returns (lanes per representative, ms per launch) pairs.
-std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dtype, hipStream_t st, int reps, bool pad,
-                                                bool epi);
+std::vector<std::pair<int, double>> autotune_hv(const Block& b, int nvec, int dtype, hipStream_t st, int reps,
+                                                const VecLayout& vl, bool epi);
 int irrep_dim_bucket(int d);
+// gcnArchName of the current device
+std::string device_arch();
 
 // One batched Lanczos run of R chains on a block: device state, an enqueue of
 // every kernel on one stream (no host synchronisation) and an asynchronous
@@ -162,7 +188,7 @@ struct LanczosRun {
   uint64_t seed;
   int target = 0, TB = 0, nb_vec = 0, gl = 0, ng_hv = 0;
   int first_chain = 0;           // chain keys start at this chain index
-  bool pad = false;              // padded vector rows (FTLM_LAYOUT_PADDED)
+  VecLayout vl;                  // row layout of the stored vectors
   double sigma = 1.0;            // power-of-two storage scale of the vectors (FP16)
   uint64_t rows = 0;             // rows of each stored vector
   // optional timing of the H.V launches (two events per step)
@@ -187,6 +213,11 @@ struct LanczosRun {
   double hv_ms() const;          // after the stream has finished
   ~LanczosRun();
   void download(hipStream_t st, double* alpha, double* beta, int32_t* nsteps);
+  // Checkpoint: the whole device state after `next_step` steps (both vectors,
+  // per-chain state, coefficients so far) to a file, and a run rebuilt from
+  // one on a block that must be the same (cluster, sector, irrep, row, rows).
+  void save(const char* path, hipStream_t st, int next_step) const;
+  static std::unique_ptr<LanczosRun> load(const Block& b, const char* path, hipStream_t st, int& next_step);
 };
 
 void run_lanczos(Block& b, int R, int steps, uint64_t seed, int storage, int dist, double* alpha,
@@ -270,4 +301,11 @@ struct ftlm_sector {
 
 struct ftlm_block {
   std::unique_ptr<ftlm::Block> b;
+};
+
+struct ftlm_run_state {
+  ftlm::Block* block = nullptr;               // the caller's block (must outlive the state)
+  std::unique_ptr<ftlm::LanczosRun> run;
+  hipStream_t st = nullptr;
+  int next_step = 0;
 };

@@ -22,14 +22,15 @@ namespace ftlm {
 namespace {
 
 // thread layout (row r0, chain v) as in the Lanczos kernels; D rows of the
-// stored vectors.  With meta (padded layout) row i * dstride + k is block row
-// offset(i) + k of representative i, and rows k >= n_Gamma(i) are zeros.
+// stored vectors.  With meta (padded layouts) stored row r holds row k of
+// representative i (dev::padded_rep_of), block row offset(i) + k for
+// k < n_Gamma(i); every other stored row is zero.
 template <typename T>
 __global__ void __launch_bounds__(256) k_kpm_start(const uint64_t* __restrict__ keys, int dist, uint64_t D, int R,
                                                   const double* __restrict__ inv_norm, T* __restrict__ Q,
                                                   T* __restrict__ Qz, double* __restrict__ partials,
                                                   const uint64_t* __restrict__ meta,
-                                                  const double* __restrict__ stabf, int dstride) {
+                                                  const double* __restrict__ stabf, dev::PadMap pm) {
   __shared__ double red[256];
   const int t = threadIdx.x;
   const int RB = blockDim.x / R;
@@ -40,11 +41,14 @@ __global__ void __launch_bounds__(256) k_kpm_start(const uint64_t* __restrict__ 
       uint64_t brow = row;
       bool live = true;
       if (meta) {
-        const uint64_t i = row / (uint64_t)dstride;
-        const int k = (int)(row - i * (uint64_t)dstride);
-        const uint64_t m = meta[i];
-        live = k < (int)stabf[4 * (m >> 48)];
-        brow = (m & ((1ull << 48) - 1)) + (uint64_t)k;
+        uint64_t i;
+        int k;
+        live = dev::padded_rep_of(pm, row, i, k);
+        if (live) {
+          const uint64_t m = meta[i];
+          live = k < (int)stabf[4 * (m >> 48)];
+          brow = (m & ((1ull << 48) - 1)) + (uint64_t)k;
+        }
       }
       const double x = live ? dev::start_value(keys[v], brow, dist) : 0.0;
       if (inv_norm) {
@@ -180,14 +184,15 @@ template <typename T>
 void kpm_typed(const Block& b, int R, int M, uint64_t seed, int dist, double center, double half_width,
                double* moments, hipStream_t st) {
   // the Lanczos run's row layout: padded rows give the H.V its dense gather
-  const bool pad = padded_vectors(b);
-  const uint64_t D = pad ? b.D_pad : b.D;
-  const uint64_t* meta = pad ? b.d_meta.p : nullptr;
+  const VecLayout vl = run_layout(b, (int64_t)R * (int64_t)sizeof(T));
+  const uint64_t D = vec_rows(b, vl);
+  const uint64_t* meta = vl.pad ? b.d_meta.p : nullptr;
+  const dev::PadMap pm = pad_map(b, vl);
   const double* stabf = b.d_stabf64.p;
   const int TB = R * (256 / R);
   const unsigned nb = groups_for(D, TB / R);
   const int dtype = sizeof(T) == 8 ? FTLM_F64 : FTLM_F32;
-  const int gl = hv_layout_lanes(b, R, dtype, pad, true);
+  const int gl = hv_layout_lanes(b, R, dtype, vl, true);
   const int ng_hv = hv_partial_groups(b, R, gl);
   DevBuf<T> q0, q1;
   q0.alloc(D * R);
@@ -213,10 +218,10 @@ void kpm_typed(const Block& b, int R, int M, uint64_t seed, int dist, double cen
   scal0.upload(s0, st);
   scal1.upload(s1, st);
   hipLaunchKernelGGL((k_kpm_start<T>), dim3(nb), dim3(TB), 0, st, keys.p, dist, D, R, (const double*)nullptr, q0.p,
-                     q1.p, pnrm.p, meta, stabf, b.dg);
+                     q1.p, pnrm.p, meta, stabf, pm);
   hipLaunchKernelGGL(k_kpm_init, dim3(R), dim3(256), 0, st, pnrm.p, (int)nb, R, inv_norm.p, rr.p, mu.p, M, 0);
   hipLaunchKernelGGL((k_kpm_start<T>), dim3(nb), dim3(TB), 0, st, keys.p, dist, D, R, inv_norm.p, q0.p, q1.p,
-                     pnrm.p, meta, stabf, b.dg);
+                     pnrm.p, meta, stabf, pm);
   hipLaunchKernelGGL(k_kpm_init, dim3(R), dim3(256), 0, st, pnrm.p, (int)nb, R, inv_norm.p, rr.p, mu.p, M, 1);
   FTLM_HIP(hipGetLastError());
   const int steps = M > 1 ? M / 2 : 0;  // step k yields moments 2k+1 and 2k+2
@@ -224,7 +229,7 @@ void kpm_typed(const Block& b, int R, int M, uint64_t seed, int dist, double cen
     T* tk = (k & 1) ? q1.p : q0.p;
     T* tprev = (k & 1) ? q0.p : q1.p;  // t_{k-1} on entry, t_{k+1} on exit
     LanczosEpilogue lz{k == 0 ? scal0.p : scal1.p, pdot.p, ng_hv, center};
-    apply_hv_gl(b, tk, tprev, R, R, dtype, st, &lz, gl, pad);
+    apply_hv_gl(b, tk, tprev, R, R, dtype, st, &lz, gl, vl);
     constexpr int NV = 16 / (int)sizeof(T);
     if (R % NV == 0 && ((uintptr_t)tprev & 15) == 0) {
       // rows of whole 16-byte column groups, every row 16-byte aligned

@@ -20,6 +20,9 @@
 // Box-Muller transform); normalised in FP64, then rounded to storage.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
 
 #include "device.h"
 #include "internal.h"
@@ -48,12 +51,13 @@ struct Chain {
 // threads per block, so each thread's elements belong to one chain and the
 // per-chain block sums are reduced in a fixed order.
 template <typename T>
-// Padded layout (meta != nullptr): stored row i * dstride + k is block row
-// offset(i) + k for k < n_Gamma(i) and zero otherwise; D counts stored rows.
+// Padded layout (meta != nullptr): stored row r holds row k of representative
+// i (dev::padded_rep_of), which is block row offset(i) + k for k < n_Gamma(i);
+// every other stored row is zero.  D counts stored rows.
 __global__ void __launch_bounds__(256) k_start(const uint64_t* __restrict__ keys, int dist, uint64_t D, int R,
                                               const double* __restrict__ inv_norm, T* __restrict__ Q,
                                               double* __restrict__ partials, const uint64_t* __restrict__ meta,
-                                              const double* __restrict__ stabf, int dstride) {
+                                              const double* __restrict__ stabf, dev::PadMap pm) {
   __shared__ double red[256];
   const int t = threadIdx.x;
   const int RB = blockDim.x / R;
@@ -63,11 +67,14 @@ __global__ void __launch_bounds__(256) k_start(const uint64_t* __restrict__ keys
     uint64_t brow = row;
     bool live = true;
     if (meta) {
-      const uint64_t i = row / (uint64_t)dstride;
-      const int k = (int)(row - i * (uint64_t)dstride);
-      const uint64_t m = meta[i];
-      live = k < (int)stabf[4 * (m >> 48)];
-      brow = (m & ((1ull << 48) - 1)) + (uint64_t)k;
+      uint64_t i;
+      int k;
+      live = dev::padded_rep_of(pm, row, i, k);
+      if (live) {
+        const uint64_t m = meta[i];
+        live = k < (int)stabf[4 * (m >> 48)];
+        brow = (m & ((1ull << 48) - 1)) + (uint64_t)k;
+      }
     }
     const double x = live ? start_value(keys[v], brow, dist) : 0.0;
     if (inv_norm) {
@@ -226,15 +233,15 @@ void enqueue_begin_typed(LanczosRun& L, hipStream_t st) {
   FTLM_HIP(hipMemsetAsync(L.d_n.p, 0, L.d_n.bytes(), st));
   if (L.target == 0) return;
   // start vectors: norm of the FP64 draw, then the stored, normalised q_0 and its norm
-  const uint64_t* meta = L.pad ? L.block->d_meta.p : nullptr;
+  const uint64_t* meta = L.vl.pad ? L.block->d_meta.p : nullptr;
   const double* stabf = L.block->d_stabf64.p;
-  const int dstride = L.block->dg;
+  const dev::PadMap pm = pad_map(*L.block, L.vl);
   hipLaunchKernelGGL((k_start<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, L.keys.p, L.dist, D, R, (const double*)nullptr,
-                     q0, L.partials.p, meta, stabf, dstride);
+                     q0, L.partials.p, meta, stabf, pm);
   hipLaunchKernelGGL(k_init_chain, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, L.inv_norm.p, ch, 0,
                      L.sigma);
   hipLaunchKernelGGL((k_start<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, L.keys.p, L.dist, D, R, L.inv_norm.p, q0,
-                     L.partials.p, meta, stabf, dstride);
+                     L.partials.p, meta, stabf, pm);
   hipLaunchKernelGGL(k_init_chain, dim3(R), dim3(256), 0, st, L.partials.p, L.nb_vec, R, L.inv_norm.p, ch, 1,
                      L.sigma);
   FTLM_HIP(hipMemsetAsync(L.q1.p, 0, L.q1.bytes(), st));
@@ -256,7 +263,7 @@ void enqueue_one_step(LanczosRun& L, hipStream_t st, bool odd, int timed_j) {
   T* qprev = (T*)(odd ? L.q0.p : L.q1.p);
   LanczosEpilogue lz{L.scal.p, L.partials.p, L.ng_hv};
   if (timed_j >= 0) FTLM_HIP(hipEventRecord(L.hv_events[2 * timed_j], st));
-  apply_hv_gl(b, qj, qprev, R, R, dtype, st, &lz, L.gl, L.pad);  // qprev <- w
+  apply_hv_gl(b, qj, qprev, R, R, dtype, st, &lz, L.gl, L.vl);  // qprev <- w
   if (timed_j >= 0) FTLM_HIP(hipEventRecord(L.hv_events[2 * timed_j + 1], st));
   hipLaunchKernelGGL(k_alpha, dim3(R), dim3(256), 0, st, L.partials.p, L.ng_hv, R, ch, L.d_alpha.p, steps);
   hipLaunchKernelGGL((k_update<T>), dim3(L.nb_vec), dim3(L.TB), 0, st, ch, D, R, qj, qprev, L.partials.p);
@@ -311,12 +318,55 @@ uint64_t chain_key(uint64_t seed, int two_M, int irrep, int row, int chain) {
 
 bool padded_vectors(const Block& b) {
   bool pad = false;
-  if (b.lanczos_layout == FTLM_LAYOUT_PADDED)
+  if (b.lanczos_layout == FTLM_LAYOUT_PADDED || b.lanczos_layout == FTLM_LAYOUT_PACKED)
     pad = true;
   else if (b.lanczos_layout == FTLM_LAYOUT_AUTO)
     pad = b.D >= (1ull << 20) && (double)b.D_pad <= 1.02 * (double)b.D;
   if (pad && b.D_pad >= (1ull << 48)) fail(FTLM_ERR_UNSUPPORTED, "padded rows above 2^48");
   return pad;
+}
+
+VecLayout vec_layout(const Block& b, int kind, int64_t row_bytes) {
+  VecLayout v;
+  if (kind == FTLM_LAYOUT_BLOCK) return v;
+  if (kind != FTLM_LAYOUT_PADDED && kind != FTLM_LAYOUT_PACKED) fail(FTLM_ERR_INVALID_ARG, "bad row layout");
+  v.pad = true;
+  if (kind == FTLM_LAYOUT_PACKED && row_bytes > 0 && 128 % row_bytes == 0 && b.dg > 0 &&
+      b.sec->n_reps < (1ull << 32)) {
+    const uint32_t L = (uint32_t)(128 / row_bytes);
+    const uint32_t p = L / (uint32_t)b.dg;
+    if (p >= 2 && p * (uint32_t)b.dg < L) {
+      v.rpl = p;
+      v.rpline = L;
+    }
+  }
+  if (vec_rows(b, v) >= (1ull << 48)) fail(FTLM_ERR_UNSUPPORTED, "padded rows above 2^48");
+  return v;
+}
+
+// AUTO takes plain padded rows: packing measured no faster (the s = 3/2
+// dodecahedron H_g block, 2 FP32 chains: 578 ms per H.V packed and padded; the
+// gather is bound by the device's rate of random line accesses, one per
+// connection either way, not by the bytes of the lines), and it costs rows.
+VecLayout run_layout(const Block& b, int64_t row_bytes) {
+  if (!padded_vectors(b)) return VecLayout{};
+  return vec_layout(b, b.lanczos_layout == FTLM_LAYOUT_PACKED ? FTLM_LAYOUT_PACKED : FTLM_LAYOUT_PADDED, row_bytes);
+}
+
+uint64_t vec_rows(const Block& b, const VecLayout& v) {
+  if (!v.pad) return b.D;
+  const uint64_t n = b.sec->n_reps;
+  if (v.rpl <= 1) return n * (uint64_t)b.dg;
+  return (n + v.rpl - 1) / v.rpl * (uint64_t)v.rpline;
+}
+
+dev::PadMap pad_map(const Block& b, const VecLayout& v) {
+  dev::PadMap m{};
+  m.dstride = (uint32_t)std::max(b.dg, 1);
+  m.rpl = v.rpl;
+  m.rpline = v.rpl > 1 ? v.rpline : m.dstride;
+  m.n_reps = b.sec->n_reps;
+  return m;
 }
 
 LanczosRun::LanczosRun(const Block& b, int R_, int steps_, uint64_t seed_, int storage_, int dist_)
@@ -328,21 +378,23 @@ LanczosRun::LanczosRun(const Block& b, int R_, int steps_, uint64_t seed_, int s
     fail(FTLM_ERR_INVALID_ARG, "storage must be FTLM_F64, FTLM_F32 or FTLM_F16");
   const uint64_t D = b.D;
   target = (int)std::min<uint64_t>((uint64_t)steps, D);
-  pad = padded_vectors(b);
-  rows = pad ? b.D_pad : D;
+  const int64_t elem = storage == FTLM_F64 ? 8 : storage == FTLM_F32 ? 4 : 2;
+  vl = run_layout(b, (int64_t)R * elem);
+  rows = vec_rows(b, vl);
   // FP16: elements of a unit vector are ~ 1/sqrt(rows); scale them to ~1
   sigma = 1.0;
   if (storage == FTLM_F16 && rows > 1) sigma = std::ldexp(1.0, (int)std::floor(0.5 * std::log2((double)rows)));
   TB = R * (256 / R);
   nb_vec = (int)blocks_for(std::max<uint64_t>(rows, 1), TB / R);
   // one lane layout for the whole run (the partial-sum buffer is sized for it)
-  gl = hv_layout_lanes(b, R, storage, pad, true);
+  gl = hv_layout_lanes(b, R, storage, vl, true);
   ng_hv = D ? hv_partial_groups(b, R, gl) : 1;
 }
 
 size_t LanczosRun::estimate_bytes(const Block& b, int R, int steps, int storage) {
   const size_t elem = storage == FTLM_F64 ? 8 : storage == FTLM_F32 ? 4 : 2;
-  const uint64_t rows = std::max(b.D, b.lanczos_layout == FTLM_LAYOUT_BLOCK ? b.D : b.D_pad);
+  // packed rows add at most a third of the padded rows (p >= 2 representatives per line)
+  const uint64_t rows = std::max(b.D, b.lanczos_layout == FTLM_LAYOUT_BLOCK ? b.D : b.D_pad + b.D_pad / 2);
   return 2 * (size_t)rows * R * elem + (size_t)8192 * R * 8 + (size_t)R * steps * 16 + (size_t)R * 128;
 }
 
@@ -425,6 +477,133 @@ void LanczosRun::download(hipStream_t st, double* alpha, double* beta, int32_t* 
   FTLM_HIP(hipMemcpyAsync(nsteps, d_n.p, (size_t)R * sizeof(int32_t), hipMemcpyDeviceToHost, st));
 }
 
+namespace {
+
+// Checkpoint file: a fixed header, then the per-chain states, alpha and beta
+// (R x steps), and the two stored vectors q0 and q1 (rows x R each).
+constexpr char kRunMagic[8] = {'F', 'T', 'L', 'M', 'R', 'U', 'N', '1'};
+struct RunFileHeader {
+  char magic[8];
+  uint32_t version, header_bytes;
+  uint64_t cluster_hash;
+  int32_t two_M, irrep, row, dg;
+  uint64_t D, rows;
+  int32_t layout, R, steps, storage, dist, target, next_step, first_chain;
+  int32_t chain_bytes, rpl;
+  uint64_t seed;
+  double sigma;
+  uint64_t vec_bytes;
+};
+
+constexpr size_t kStageBytes = 64ull << 20;
+
+struct File {
+  FILE* f = nullptr;
+  File(const char* path, const char* mode) : f(std::fopen(path, mode)) {
+    if (!f) fail(FTLM_ERR_INVALID_ARG, std::string("cannot open ") + path);
+  }
+  ~File() {
+    if (f) std::fclose(f);
+  }
+};
+
+struct Pinned {
+  void* p = nullptr;
+  explicit Pinned(size_t n) { FTLM_HIP(hipHostMalloc(&p, n, hipHostMallocDefault)); }
+  ~Pinned() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+// device -> file and file -> device through a pinned staging buffer
+void dev_to_file(FILE* f, const void* dev, size_t bytes, hipStream_t st, Pinned& stage) {
+  for (size_t o = 0; o < bytes; o += kStageBytes) {
+    const size_t n = std::min(kStageBytes, bytes - o);
+    FTLM_HIP(hipMemcpyAsync(stage.p, (const uint8_t*)dev + o, n, hipMemcpyDeviceToHost, st));
+    FTLM_HIP(hipStreamSynchronize(st));
+    if (std::fwrite(stage.p, 1, n, f) != n) fail(FTLM_ERR_INVALID_ARG, "checkpoint write failed");
+  }
+}
+
+void file_to_dev(FILE* f, void* dev, size_t bytes, hipStream_t st, Pinned& stage) {
+  for (size_t o = 0; o < bytes; o += kStageBytes) {
+    const size_t n = std::min(kStageBytes, bytes - o);
+    FTLM_HIP(hipStreamSynchronize(st));  // the previous chunk has left the staging buffer
+    if (std::fread(stage.p, 1, n, f) != n) fail(FTLM_ERR_INVALID_ARG, "checkpoint file is truncated");
+    FTLM_HIP(hipMemcpyAsync((uint8_t*)dev + o, stage.p, n, hipMemcpyHostToDevice, st));
+  }
+  FTLM_HIP(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
+void LanczosRun::save(const char* path, hipStream_t st, int next_step) const {
+  if (!path) fail(FTLM_ERR_INVALID_ARG, "null path");
+  FTLM_HIP(hipStreamSynchronize(st));
+  RunFileHeader h{};
+  std::memcpy(h.magic, kRunMagic, 8);
+  h.version = 1;
+  h.header_bytes = sizeof(RunFileHeader);
+  h.cluster_hash = block->sec->cluster_hash;
+  h.two_M = block->sec->two_M;
+  h.irrep = block->irrep;
+  h.row = block->row;
+  h.dg = block->dg;
+  h.D = block->D;
+  h.rows = rows;
+  h.layout = vl.kind();
+  h.rpl = (int32_t)vl.rpl;
+  h.R = R;
+  h.steps = steps;
+  h.storage = storage;
+  h.dist = dist;
+  h.target = target;
+  h.next_step = next_step;
+  h.first_chain = first_chain;
+  h.chain_bytes = (int32_t)sizeof(Chain);
+  h.seed = seed;
+  h.sigma = sigma;
+  h.vec_bytes = q0.bytes();
+  File f(path, "wb");
+  if (std::fwrite(&h, sizeof(h), 1, f.f) != 1) fail(FTLM_ERR_INVALID_ARG, "checkpoint write failed");
+  Pinned stage(kStageBytes);
+  dev_to_file(f.f, chain.p, chain.bytes(), st, stage);
+  dev_to_file(f.f, d_alpha.p, d_alpha.bytes(), st, stage);
+  dev_to_file(f.f, d_beta.p, d_beta.bytes(), st, stage);
+  dev_to_file(f.f, q0.p, q0.bytes(), st, stage);
+  dev_to_file(f.f, q1.p, q1.bytes(), st, stage);
+}
+
+std::unique_ptr<LanczosRun> LanczosRun::load(const Block& b, const char* path, hipStream_t st, int& next_step) {
+  if (!path) fail(FTLM_ERR_INVALID_ARG, "null path");
+  File f(path, "rb");
+  RunFileHeader h{};
+  if (std::fread(&h, sizeof(h), 1, f.f) != 1 || std::memcmp(h.magic, kRunMagic, 8) != 0 || h.version != 1 ||
+      h.header_bytes != sizeof(RunFileHeader) || h.chain_bytes != (int32_t)sizeof(Chain))
+    fail(FTLM_ERR_INVALID_ARG, std::string(path) + " is not a Lanczos checkpoint of this library");
+  if (h.cluster_hash != b.sec->cluster_hash || h.two_M != b.sec->two_M || h.irrep != b.irrep || h.row != b.row ||
+      h.dg != b.dg || h.D != b.D)
+    fail(FTLM_ERR_INVALID_ARG, "the checkpoint belongs to another block");
+  auto L = std::make_unique<LanczosRun>(b, h.R, h.steps, h.seed, h.storage, h.dist);
+  L->first_chain = h.first_chain;
+  if (L->rows != h.rows || L->vl.kind() != h.layout || (int32_t)L->vl.rpl != h.rpl || L->target != h.target ||
+      L->sigma != h.sigma)
+    fail(FTLM_ERR_INVALID_ARG, "the checkpoint's row layout differs from this block's");
+  L->allocate();
+  if (L->q0.bytes() != h.vec_bytes) fail(FTLM_ERR_INVALID_ARG, "checkpoint vector size mismatch");
+  Pinned stage(kStageBytes);
+  file_to_dev(f.f, L->chain.p, L->chain.bytes(), st, stage);
+  file_to_dev(f.f, L->d_alpha.p, L->d_alpha.bytes(), st, stage);
+  file_to_dev(f.f, L->d_beta.p, L->d_beta.bytes(), st, stage);
+  file_to_dev(f.f, L->q0.p, L->q0.bytes(), st, stage);
+  file_to_dev(f.f, L->q1.p, L->q1.bytes(), st, stage);
+  // the H.V epilogue's coefficients follow from the chain states
+  hipLaunchKernelGGL(k_scal, dim3((L->R + 63) / 64), dim3(64), 0, st, (const Chain*)L->chain.p, L->R, L->scal.p);
+  FTLM_HIP(hipGetLastError());
+  next_step = h.next_step;
+  return L;
+}
+
 void run_lanczos(Block& b, int R, int steps, uint64_t seed, int storage, int dist, double* alpha, double* beta,
                  int32_t* nsteps, hipStream_t st, ftlm_run_info* info) {
   if (!alpha || !beta || !nsteps) fail(FTLM_ERR_INVALID_ARG, "null output");
@@ -436,7 +615,7 @@ void run_lanczos(Block& b, int R, int steps, uint64_t seed, int storage, int dis
   L.download(st, alpha, beta, nsteps);
   FTLM_HIP(hipStreamSynchronize(st));
   if (info) {
-    info->layout = L.pad ? FTLM_LAYOUT_PADDED : FTLM_LAYOUT_BLOCK;
+    info->layout = L.vl.kind();
     info->rows = L.rows;
     info->hv_launches = L.target;
     info->hv_ms = L.hv_ms();

@@ -53,11 +53,11 @@ void launch_shape(const Shape& sh, const void* jobs, int n, size_t shm, hipStrea
 bool wg_supported(const Block& b, int R, int storage) {
   if (R < 1 || R > kWgMaxR || b.D == 0 || b.sec->n_reps == 0) return false;
   if (storage != FTLM_F64 && storage != FTLM_F32) return false;
-  if (b.sec->hv_mode != FTLM_HV_ENTRIES || b.lanczos_layout == FTLM_LAYOUT_PADDED) return false;
+  if (b.sec->hv_mode != FTLM_HV_ENTRIES || (b.lanczos_layout == FTLM_LAYOUT_PADDED || b.lanczos_layout == FTLM_LAYOUT_PACKED)) return false;
   if (irrep_dim_bucket(b.dg) < 0) return false;
   LaunchCfg c{};
   HvArgs<double> a{};
-  hv_setup(b, R, R, wg_lanes(R), false, nullptr, c, a);
+  hv_setup(b, R, R, wg_lanes(R), VecLayout{}, nullptr, c, a);
   return c.slds && a.tile_w >= R && c.vpl <= 4;
 }
 
@@ -84,9 +84,9 @@ WgBatch::WgBatch(std::vector<WgTask> t, hipStream_t st_) : tasks(std::move(t)), 
     const WgTask& k = tasks[i];
     const Block& b = *k.block;
     if (k.storage == FTLM_F64)
-      hv_setup(b, k.R, k.R, wg_lanes(k.R), false, nullptr, cfg[i], a64[i]);
+      hv_setup(b, k.R, k.R, wg_lanes(k.R), VecLayout{}, nullptr, cfg[i], a64[i]);
     else
-      hv_setup(b, k.R, k.R, wg_lanes(k.R), false, nullptr, cfg[i], a32[i]);
+      hv_setup(b, k.R, k.R, wg_lanes(k.R), VecLayout{}, nullptr, cfg[i], a32[i]);
     shape[i] = Shape{k.storage, b.dgp, cfg[i].vpl, b.sec->wide};
     groups[shape[i]].push_back(i);
   }

@@ -18,6 +18,7 @@
 #include "device.h"
 #include "dispatch.h"
 #include "internal.h"
+#include "tune_cache.h"
 
 namespace ftlm {
 
@@ -446,6 +447,15 @@ std::shared_ptr<Sector> build_sector(const ftlm_cluster* cl, std::shared_ptr<con
       if (it == bondmap.end() || std::fabs(it->second - kv.second) > 1e-12 * std::max(1.0, std::fabs(kv.second)))
         fail(FTLM_ERR_BONDS_NOT_INVARIANT, "bond list is not invariant under the group");
     }
+  }
+  {
+    uint64_t h = fnv1a(&s.N, sizeof(s.N));
+    h = fnv1a(&s.two_s, sizeof(s.two_s), h);
+    h = fnv1a(s.bonds.data(), s.bonds.size() * sizeof(int32_t), h);
+    h = fnv1a(s.J.data(), s.J.size() * sizeof(double), h);
+    h = fnv1a(G->perms.data(), G->perms.size() * sizeof(int32_t), h);
+    const int zf = s.zflip ? 1 : 0;
+    s.cluster_hash = fnv1a(&zf, sizeof(zf), h);
   }
   // digit-sum counts
   const int Amax = s.N * (s.d - 1);

@@ -163,3 +163,82 @@ def test_empty_block_zeroes_dots():
     scale = torch.ones((2, 2), dtype=torch.float64, device="cuda")
     LB.apply_H_ex(X, torch.zeros_like(X), layout=P.LAYOUT_BLOCK, scale=scale, dots=dots)
     assert np.array_equal(dots.cpu().numpy(), [0.0, 0.0])
+
+
+def _packed_rows(n_reps, d, row_bytes):
+    """The packed layout as the ABI documents it: rows of representative i and
+    the total row count (p = (128 / row_bytes) // d per 128-byte line when
+    2 <= p and p d < 128 / row_bytes, else d rows per representative)."""
+    L = 128 // row_bytes if 128 % row_bytes == 0 else 0
+    p = L // d if L else 0
+    if p >= 2 and p * d < L:
+        start = (np.arange(n_reps) // p) * L + (np.arange(n_reps) % p) * d
+        return start, -(-n_reps // p) * L, True
+    return np.arange(n_reps) * d, n_reps * d, False
+
+
+def _to_layout(B, X, start, rows):
+    Xp = np.zeros((rows, X.shape[1]), dtype=X.dtype)
+    for i in np.nonzero(B.n_rep)[0]:
+        o, n = int(B.offsets[i]), int(B.n_rep[i])
+        Xp[start[i]:start[i] + n] = X[o:o + n]
+    return Xp
+
+
+@pytest.mark.parametrize("bucket", range(6))
+def test_packed_layout_against_oracle(bucket):
+    """The packed row layout (no representative straddles a 128-byte line),
+    for every dimension bucket and row sizes of 4, 8 and 16 bytes: every
+    output row equals the oracle's, and the rows between representatives and
+    the padding rows are not written."""
+    name, two_s, two_M, gi = BUCKETS[bucket]
+    B, H, LB, keep = _blocks(name, two_s, two_M, gi)
+    rng = np.random.default_rng(300 + bucket)
+    d = B.irrep.dim
+    n_reps = len(B.sec.reps)
+    seen_packed = False
+    for nvec, dt in ((1, P.F32), (2, P.F32), (4, P.F32), (1, P.F64), (2, P.F64), (2, P.F16), (8, P.F16)):
+        elem = {P.F64: 8, P.F32: 4, P.F16: 2}[dt]
+        start, rows, packed = _packed_rows(n_reps, d, nvec * elem)
+        seen_packed |= packed
+        X = rng.uniform(-1, 1, (B.D, nvec)).astype(NP[dt])
+        Xp = torch.from_numpy(_to_layout(B, X, start, rows)).cuda()
+        Y, info = LB.apply_H_ex(Xp, layout=P.LAYOUT_PACKED)
+        Yh = Y.cpu().numpy()
+        ref = hv.apply(B, H, X.astype(np.float64))
+        got = np.concatenate([Yh[start[i]:start[i] + int(B.n_rep[i])] for i in np.nonzero(B.n_rep)[0]])
+        assert rel_err_cols(got.astype(np.float64), ref) <= TOL[dt], (nvec, dt)
+        written = np.zeros(rows, dtype=bool)
+        for i in np.nonzero(B.n_rep)[0]:
+            written[start[i]:start[i] + int(B.n_rep[i])] = True
+        assert not np.any(Yh[~written]), (nvec, dt)
+    # d = 1, 2, 4 divide every power-of-two line, where packing is the padded layout itself
+    assert seen_packed or d in (1, 2, 4)
+
+
+def test_packed_lanczos_and_kpm_match_block_rows():
+    """Lanczos chains and KPM moments in the packed layout (one FP64 chain: 8-byte rows,
+    3 representatives of d = 5 to a 16-row line) equal those in block rows up to
+    the order of the FP64 reductions; two FP32 chains the same to FP32 rounding."""
+    name, two_s, two_M, gi = "dodecahedron", 1, 0, 8
+    _, _, irs = oracle_group(name)
+    B, H, LB, keep = _blocks(name, two_s, two_M, gi)
+    S = LB.sector
+    LK = P.Block(S, gi, 0, user_rho=irs[gi].rho, layout=P.LAYOUT_PACKED)
+    LBl = P.Block(S, gi, 0, user_rho=irs[gi].rho, layout=P.LAYOUT_BLOCK)
+    n_reps = len(B.sec.reps)
+    a, b, n, info = LK.ftlm(1, 40, 5, storage=P.F64, info=True)
+    assert info["layout"] == P.LAYOUT_PACKED and info["rows"] == -(-n_reps // 3) * 16
+    a1, b1, n1 = LBl.ftlm(1, 40, 5, storage=P.F64)
+    assert np.max(np.abs(a[:, :15] - a1[:, :15])) < 1e-12 * np.max(np.abs(a1))
+    assert np.max(np.abs(b[:, :15] - b1[:, :15])) < 1e-12 * np.max(np.abs(b1))
+    a, b, n, info = LK.ftlm(2, 30, 6, storage=P.F32, info=True)
+    assert info["layout"] == P.LAYOUT_PACKED and info["rows"] == -(-n_reps // 3) * 16
+    a1, b1, n1 = LBl.ftlm(2, 30, 6, storage=P.F32)
+    assert np.max(np.abs(a[:, :15] - a1[:, :15])) < 1e-6 * np.max(np.abs(a1))
+    # R = 3 FP64: 24-byte rows do not divide a line: plain padded rows
+    _, _, _, info = LK.ftlm(3, 10, 6, storage=P.F64, info=True)
+    assert info["layout"] == P.LAYOUT_PADDED
+    m = LK.kpm(1, 41, 9, 0.5, 20.0)
+    m1 = LBl.kpm(1, 41, 9, 0.5, 20.0)
+    assert np.max(np.abs(m - m1)) < 1e-12

@@ -143,6 +143,8 @@ def test_m0_block_dimension_and_lowest_ritz_value_s32(dodeca32, gi):
     chain of 60 Lanczos steps in FP32 storage, whose lowest Ritz value is kept
     for the ground-state pin below."""
     cl, G, irs, S = dodeca32
+    gc.collect()
+    torch.cuda.empty_cache()     # the run's vectors are allocated by the library, not by torch
     ir = irs[gi]
     inv = next(k for k, p in enumerate(G.perms) if np.array_equal(p, cl.gens[2]))
     par = int(round(ir.chars[inv].real / ir.dim))

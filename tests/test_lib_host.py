@@ -215,3 +215,34 @@ def test_kpm_observables_match_oracle():
             assert np.allclose(a, b, rtol=1e-11, atol=1e-12)
     with pytest.raises(P.FtlmError):
         P.kpm_observables(blocks_l, np.array([-1.0]))
+
+
+def test_autotune_cache_file_roundtrip(tmp_path):
+    """The autotuner cache's file form: entries of one architecture are taken
+    in, others skipped; what is saved reads back; clear empties the cache;
+    malformed lines are refused."""
+    P.autotune_clear()
+    f = tmp_path / "tune.txt"
+    f.write_text("# arch cluster N two_s G dgp nvec dtype mode pad epi lanes\n"
+                 "gfx950:sramecc+:xnack- 123 30 1 120 5 24 1 1 1 1 8\n"
+                 "gfx950:sramecc+:xnack- 123 30 1 120 5 24 1 1 0 0 16\n"
+                 "gfx942:sramecc+:xnack- 123 30 1 120 5 24 1 1 1 1 4\n")
+    assert P.autotune_load(f, "gfx950:sramecc+:xnack-") == 2
+    g = tmp_path / "out.txt"
+    assert P.autotune_save(g) == 2
+    lines = sorted(g.read_text().split("\n")[:-1])
+    assert lines == sorted(f.read_text().split("\n")[1:3])
+    assert P.autotune_save(g, "gfx942:sramecc+:xnack-") == 0
+    assert P.autotune_load(f) == 3
+    assert P.autotune_save(g) == 3
+    P.autotune_clear()
+    assert P.autotune_save(g) == 0 and g.read_text() == ""
+    bad = tmp_path / "bad.txt"
+    bad.write_text("gfx950 1 2 3\n")
+    with pytest.raises(P.FtlmError, match="INVALID_ARG"):
+        P.autotune_load(bad)
+    bad.write_text("gfx950 123 30 1 120 5 24 1 1 1 1 3\n")
+    with pytest.raises(P.FtlmError, match="INVALID_ARG"):
+        P.autotune_load(bad)
+    with pytest.raises(P.FtlmError, match="INVALID_ARG"):
+        P.autotune_load(tmp_path / "missing.txt")
