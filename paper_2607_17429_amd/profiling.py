@@ -47,9 +47,13 @@ def kernel_stats_markdown(stats_csv: str, top: int = 14) -> str:
     return "\n".join(out)
 
 
-def lanczos_hv(trace_csv: str):
+def lanczos_hv(trace_csv: str, first: int = 0, match: str = ""):
     """(count, avg ms, kernel name) of the H.V dispatches made by ftlm_run: those
-    that the Lanczos alpha reduction follows on the same queue."""
+    that the Lanczos alpha reduction follows on the same queue.  With match only
+    kernels whose name contains it count.  With first > 0 only the first
+    `first` such launches (in time order) of the most frequent remaining H.V
+    kernel count: with the blocks of a job run in irrep order, the run of the
+    roofline block when the blocks before it take other kernel shapes."""
     rows = list(csv.DictReader(open(trace_csv)))
     rows.sort(key=lambda r: int(r["Start_Timestamp"]))
     by_q = {}
@@ -58,10 +62,16 @@ def lanczos_hv(trace_csv: str):
     picked = []
     for q in by_q.values():
         for a, b in zip(q, q[1:]):
-            if "k_hv<" in a["Kernel_Name"] and "k_alpha" in b["Kernel_Name"]:
+            if "k_hv<" in a["Kernel_Name"] and "k_alpha" in b["Kernel_Name"] and match in a["Kernel_Name"]:
                 picked.append(a)
     if not picked:
         return 0, None, None
+    if first:
+        names = {}
+        for r in picked:
+            names[r["Kernel_Name"]] = names.get(r["Kernel_Name"], 0) + 1
+        top = max(names, key=names.get)
+        picked = sorted((r for r in picked if r["Kernel_Name"] == top), key=lambda r: int(r["Start_Timestamp"]))[:first]
     ms = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in picked) / len(picked) / 1e6
     return len(picked), ms, picked[0]["Kernel_Name"]
 
@@ -101,6 +111,13 @@ def main():
     ap.add_argument("--cmd", default="")
     ap.add_argument("--bench-json", default=None, help="bench.py output line, for the algorithmic bytes")
     ap.add_argument("--trace", default=None, help="kernel_trace.csv of the trace run (H.V launches inside ftlm_run)")
+    ap.add_argument("--first", type=int, default=0,
+                    help="count only the first N in-run launches of the most frequent H.V kernel (the roofline block)")
+    ap.add_argument("--hv-json", default=None,
+                    help="stdout of the counter run (bench.py --profile-hv), for the gather-efficiency figures")
+    ap.add_argument("--match", default="", help="count only H.V kernels whose name contains this")
+    ap.add_argument("--step-cmd", default="bench.py --steps 1 --warmup 0 --no-cpu-baseline",
+                    help="the bench command of the trace run, for the summary's heading")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
     tr = counter_traffic(args.fetch, args.write)
@@ -115,13 +132,20 @@ def main():
         json.dump(rec, f, indent=1)
     md = [f"# k_hv on {args.workload}: rocprofv3 summary", "",
           "Commands (from the repository root):", "", "```", args.cmd, "```", "",
-          "## Kernel trace statistics (one bench step, `bench.py --steps 1 --warmup 0 --no-cpu-baseline`)", "",
+          f"## Kernel trace statistics (one bench step, `{args.step_cmd}`)", "",
           kernel_stats_markdown(args.stats), ""]
     if args.trace:
-        n, ms, name = lanczos_hv(args.trace)
+        n, ms, name = lanczos_hv(args.trace, args.first, args.match)
         if n:
-            md += [f"H.V launches inside `ftlm_run` (each followed by `k_alpha` on its queue): {n}, "
+            which = (f"the first {n} of the most frequent H.V kernel"
+                     + (f" whose name contains `{args.match}`" if args.match else "")
+                     + ", i.e. the roofline block's run" if args.first else f"{n}")
+            md += [f"H.V launches inside `ftlm_run` (each followed by `k_alpha` on its queue): {which}, "
                    f"average {ms:.3f} ms (`{name[:90]}`).", ""]
+            if args.bench_json:
+                bj = json.loads(open(args.bench_json).read().strip().splitlines()[-1])
+                md += [f"The bench line of the same run (HIP events on the launch stream): "
+                       f"{bj['roofline']['avg_launch_ms']:.3f} ms per launch over {bj['roofline']['launches']} launches.", ""]
     md += [
           "## HBM traffic of one H.V launch inside `ftlm_run` (`bench.py --profile-hv`)", "",
           "| counter | raw KiB / launch | calibration (1 GiB copy) raw KiB | scale | bytes / launch |",
@@ -134,6 +158,27 @@ def main():
     if balg:
         md += ["", f"Algorithmic bytes per launch (byte model): {balg / 1e9:.3f} GB; "
                    f"measured / algorithmic = {total / balg:.3f}."]
+    if args.hv_json:
+        hj = None
+        for line in open(args.hv_json):
+            if line.startswith('{"copy_bytes"'):
+                hj = json.loads(line)
+        if hj:
+            st = hj["stats"]
+            conn, act = st["connections"], st["active_connections"]
+            useful = st["gathered_rows"] * hj["nvec"] * hj["elem_bytes"]
+            fetch = tr["FETCH_SIZE"]["bytes_per_launch"]
+            rec["gather"] = dict(layout=hj["layout"], connections=conn, active_connections=act,
+                                 useful_slice_bytes=useful, fetch_bytes_per_connection=fetch / conn,
+                                 useful_bytes_per_active_connection=useful / max(act, 1),
+                                 gather_efficiency=useful / fetch)
+            with open(os.path.join(args.out, f"hv_traffic_{args.workload}.json"), "w") as f:
+                json.dump(rec, f, indent=1)
+            md += ["", f"Gather efficiency ({hj['layout']} rows, {hj['nvec']} vectors of {hj['elem_bytes']} B): "
+                       f"{conn:,} connections ({act:,} with an active target) per launch; the useful X slices "
+                       f"are {useful / 1e9:.3f} GB ({useful / max(act, 1):.1f} B per active connection); "
+                       f"FETCH_SIZE is {fetch / conn:.1f} B per connection; useful slice bytes / fetched bytes "
+                       f"= {useful / fetch:.3f}."]
     md += ["", f"Kernel source hash ({' + '.join(os.path.basename(p) for p in HV_SOURCES)}): `{rec['source_sha']}`", ""]
     with open(os.path.join(args.out, f"k_hv_{args.workload}.md"), "w") as f:
         f.write("\n".join(md))
