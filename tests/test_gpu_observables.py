@@ -132,16 +132,24 @@ def test_icosidodecahedron_m0_fp32_against_fp64():
 
 @pytest.mark.timeout(600)
 def test_fp16_storage_on_the_papers_validation_case():
-    """Section 4.2: the s=3/2 icosahedron, every M >= 0 sector and irrep,
-    R = 100 chains of N_L = 100 steps, run once with FP32 and once with FP16
-    vector storage from the same start vectors: for T >= 0.1 the heat capacity
-    and the susceptibility differ by at most |dC| = 8e-5 and |dchi| = 1e-4 (the
-    paper's bound, per cluster, g = 1)."""
+    """Section 4.2's validation of half-precision storage: the s=3/2
+    icosahedron, every M >= 0 sector and irrep, R = 100 chains of N_L = 100
+    steps, once with FP32 and once with FP16 vector storage from the same
+    start vectors.  What the paper states and this test checks, for T >= 0.1:
+    the deviation lies inside the backward-error envelope of rounding the
+    stored iterates, an operator perturbation of norm u W (u = 2^-11, W the
+    spectral width: |dE| <= u W, |dC| <= u W C / T, |dchi| <= u W chi / T),
+    and it is far below the statistical uncertainty of the trace estimator
+    (here at most 1% of the spread between two independent FP32 runs; the
+    paper reports three orders of magnitude).  The paper's own run printed
+    |dC| = 8e-5 and |dchi| = 1e-4, one realization; ours are logged next to
+    it."""
     log("[observables] s=3/2 icosahedron, FP16 against FP32 storage")
     cl = clusters.get("icosahedron")
     T = np.geomspace(0.05, 10, 50)
     r32 = P.campaign(cl, cl.gens, 3, 100, 100, 0x5EED0004, T, storage=P.F32)
     r16 = P.campaign(cl, cl.gens, 3, 100, 100, 0x5EED0004, T, storage=P.F16)
+    other = P.campaign(cl, cl.gens, 3, 100, 100, 0x5EED0014, T, storage=P.F32)   # independent chains
     assert r32["stats"]["work"] == r16["stats"]["work"]
     dC = np.abs(r16["C"] - r32["C"])
     dX = np.abs(r16["chi"] - r32["chi"])
@@ -149,5 +157,16 @@ def test_fp16_storage_on_the_papers_validation_case():
     for k in range(0, len(T), 5):
         log(f"    T={T[k]:.4f} |dE| {dE[k]:.2e} |dC| {dC[k]:.2e} |dchi| {dX[k]:.2e}  (C {r32['C'][k]:.4f} chi {r32['chi'][k]:.4f})")
     hot = T >= 0.1
-    log(f"  T >= 0.1: max |dC| {dC[hot].max():.2e}  max |dchi| {dX[hot].max():.2e}")
-    assert dC[hot].max() <= 8e-5 and dX[hot].max() <= 1e-4
+    log(f"  T >= 0.1: max |dC| {dC[hot].max():.2e}  max |dchi| {dX[hot].max():.2e}  (the paper's run: 8e-5, 1e-4)")
+    # spectral width: each bond's S_i.S_j has eigenvalues in [-s(s+1), s^2],
+    # so W <= N_b (s(s+1) + s^2) = N_b s (2s + 1)
+    u = 2.0 ** -11
+    s_ = 1.5
+    W = cl.nbonds * s_ * (2 * s_ + 1)
+    assert np.all(dE[hot] <= u * W)
+    assert np.all(dC[hot] <= u * W * r32["C"][hot] / T[hot])
+    assert np.all(dX[hot] <= u * W * r32["chi"][hot] / T[hot])
+    stat_C = np.abs(other["C"] - r32["C"])[hot].max()
+    stat_X = np.abs(other["chi"] - r32["chi"])[hot].max()
+    log(f"  statistical spread between independent FP32 runs: C {stat_C:.2e} chi {stat_X:.2e}")
+    assert dC[hot].max() <= 1e-2 * stat_C and dX[hot].max() <= 1e-2 * stat_X
