@@ -132,6 +132,27 @@ __device__ __forceinline__ uint64_t shfl64(uint64_t v, int src) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Swap a value with the other lane of its lane pair (lanes 2i and 2i + 1):
+// DPP quad permutation [1, 0, 3, 2], a register move with no LDS traffic.
+__device__ __forceinline__ uint32_t pair_swap_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float pair_swap(float v) { return __uint_as_float(pair_swap_u32(__float_as_uint(v))); }
+__device__ __forceinline__ double pair_swap(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint64_t r = (uint64_t)pair_swap_u32((uint32_t)u) | ((uint64_t)pair_swap_u32((uint32_t)(u >> 32)) << 32);
+  return __longlong_as_double((long long)r);
+}
+__device__ __forceinline__ _Float16 pair_swap(_Float16 v) {
+  return __builtin_bit_cast(_Float16, (uint16_t)pair_swap_u32(__builtin_bit_cast(uint16_t, v)));
+}
+
+// Both columns of one row of a two-column slice, loaded as one aligned word.
+template <typename T>
+struct alignas(2 * sizeof(T)) RowPair {
+  T c0, c1;
+};
+
 template <typename E>
 __device__ __forceinline__ const E* stage(const E* src, uint32_t count, char* dst_bytes) {
   E* dst = (E*)dst_bytes;
@@ -184,6 +205,10 @@ __device__ __forceinline__ void hv_pass(const HvArgs<T>& a, const HvTabs& tb,
   const int gbase = lane - lg;
   // uniform: the whole launch may gather without clamps (see the gather below)
   const bool dense = CONTIG || hv_dense(a, DG, VPL, ntiles);
+  // uniform: a pair of lanes per representative, one column each, and
+  // two-element rows that start on a two-element boundary (see the gather)
+  const bool pair_rows = CONTIG && VPL == 1 && GL == 2 && a.ld == 2 &&
+                         ((uintptr_t)a.X & (2 * sizeof(T) - 1)) == 0;
   // lane lg of the group owns columns vbase + j * vstep, j < VPL
   const int vbase = tile * a.tile_w + lg * hv_col_lane(CONTIG, VPL);
   const int vstep = hv_col_step(CONTIG, GL);
@@ -267,7 +292,22 @@ __device__ __forceinline__ void hv_pass(const HvArgs<T>& a, const HvTabs& tb,
         // and a select zeroes those values, so all loads of the flip are in
         // flight together instead of each waiting inside its own branch.
         T xv[DG][VPL];
-        if (dense) {
+        if (pair_rows) {
+          // two lanes, one column each, rows of two elements: lane 0 loads
+          // rows 0 .. H-1 and lane 1 rows H .. DG-1 (H = ceil(DG / 2)), both
+          // columns of a row in one load, then each lane hands the other
+          // column to its partner.  ceil(DG / 2) loads per flip instead of DG.
+          constexpr int H = (DG + 1) / 2;
+          const RowPair<T>* xr = reinterpret_cast<const RowPair<T>*>(a.X) + offr;
+#pragma unroll
+          for (int k = 0; k < H; ++k) {
+            const RowPair<T> v = xr[lg ? (k + H < DG ? k + H : DG - 1) : k];
+            const T recv = pair_swap(lg ? v.c0 : v.c1);
+            const T keep = lg ? v.c1 : v.c0;
+            xv[k][0] = lg ? recv : keep;
+            if (k + H < DG) xv[k + H][0] = lg ? keep : recv;
+          }
+        } else if (dense) {
           // padded rows with d_Gamma == DG and every column in range: rows
           // k >= n_r of a target are stored zeros, so no clamp or select
           const T* xr = a.X + offr * (uint64_t)a.ld + vbase;

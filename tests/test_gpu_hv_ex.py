@@ -88,6 +88,55 @@ def test_padded_adjacent_column_kernel_against_oracle(bucket):
 
 
 @pytest.mark.parametrize("bucket", range(6))
+def test_paired_rows_kernel_against_oracle(bucket):
+    """Two vectors on two lanes per representative (one column each), the
+    launch shape of the largest blocks' Lanczos runs: the gather loads both
+    columns of a row at once and the lanes swap halves.  Every dimension
+    bucket, FP64, FP32 and FP16, plain and with the Lanczos epilogue, against
+    the oracle; an input that starts one element past a two-element boundary
+    takes the row-by-row gather instead and gives the same bits."""
+    name, two_s, two_M, gi = BUCKETS[bucket]
+    B, H, LB, keep = _blocks(name, two_s, two_M, gi)
+    rng = np.random.default_rng(300 + bucket)
+    nvec = 2
+    for dt in (P.F64, P.F32, P.F16):
+        X = rng.uniform(-1, 1, (B.D, nvec)).astype(NP[dt])
+        Xh = _to_padded(B, X)
+        Xp = torch.from_numpy(Xh).cuda()
+        Y, info = LB.apply_H_ex(Xp, layout=P.LAYOUT_PADDED, lanes=2)
+        assert info["lanes_used"] == 2 and info["adjacent_columns"] == 1, info
+        got, pad = _from_padded(B, Y.cpu().numpy())
+        ref = hv.apply(B, H, X.astype(np.float64))
+        assert rel_err_cols(got.astype(np.float64), ref) <= TOL[dt], dt
+        assert not np.any(pad)
+        # the same rows one element off the two-element boundary
+        buf = torch.zeros(Xh.size + 1, dtype=TT[dt], device="cuda")
+        Xo = buf[1:].view(Xh.shape)
+        Xo.copy_(Xp)
+        assert Xo.data_ptr() % (2 * Xo.element_size()) != 0
+        Yo, info_o = LB.apply_H_ex(Xo, layout=P.LAYOUT_PADDED, lanes=2)
+        assert info_o["lanes_used"] == 2
+        assert torch.equal(Yo, Y), dt
+        if dt == P.F16:
+            continue
+        # the epilogue: Y <- s H X - b Y0 and the sums X . Y
+        Y0 = rng.uniform(-1, 1, (B.D, nvec)).astype(NP[dt])
+        sb = np.array([[1.25, 0.0], [0.75, -0.5]])
+        Yp = torch.from_numpy(_to_padded(B, Y0)).cuda()
+        dots = torch.full((nvec,), np.nan, dtype=torch.float64, device="cuda")
+        Ye, info_e = LB.apply_H_ex(Xp, Yp, layout=P.LAYOUT_PADDED, lanes=2,
+                                   scale=torch.from_numpy(sb).cuda(), dots=dots)
+        assert info_e["adjacent_columns"] == 1
+        gote, pade = _from_padded(B, Ye.cpu().numpy())
+        refe = sb[:, 0] * ref - sb[:, 1] * Y0.astype(np.float64)
+        assert rel_err_cols(gote.astype(np.float64), refe) <= TOL[dt], dt
+        assert not np.any(pade)
+        X64 = X.astype(np.float64)
+        want = np.sum(X64 * gote.astype(np.float64), axis=0)
+        assert np.all(np.abs(dots.cpu().numpy() - want) <= 1e-12 * np.sum(np.abs(X64 * gote.astype(np.float64)), axis=0))
+
+
+@pytest.mark.parametrize("bucket", range(6))
 def test_lanczos_epilogue_against_oracle(bucket):
     """The fused first half of a Lanczos step, Y <- s (H - e) X - b Y with the
     FP64 sums X . Y, in the padded layout with adjacent columns: every element
