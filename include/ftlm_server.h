@@ -10,11 +10,13 @@
  * overtake one that does not, until that one has been overtaken 64 times and
  * then holds back the queue behind it (nothing behind it is admitted until it
  * is).  Small jobs (sectors of a few hundred representatives, R <= 32, FP64
- * or FP32 storage) admitted in the same pass over the queue run together as
- * one batch of the fused small-block kernel (ftlm_run_fused: one launch per
- * kernel shape, one workgroup per job, up to 64 jobs), which takes one slot;
- * a small job admitted alone runs the per-step kernels, which are faster for
- * one job.  Sector tables are built with the entry table (FTLM_HV_ENTRIES),
+ * or FP32 storage) admitted in the same pass over the queue, while no job
+ * with long steps (about 1 ms or more of estimated device time) is running,
+ * run together as one batch of the fused small-block kernel
+ * (ftlm_run_fused: one launch per kernel shape, one workgroup per job, up to
+ * 64 jobs), which takes one slot; a small job admitted alone, or next to a
+ * long-step job, runs the per-step kernels, which are faster for one job and
+ * interleave with long launches.  Sector tables are built with the entry table (FTLM_HV_ENTRIES),
  * whose size the admission estimate counts.  A job whose estimate alone exceeds
  * hbm_budget_bytes ends with FTLM_ERR_OUT_OF_MEMORY.  Sector tables are cached and shared by all
  * jobs with the same (cluster, generators, 2M); unused ones are evicted when

@@ -73,6 +73,7 @@ struct Job {
   double* h_beta = nullptr;
   int32_t* h_n = nullptr;
   int overtaken = 0;
+  bool heavy = false;  // a per-step job with an estimated step of at least kHeavyStepSeconds
   // incremental enqueue: steps [0, next_step) are on the stream, at most two
   // chunks of `chunk` steps are in flight, each followed by an event
   int next_step = 0, chunk = 1;
@@ -87,6 +88,12 @@ constexpr int kMaxOvertake = 64;
 constexpr size_t kMaxBatchJobs = 64;  // jobs of one fused batch
 constexpr double kChunkSeconds = 0.01;
 constexpr double kHbmBytesPerSecond = 4.0e12;  // sustained gather rate assumed for chunk sizing
+// Small jobs are batched into the fused kernel only while no job with steps
+// this long runs: its H.V launches fill every compute unit, and the fused
+// kernel's one long workgroup per job then waits behind them (measured on the
+// serving mix: median latency 110 ms batched against 23 ms with per-step
+// kernels, at the same throughput), while short per-step kernels interleave.
+constexpr double kHeavyStepSeconds = 1e-3;
 
 std::string key_of(const void* p, size_t n) { return std::string((const char*)p, n); }
 
@@ -172,6 +179,7 @@ struct Server {
   std::vector<std::shared_ptr<Job>> running;    // per-step jobs, one slot each
   std::vector<std::unique_ptr<FusedBatch>> batches;  // one slot each
   std::vector<std::shared_ptr<Job>> forming;    // small jobs admitted in this walk
+  int heavy_running = 0;                        // running jobs with Job::heavy
   // Streams, events and pinned result buffers are recycled: creating and
   // freeing them per job would add driver calls that can serialize the device.
   std::vector<std::pair<hipStream_t, hipEvent_t>> free_streams;
@@ -377,7 +385,7 @@ int Server::try_admit(const std::shared_ptr<Job>& j) {
   SecEntry& se = sit->second;
   // a small job under the automatic engine joins the batch of this walk
   // (no slot of its own once the batch has one)
-  const bool small = j->engine == FTLM_ENGINE_AUTO && j->R <= kWgMaxChains &&
+  const bool small = j->engine == FTLM_ENGINE_AUTO && heavy_running == 0 && j->R <= kWgMaxChains &&
                      (j->storage == FTLM_F64 || j->storage == FTLM_F32) &&
                      wg_rounds(se.sec->n_reps, j->R) <= kWgAutoMaxRounds;
   const bool room = forming.size() < kMaxBatchJobs;
@@ -483,6 +491,8 @@ void Server::start_steps(const std::shared_ptr<Job>& j) {
     const double step_bytes = (double)S.n_entries * (rows * j->R * elem + 8.0) + 6.0 * (double)j->D * j->R * elem;
     const double step_s = step_bytes / kHbmBytesPerSecond;
     j->chunk = (int)std::max(1.0, std::min((double)std::max(j->run->target, 1), kChunkSeconds / std::max(step_s, 1e-9)));
+    j->heavy = step_s >= kHeavyStepSeconds;
+    if (j->heavy) heavy_running++;
   }
   j->next_step = 0;
   j->enqueued_all = false;
@@ -490,10 +500,10 @@ void Server::start_steps(const std::shared_ptr<Job>& j) {
   running.push_back(j);
 }
 
-// The small jobs admitted in one walk: two or more run as one fused batch
-// (one launch per kernel shape), a lone job runs the per-step kernels, which
-// are faster for one job (measured on the serving mix: 0.7 ms against
-// 1.4 ms fused) unless it asked for the fused engine.
+// The small jobs admitted in one walk (only while no heavy job runs): two or
+// more run as one fused batch (one launch per kernel shape), a lone job runs
+// the per-step kernels, which are faster for one job (measured on the serving
+// mix: 0.7 ms against 1.4 ms fused) unless it asked for the fused engine.
 void Server::flush_forming() {
   if (forming.empty()) return;
   std::vector<std::shared_ptr<Job>> js;
@@ -632,6 +642,8 @@ void Server::retire(const std::shared_ptr<Job>& j, int status) {
   auto it = sectors.find(j->sector_key);
   if (j->holds_sector && it != sectors.end()) it->second.users--;
   j->holds_sector = false;
+  if (j->heavy) heavy_running--;
+  j->heavy = false;
   used -= j->footprint;
   j->footprint = 0;
   std::lock_guard<std::mutex> lk(mu);
