@@ -39,14 +39,19 @@ WORKLOADS = {
                                  desc="s=1/2 Heisenberg icosidodecahedron (N=30, 60 bonds), I_h, M=0 "
                                       "(D_M=155,117,520), all 10 irreps row 1 (blocks 1,291,834..6,465,762, "
                                       "41,364,764 rows); R=24 Gaussian chains per block, 60 Lanczos steps, FP32 "
-                                      "storage, FP64 reductions, eigensolve and thermal sums at 50 T"),
+                                      "storage, FP64 reductions, eigensolve and thermal sums at 50 T",
+                                 context=dict(paper="Section 4.3's workstation-scale example: the same ten-irrep "
+                                                    "M=0 sweep (as 20 Z2-parity blocks, 8 vectors per launch) in "
+                                                    "96.5 s end to end (the paper's workstation GPU is an RTX 4000 "
+                                                    "SFF Ada); another machine and a wall time, not a target",
+                                              paper_s=96.5, paper_elem_vec_per_s=41364764 * 24 * 60 / 96.5)),
     "icosidodecahedron_Hg": dict(cluster="icosidodecahedron", two_s=1, two_M=0, irrep=8, R=24, steps=60,
                                  dist="gaussian", storage="f32",
                                  desc="s=1/2 Heisenberg icosidodecahedron (N=30, 60 bonds), I_h, M=0, "
                                       "irrep H_g row 1 (D=6,465,762); R=24 Gaussian chains, 60 Lanczos steps, "
                                       "FP32 storage, FP64 reductions"),
     "dodecahedron_s32_Hg": dict(cluster="dodecahedron", two_s=3, two_M=0, irrep=8, R=2, steps=60,
-                                dist="rademacher", storage="f32", fp64_check=False,
+                                dist="rademacher", storage="f32", fp64_check=False, otf_timing=False,
                                 desc="s=3/2 Heisenberg dodecahedron (N=20, 30 bonds, 40-bit labels), I_h, M=0 "
                                      "(D_M=86,981,744,944), irrep H_g row 1 (D=3,624,380,734); R=2 Rademacher chains, "
                                      "60 Lanczos steps, FP32 storage, FP64 reductions"),
@@ -56,12 +61,12 @@ WORKLOADS = {
                                           "row 1 (D=6,465,762); R=24 Gaussian chains, 60 Lanczos steps, FP16 storage "
                                           "with a per-chain power-of-two scale, FP64 arithmetic and reductions"),
     "dodecahedron_s32_Hg_f16": dict(cluster="dodecahedron", two_s=3, two_M=0, irrep=8, R=2, steps=60,
-                                    dist="rademacher", storage="f16", fp64_check=False,
+                                    dist="rademacher", storage="f16", fp64_check=False, otf_timing=False,
                                     desc="s=3/2 Heisenberg dodecahedron (N=20, 30 bonds, 40-bit labels), I_h, M=0, "
                                          "irrep H_g row 1 (D=3,624,380,734); R=2 Rademacher chains, 60 Lanczos steps, "
                                          "FP16 storage with a per-chain power-of-two scale, FP64 arithmetic"),
     "dodecahedron_s32_Hg_flip": dict(cluster="dodecahedron", two_s=3, two_M=0, irrep=16, R=2, steps=60,
-                                     dist="rademacher", storage="f32", fp64_check=False, flip=True,
+                                     dist="rademacher", storage="f32", fp64_check=False, otf_timing=False, flip=True,
                                      desc="s=3/2 Heisenberg dodecahedron, M=0 resolved by G x Z2 (I_h x spin "
                                           "flip), irrep H_g^+ row 1 (D=1,812,277,727); R=2 Rademacher chains, 60 "
                                           "Lanczos steps, FP32 storage, FP64 reductions"),
@@ -75,6 +80,28 @@ WORKLOADS = {
                              desc="s=1/2 Heisenberg dodecahedron (N=20), I_h, all M >= 0 sectors, all irreps, row 1; "
                                   "R=24 Rademacher chains batched in one H.V launch per step, 60 Lanczos steps, "
                                   "FP64; E, C, chi at 50 T"),
+    "icosidodecahedron_all": dict(cluster="icosidodecahedron", two_s=1, R=24, steps=60, dist="gaussian",
+                                  storage="f32", campaign=True, chains_per_run=0, alt_paths=False,
+                                  cpu_baseline=False,
+                                  roofline_note="the blocks' H.V launches are those of the default workload "
+                                                "(its roofline line); no separate roofline for the campaign",
+                                  desc="s=1/2 Heisenberg icosidodecahedron (N=30), I_h, all M >= 0 sectors, all "
+                                       "10 irreps, row 1; R=24 Gaussian chains batched in one H.V launch per step, "
+                                       "60 Lanczos steps, FP32 storage, FP64 reductions; E, C, chi at 50 T",
+                                  context=dict(paper="Table 3: the same run (R=24, N_L=60, all M >= 0 sectors) in "
+                                                     "91.5 s FP32 and 81.1 s FP16 end to end on one B200, 433.4 s "
+                                                     "FP32 on the RTX 4000 SFF Ada workstation; other machines, "
+                                                     "not a target",
+                                               paper_b200_fp32_s=91.5, paper_b200_fp16_s=81.1,
+                                               paper_workstation_fp32_s=433.4)),
+    "icosidodecahedron_all_f16": dict(cluster="icosidodecahedron", two_s=1, R=24, steps=60, dist="gaussian",
+                                      storage="f16", campaign=True, chains_per_run=0, alt_paths=False,
+                                      cpu_baseline=False,
+                                      roofline_note="no separate roofline for the campaign",
+                                      desc="s=1/2 Heisenberg icosidodecahedron (N=30), I_h, all M >= 0 sectors, "
+                                           "all 10 irreps, row 1; R=24 Gaussian chains batched, 60 Lanczos steps, "
+                                           "FP16 storage with a per-chain power-of-two scale, FP64 arithmetic; "
+                                           "E, C, chi at 50 T"),
     "dodecahedron_Hg": dict(cluster="dodecahedron", two_s=1, two_M=0, irrep=8, R=24, steps=60, dist="rademacher",
                             storage="f64",
                             desc="s=1/2 dodecahedron (N=20), I_h, M=0, irrep H_g (D=7,800); R=24 Rademacher, "
@@ -359,17 +386,29 @@ def bench_campaign(P, np, wl, cl, args):
     recs = [run(0x5EED0001 + k, wl["chains_per_run"]) for k in range(args.steps)]
     wall = time.perf_counter() - t0
     work = sum(r["stats"]["work"] for r in recs)
-    other = 1 if wl["chains_per_run"] == 0 else 0          # the other path, for the speedup figure
-    t1 = time.perf_counter()
-    alt = run(0x5EED0001, other)
-    alt_s = time.perf_counter() - t1
     st = recs[0]["stats"]
-    # the same campaign with the per-step kernels only (no fused small-block kernel)
-    run(0x5EED0001, wl["chains_per_run"], P.ENGINE_STEPS)
-    t2 = time.perf_counter()
-    per_step = run(0x5EED0001, wl["chains_per_run"], P.ENGINE_STEPS)
-    per_step_s = time.perf_counter() - t2
-    cpu = None if args.no_cpu_baseline else oracle_campaign_rate(wl, args.cpu_seconds)
+    progress(f"campaign: {wall / args.steps:.3f} s per run")
+    engine_fields, single_fields = None, None
+    if wl.get("alt_paths", True):
+        other = 1 if wl["chains_per_run"] == 0 else 0          # the other path, for the speedup figure
+        t1 = time.perf_counter()
+        alt = run(0x5EED0001, other)
+        alt_s = time.perf_counter() - t1
+        # the same campaign with the per-step kernels only (no fused small-block kernel)
+        run(0x5EED0001, wl["chains_per_run"], P.ENGINE_STEPS)
+        t2 = time.perf_counter()
+        per_step = run(0x5EED0001, wl["chains_per_run"], P.ENGINE_STEPS)
+        per_step_s = time.perf_counter() - t2
+        engine_fields = {"name": args.engine, "fused_blocks": st["fused_blocks"],
+                         "per_step_engine_elem_vec_per_s": per_step["stats"]["work"] / per_step_s,
+                         "speedup_over_per_step_engine": (work / wall) / (per_step["stats"]["work"] / per_step_s)}
+        single_fields = {"this_path": "single-vector" if wl["chains_per_run"] == 1 else "batched",
+                         "other_path_elem_vec_per_s": alt["stats"]["work"] / alt_s,
+                         "speedup_batched_over_single":
+                             (work / wall) / (alt["stats"]["work"] / alt_s) if other == 1
+                             else (alt["stats"]["work"] / alt_s) / (work / wall)}
+    cpu = None if args.no_cpu_baseline or not wl.get("cpu_baseline", True) else \
+        oracle_campaign_rate(wl, args.cpu_seconds)
     return {
         "metric": "FTLM campaign basis-elems x vecs/s (all M >= 0 sectors and irreps, thermal sums)",
         "value": work / wall, "unit": "basis-elems*vecs/s", "n_gpus": 1, "steps": args.steps,
@@ -379,17 +418,13 @@ def bench_campaign(P, np, wl, cl, args):
         "config": {"workload": wl["desc"], "sectors": st["sectors"], "blocks": st["blocks"], "rows": st["rows"],
                    "R": wl["R"], "lanczos_steps": wl["steps"], "parallelism": "single GPU"},
         "roofline": None,
-        "roofline_note": "every block is cache-resident (largest few MB), so an HBM roofline does not bound it",
+        "roofline_note": wl.get("roofline_note", "every block is cache-resident (largest few MB), so an HBM "
+                                                 "roofline does not bound it"),
         "cpu_baseline": cpu,
+        "context": dict(wl["context"], this_run_s=wall / args.steps) if "context" in wl else None,
         "breakdown_s": {k: st[k] for k in ("seconds_build", "seconds_lanczos", "seconds_thermo", "seconds_total")},
-        "engine": {"name": args.engine, "fused_blocks": st["fused_blocks"],
-                   "per_step_engine_elem_vec_per_s": per_step["stats"]["work"] / per_step_s,
-                   "speedup_over_per_step_engine": (work / wall) / (per_step["stats"]["work"] / per_step_s)},
-        "single_vs_batched": {"this_path": "single-vector" if wl["chains_per_run"] == 1 else "batched",
-                              "other_path_elem_vec_per_s": alt["stats"]["work"] / alt_s,
-                              "speedup_batched_over_single":
-                                  (work / wall) / (alt["stats"]["work"] / alt_s) if other == 1
-                                  else (alt["stats"]["work"] / alt_s) / (work / wall)},
+        "engine": engine_fields,
+        "single_vs_batched": single_fields,
         "E_T0.05": float(recs[0]["E"][0]), "E_T10": float(recs[0]["E"][-1]),
     }
 
@@ -607,9 +642,28 @@ def main():
     torch.cuda.synchronize()
     hv1_ms = ev0.elapsed_time(ev1) / 5
     del X1, Y1
+    # the on-the-fly H.V (flips canonicalised and looked up inside the kernel,
+    # no entry table) on the same block, nvec = R, block rows
+    otf = None
+    if wl.get("otf_timing", True):
+        So = P.Sector(cl, G, wl["two_M"], hv_mode=P.HV_ONTHEFLY, two_s=wl["two_s"], spin_flip=wl.get("flip", False))
+        Bo = P.Block(So, rirrep, 0)
+        Xo = torch.randn((Bo.D, wl["R"]), dtype=tdt, device=dev)
+        Yo = torch.empty_like(Xo)
+        Bo.apply_H(Xo, Yo, stream=stream)
+        ev0.record(stream)
+        for _ in range(3):
+            Bo.apply_H(Xo, Yo, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        otf_ms = ev0.elapsed_time(ev1) / 3
+        otf = {"ms": otf_ms, "elem_vec_per_s": Bo.D * wl["R"] / (otf_ms * 1e-3), "vs_entries": otf_ms / hv_ms,
+               "sector_device_bytes": So.device_bytes}
+        del Xo, Yo, Bo, So
     torch.cuda.empty_cache()        # the library allocates the runs below itself
 
-    progress(f"H.V alone: {hv_ms:.3f} ms (nvec {wl['R']}), single FP64 {hv1_ms:.3f} ms")
+    progress(f"H.V alone: {hv_ms:.3f} ms (nvec {wl['R']}), single FP64 {hv1_ms:.3f} ms"
+             + (f", on the fly {otf['ms']:.3f} ms" if otf else ""))
     # the second workload on the same H.V: KPM moments (2 per product) for the
     # same R start vectors, window from the Ritz values widened by 5%
     kpm = None
@@ -691,13 +745,15 @@ def main():
                      "algorithmic_bytes_per_launch": balg, "avg_launch_ms": lz_hv_ms, "launches": lz_launches,
                      "nvec": wl["R"]},
         "cpu_baseline": cpu,
+        "context": dict(wl["context"], this_job_s=float(np.mean([r["total"] for r in recs]))) if "context" in wl else None,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "of": "whole jobs of this workload (the timed steps)"},
         "breakdown_ms": {k: float(np.mean([r[k] for r in recs]) * 1e3) for k in ("build", "lanczos", "thermo")},
         "hv": {"apply_H_ms": hv_ms, "apply_H_GBs": balg_apply / (hv_ms * 1e-3) / 1e9,
                "batched_elem_vec_per_s": hv_D * wl["R"] / (hv_ms * 1e-3),
                "single_fp64_elem_vec_per_s": hv_D / (hv1_ms * 1e-3), "single_fp64_ms": hv1_ms,
-               "connections": stats["connections"], "active_connections": stats["active_connections"]},
+               "connections": stats["connections"], "active_connections": stats["active_connections"],
+               "on_the_fly": otf},
         "observables_vs_fp64": obs_err,
         "serving": serving,
         "kpm": kpm,
