@@ -443,7 +443,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hv-reps", type=int, default=20)
-    ap.add_argument("--layout", default="auto", choices=["auto", "block", "padded", "packed"],
+    ap.add_argument("--layout", default="auto", choices=["auto", "block", "padded", "packed", "aligned"],
                     help="rows of the Lanczos vectors inside ftlm_run (auto: the library's choice)")
     ap.add_argument("--engine", default="auto", choices=["auto", "steps", "fused"],
                     help="campaign workloads: Lanczos engine (fused small-block kernel, per-step kernels, or automatic)")
@@ -496,8 +496,9 @@ def main():
     wl = WORKLOADS[args.workload]
     cl = clusters.get(wl["cluster"])
     layout = {"auto": P.LAYOUT_AUTO, "block": P.LAYOUT_BLOCK, "padded": P.LAYOUT_PADDED,
-              "packed": P.LAYOUT_PACKED}[args.layout]
-    LAYOUT_NAMES = {P.LAYOUT_BLOCK: "block", P.LAYOUT_PADDED: "padded", P.LAYOUT_PACKED: "packed"}
+              "packed": P.LAYOUT_PACKED, "aligned": P.LAYOUT_ALIGNED}[args.layout]
+    LAYOUT_NAMES = {P.LAYOUT_BLOCK: "block", P.LAYOUT_PADDED: "padded", P.LAYOUT_PACKED: "packed",
+                    P.LAYOUT_ALIGNED: "aligned"}
     if wl.get("campaign"):
         torch.cuda.set_device(0)
         print(json.dumps(bench_campaign(P, np, wl, cl, args)), flush=True)
@@ -578,7 +579,7 @@ def main():
         torch.cuda.synchronize()
         st = B0.hv_stats()
         elem = {P.F64: 8, P.F32: 4, P.F16: 2}[storage]
-        pad = info["layout"] in (P.LAYOUT_PADDED, P.LAYOUT_PACKED)
+        pad = info["layout"] in (P.LAYOUT_PADDED, P.LAYOUT_PACKED, P.LAYOUT_ALIGNED)
         print(json.dumps({"copy_bytes": 1 << 30, "hv_launches": info["hv_launches"], "lanes_per_rep": tuned[0],
                           "layout": LAYOUT_NAMES[info["layout"]], "nvec": wl["R"], "elem_bytes": elem,
                           "rows": info["rows"], "avg_launch_ms": info["hv_ms"] / max(info["hv_launches"], 1),
@@ -624,7 +625,7 @@ def main():
     hv_ms = ev0.elapsed_time(ev1) / args.hv_reps
     stats = B.hv_stats()
     # roofline: the H.V launches of the timed runs on the roofline block (HIP events on the run's stream)
-    pad = recs[0]["layout"] in (P.LAYOUT_PADDED, P.LAYOUT_PACKED)
+    pad = recs[0]["layout"] in (P.LAYOUT_PADDED, P.LAYOUT_PACKED, P.LAYOUT_ALIGNED)
     lz_launches = sum(r["hv_launches"] for r in recs)
     lz_hv_ms = sum(r["hv_ms"] for r in recs) / max(lz_launches, 1)
     balg = algorithmic_bytes(stats, B.D, S.n_reps, wl["R"], elem, pad=pad, epilogue=True)

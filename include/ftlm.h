@@ -91,10 +91,24 @@ typedef struct ftlm_cluster {
  * line are held at zero (it applies when 2 <= p and p d_Gamma < L; otherwise
  * it is PADDED).  A random gather of a representative's rows then reads one
  * 128-byte line instead of 1.25 on average for 40-byte slices: fewer bytes,
- * the same number of random accesses.  AUTO: PADDED when D >= 2^20 and the
- * padding adds at most 2% rows, BLOCK otherwise.  The layout changes only
- * the summation order of the FP64 reductions, not what is computed. */
-enum ftlm_layout { FTLM_LAYOUT_AUTO = 0, FTLM_LAYOUT_BLOCK = 1, FTLM_LAYOUT_PADDED = 2, FTLM_LAYOUT_PACKED = 3 };
+ * the same number of random accesses.  ALIGNED: PADDED with S rows per
+ * representative, S the smallest power of two >= d_Gamma (representative i
+ * at row i * S, rows k >= n_Gamma(i) held at zero); it applies when the row
+ * size b is a power of two, S > d_Gamma and S b <= 128 (otherwise it is
+ * PADDED).  Each representative's rows then fill one naturally aligned block
+ * of S b bytes, for S / d_Gamma times the rows.  Neither PACKED nor ALIGNED
+ * measured faster than PADDED (s = 3/2 dodecahedron H_g block, 2 FP32
+ * vectors), so AUTO takes neither.  AUTO: PADDED when
+ * D >= 2^20 and the padding adds at most 2% rows, BLOCK otherwise.  The
+ * layout changes only the summation order of the FP64 reductions, not what
+ * is computed. */
+enum ftlm_layout {
+  FTLM_LAYOUT_AUTO = 0,
+  FTLM_LAYOUT_BLOCK = 1,
+  FTLM_LAYOUT_PADDED = 2,
+  FTLM_LAYOUT_PACKED = 3,
+  FTLM_LAYOUT_ALIGNED = 4
+};
 
 /* Storage of the sector's entry table (one entry per flip: target index,
  * connecting element, flip id, trivial-target bit).  WIDE: 8 bytes.
@@ -280,6 +294,9 @@ typedef struct ftlm_hv_opts {
                              enum ftlm_layout with row size ld * element bytes
                              (ceil(n_reps / p) * L rows; the rows between
                              representatives hold zeros in X and are not written in Y).
+                             ALIGNED: as described at enum ftlm_layout with row size
+                             ld * element bytes (n_reps * S rows; rows k >= n_Gamma(i)
+                             hold zeros in X and are not written in Y).
                              AUTO: the layout ftlm_run takes for this block and nvec
                              (ftlm_run_info.layout). */
   int32_t lanes;          /* lanes per output representative: a power of two 1..64, or 0

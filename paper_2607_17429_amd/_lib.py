@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libftlm.so")
 F64, F32, F16 = 0, 1, 2
 RADEMACHER, GAUSSIAN = 0, 1
 HV_AUTO, HV_ENTRIES, HV_ONTHEFLY = 0, 1, 2
-LAYOUT_AUTO, LAYOUT_BLOCK, LAYOUT_PADDED, LAYOUT_PACKED = 0, 1, 2, 3
+LAYOUT_AUTO, LAYOUT_BLOCK, LAYOUT_PADDED, LAYOUT_PACKED, LAYOUT_ALIGNED = 0, 1, 2, 3, 4
 ENTRIES_AUTO, ENTRIES_WIDE, ENTRIES_COMPACT = 0, 1, 2
 ENGINE_AUTO, ENGINE_STEPS, ENGINE_FUSED = 0, 1, 2
 

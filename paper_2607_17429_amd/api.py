@@ -196,7 +196,8 @@ class Block:
     def apply_H_ex(self, X, Y=None, layout=0, lanes=0, scale=None, dots=None, shift=0.0, stream=None,
                    noalloc=False):
         """ftlm_apply_H_ex on (rows, nvec) torch CUDA tensors: rows = D (LAYOUT_BLOCK) or
-        n_reps * d_Gamma (LAYOUT_PADDED; AUTO = the layout ftlm_run takes).  scale:
+        n_reps * d_Gamma (LAYOUT_PADDED), packed or aligned rows (LAYOUT_PACKED,
+        LAYOUT_ALIGNED; see include/ftlm.h); AUTO = the layout ftlm_run takes.  scale:
         float64 CUDA tensor (nvec, 2) of (s, b) pairs, Y <- s (H - shift) X - b Y;
         dots: float64 CUDA tensor (nvec,) receiving sum_rows X * Y.  noalloc: the
         entry point whose scratch is a static device array (ftlm_apply_H_ex_noalloc).

@@ -150,8 +150,8 @@ std::unique_ptr<Block> build_block(std::shared_ptr<Sector> sec, int irrep, int r
   const double parity = (sec->zflip && (irrep & 1)) ? -1.0 : 1.0;
   if (irrep < 0) fail(FTLM_ERR_IRREP_OUT_OF_RANGE, "irrep index out of range");
   if (opts) {
-    if (opts->lanczos_layout < FTLM_LAYOUT_AUTO || opts->lanczos_layout > FTLM_LAYOUT_PACKED)
-      fail(FTLM_ERR_INVALID_ARG, "lanczos_layout must be AUTO, BLOCK, PADDED or PACKED");
+    if (opts->lanczos_layout < FTLM_LAYOUT_AUTO || opts->lanczos_layout > FTLM_LAYOUT_ALIGNED)
+      fail(FTLM_ERR_INVALID_ARG, "lanczos_layout must be AUTO, BLOCK, PADDED, PACKED or ALIGNED");
     B->lanczos_layout = opts->lanczos_layout;
   }
   if (opts && opts->user_rho && opts->user_rho_dim > 0) {

@@ -18,16 +18,17 @@ namespace ftlm {
 namespace dev {
 
 // Row map of the padded vector layouts: representative i starts at row
-// (i / rpl) * rpline + (i % rpl) * dstride, i.e. i * dstride when rpl = 1;
-// with rpl > 1 (rpl representatives packed into one 128-byte line of rpline
-// rows) representatives are counted in 32 bits.
+// (i / rpl) * rpline + (i % rpl) * dstride (dstride = d_Gamma).  rpl = 1:
+// row i * rpline, with rpline = d_Gamma (plain padded rows) or a power of
+// two above it (aligned rows); rpl > 1: rpl representatives packed into one
+// 128-byte line of rpline rows, counted in 32 bits.
 struct PadMap {
   uint32_t dstride, rpl, rpline;
   uint64_t n_reps;
 };
 
 __host__ __device__ __forceinline__ uint64_t padded_row(uint32_t dstride, uint32_t rpl, uint32_t rpline, uint64_t i) {
-  if (rpl <= 1) return i * (uint64_t)dstride;
+  if (rpl <= 1) return i * (uint64_t)rpline;
   const uint32_t i32 = (uint32_t)i;
   return (uint64_t)(i32 / rpl) * rpline + (uint64_t)(i32 % rpl) * dstride;
 }
@@ -36,8 +37,8 @@ __host__ __device__ __forceinline__ uint64_t padded_row(uint32_t dstride, uint32
 // false for the rows between packed representatives and past the last one.
 __host__ __device__ __forceinline__ bool padded_rep_of(const PadMap& m, uint64_t row, uint64_t& i, int& k) {
   if (m.rpl <= 1) {
-    i = row / m.dstride;
-    k = (int)(row - i * m.dstride);
+    i = row / m.rpline;
+    k = (int)(row - i * m.rpline);
     return i < m.n_reps;
   }
   const uint64_t g = row / m.rpline;

@@ -208,10 +208,11 @@ HvExPlan plan_hv_ex(const Block& b, int nvec, int64_t ld, int dtype, const ftlm_
   const int layout = o ? o->layout : FTLM_LAYOUT_BLOCK;
   if (layout == FTLM_LAYOUT_AUTO)
     p.vl = run_layout(b, ld * elem);
-  else if (layout == FTLM_LAYOUT_BLOCK || layout == FTLM_LAYOUT_PADDED || layout == FTLM_LAYOUT_PACKED)
+  else if (layout == FTLM_LAYOUT_BLOCK || layout == FTLM_LAYOUT_PADDED || layout == FTLM_LAYOUT_PACKED ||
+           layout == FTLM_LAYOUT_ALIGNED)
     p.vl = vec_layout(b, layout, ld * elem);
   else
-    fail(FTLM_ERR_INVALID_ARG, "layout must be FTLM_LAYOUT_AUTO, _BLOCK, _PADDED or _PACKED");
+    fail(FTLM_ERR_INVALID_ARG, "layout must be FTLM_LAYOUT_AUTO, _BLOCK, _PADDED, _PACKED or _ALIGNED");
   p.rows = vec_rows(b, p.vl);
   p.epi = o && o->scale;
   if (o && o->dots && !o->scale) fail(FTLM_ERR_INVALID_ARG, "dots need scale");
@@ -309,7 +310,7 @@ void hv_setup(const Block& b, int nvec, int64_t ld, int gl, const VecLayout& vl,
     a.pad = pad ? 1 : 0;
     a.dstride = b.dg;
     a.rpl = vl.rpl;
-    a.rpline = vl.rpl > 1 ? vl.rpline : (uint32_t)b.dg;
+    a.rpline = vl.rpl > 1 || vl.aligned ? vl.rpline : (uint32_t)b.dg;
     a.triv_sid = s.trivial_sid;
     a.sid = s.d_stab_id.p;
     a.meta = b.d_meta.p;

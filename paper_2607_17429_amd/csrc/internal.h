@@ -126,12 +126,15 @@ void apply_hv(const Block& b, const void* X, void* Y, int nvec, int64_t ld, int 
 // 128-byte line of rpline rows (enum ftlm_layout).
 struct VecLayout {
   bool pad = false;
+  bool aligned = false; // rpline (a power of two > d_Gamma) rows per representative
   uint32_t rpl = 1;     // representatives per line (1: plain padded)
-  uint32_t rpline = 0;  // rows per line when rpl > 1
-  int kind() const { return !pad ? FTLM_LAYOUT_BLOCK : rpl > 1 ? FTLM_LAYOUT_PACKED : FTLM_LAYOUT_PADDED; }
+  uint32_t rpline = 0;  // rows per line when rpl > 1, rows per representative when aligned
+  int kind() const {
+    return !pad ? FTLM_LAYOUT_BLOCK : aligned ? FTLM_LAYOUT_ALIGNED : rpl > 1 ? FTLM_LAYOUT_PACKED : FTLM_LAYOUT_PADDED;
+  }
 };
-// kind BLOCK, PADDED or PACKED (PACKED falls back to PADDED where it does
-// not apply) for rows of row_bytes bytes
+// kind BLOCK, PADDED, PACKED or ALIGNED (PACKED and ALIGNED fall back to
+// PADDED where they do not apply) for rows of row_bytes bytes
 VecLayout vec_layout(const Block& b, int kind, int64_t row_bytes);
 // the layout ftlm_run and ftlm_kpm take for this block and row size
 VecLayout run_layout(const Block& b, int64_t row_bytes);

@@ -318,7 +318,8 @@ uint64_t chain_key(uint64_t seed, int two_M, int irrep, int row, int chain) {
 
 bool padded_vectors(const Block& b) {
   bool pad = false;
-  if (b.lanczos_layout == FTLM_LAYOUT_PADDED || b.lanczos_layout == FTLM_LAYOUT_PACKED)
+  if (b.lanczos_layout == FTLM_LAYOUT_PADDED || b.lanczos_layout == FTLM_LAYOUT_PACKED ||
+      b.lanczos_layout == FTLM_LAYOUT_ALIGNED)
     pad = true;
   else if (b.lanczos_layout == FTLM_LAYOUT_AUTO)
     pad = b.D >= (1ull << 20) && (double)b.D_pad <= 1.02 * (double)b.D;
@@ -329,8 +330,17 @@ bool padded_vectors(const Block& b) {
 VecLayout vec_layout(const Block& b, int kind, int64_t row_bytes) {
   VecLayout v;
   if (kind == FTLM_LAYOUT_BLOCK) return v;
-  if (kind != FTLM_LAYOUT_PADDED && kind != FTLM_LAYOUT_PACKED) fail(FTLM_ERR_INVALID_ARG, "bad row layout");
+  if (kind != FTLM_LAYOUT_PADDED && kind != FTLM_LAYOUT_PACKED && kind != FTLM_LAYOUT_ALIGNED)
+    fail(FTLM_ERR_INVALID_ARG, "bad row layout");
   v.pad = true;
+  if (kind == FTLM_LAYOUT_ALIGNED && row_bytes > 0 && (row_bytes & (row_bytes - 1)) == 0 && b.dg > 0) {
+    uint32_t S = 1;
+    while (S < (uint32_t)b.dg) S <<= 1;
+    if (S > (uint32_t)b.dg && (int64_t)S * row_bytes <= 128) {
+      v.aligned = true;
+      v.rpline = S;
+    }
+  }
   if (kind == FTLM_LAYOUT_PACKED && row_bytes > 0 && 128 % row_bytes == 0 && b.dg > 0 &&
       b.sec->n_reps < (1ull << 32)) {
     const uint32_t L = (uint32_t)(128 / row_bytes);
@@ -350,12 +360,16 @@ VecLayout vec_layout(const Block& b, int kind, int64_t row_bytes) {
 // connection either way, not by the bytes of the lines), and it costs rows.
 VecLayout run_layout(const Block& b, int64_t row_bytes) {
   if (!padded_vectors(b)) return VecLayout{};
-  return vec_layout(b, b.lanczos_layout == FTLM_LAYOUT_PACKED ? FTLM_LAYOUT_PACKED : FTLM_LAYOUT_PADDED, row_bytes);
+  const int kind = b.lanczos_layout == FTLM_LAYOUT_PACKED || b.lanczos_layout == FTLM_LAYOUT_ALIGNED
+                       ? b.lanczos_layout
+                       : FTLM_LAYOUT_PADDED;
+  return vec_layout(b, kind, row_bytes);
 }
 
 uint64_t vec_rows(const Block& b, const VecLayout& v) {
   if (!v.pad) return b.D;
   const uint64_t n = b.sec->n_reps;
+  if (v.aligned) return n * (uint64_t)v.rpline;
   if (v.rpl <= 1) return n * (uint64_t)b.dg;
   return (n + v.rpl - 1) / v.rpl * (uint64_t)v.rpline;
 }
@@ -364,7 +378,7 @@ dev::PadMap pad_map(const Block& b, const VecLayout& v) {
   dev::PadMap m{};
   m.dstride = (uint32_t)std::max(b.dg, 1);
   m.rpl = v.rpl;
-  m.rpline = v.rpl > 1 ? v.rpline : m.dstride;
+  m.rpline = v.rpl > 1 || v.aligned ? v.rpline : m.dstride;
   m.n_reps = b.sec->n_reps;
   return m;
 }
@@ -393,8 +407,11 @@ LanczosRun::LanczosRun(const Block& b, int R_, int steps_, uint64_t seed_, int s
 
 size_t LanczosRun::estimate_bytes(const Block& b, int R, int steps, int storage) {
   const size_t elem = storage == FTLM_F64 ? 8 : storage == FTLM_F32 ? 4 : 2;
-  // packed rows add at most a third of the padded rows (p >= 2 representatives per line)
-  const uint64_t rows = std::max(b.D, b.lanczos_layout == FTLM_LAYOUT_BLOCK ? b.D : b.D_pad + b.D_pad / 2);
+  // packed rows add at most a third of the padded rows (p >= 2 representatives
+  // per line), aligned rows less than double them (S < 2 d_Gamma)
+  const uint64_t rows = std::max(b.D, b.lanczos_layout == FTLM_LAYOUT_BLOCK     ? b.D
+                                      : b.lanczos_layout == FTLM_LAYOUT_ALIGNED ? 2 * b.D_pad
+                                                                                : b.D_pad + b.D_pad / 2);
   return 2 * (size_t)rows * R * elem + (size_t)8192 * R * 8 + (size_t)R * steps * 16 + (size_t)R * 128;
 }
 

@@ -53,7 +53,9 @@ void launch_shape(const Shape& sh, const void* jobs, int n, size_t shm, hipStrea
 bool wg_supported(const Block& b, int R, int storage) {
   if (R < 1 || R > kWgMaxR || b.D == 0 || b.sec->n_reps == 0) return false;
   if (storage != FTLM_F64 && storage != FTLM_F32) return false;
-  if (b.sec->hv_mode != FTLM_HV_ENTRIES || (b.lanczos_layout == FTLM_LAYOUT_PADDED || b.lanczos_layout == FTLM_LAYOUT_PACKED)) return false;
+  if (b.sec->hv_mode != FTLM_HV_ENTRIES || b.lanczos_layout == FTLM_LAYOUT_PADDED ||
+      b.lanczos_layout == FTLM_LAYOUT_PACKED || b.lanczos_layout == FTLM_LAYOUT_ALIGNED)
+    return false;
   if (irrep_dim_bucket(b.dg) < 0) return false;
   LaunchCfg c{};
   HvArgs<double> a{};

@@ -16,7 +16,7 @@ torch = pytest.importorskip("torch")
 P = pytest.importorskip("paper_2607_17429_amd")
 
 
-@pytest.mark.parametrize("case", range(5))
+@pytest.mark.parametrize("case", range(6))
 def test_interrupted_run_resumes_bitwise(tmp_path, case):
     name, gi, R, steps, stor, layout, cut = [
         ("dodecahedron", 8, 5, 41, P.F64, P.LAYOUT_BLOCK, 13),
@@ -24,6 +24,7 @@ def test_interrupted_run_resumes_bitwise(tmp_path, case):
         ("icosahedron", 8, 3, 30, P.F16, P.LAYOUT_BLOCK, 7),
         ("dodecahedron", 2, 24, 60, P.F32, P.LAYOUT_PADDED, 1),
         ("dodecahedron", 8, 2, 40, P.F32, P.LAYOUT_PACKED, 17),     # 3 representatives per 128-byte line
+        ("dodecahedron", 8, 2, 40, P.F32, P.LAYOUT_ALIGNED, 9),     # 8 rows (64 bytes) per representative
     ][case]
     log(f"[checkpoint] {name} irrep {gi} R={R} storage {stor} layout {layout} cut at {cut}")
     _, _, irs = oracle_group(name)

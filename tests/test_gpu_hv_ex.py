@@ -291,3 +291,79 @@ def test_packed_lanczos_and_kpm_match_block_rows():
     m = LK.kpm(1, 41, 9, 0.5, 20.0)
     m1 = LBl.kpm(1, 41, 9, 0.5, 20.0)
     assert np.max(np.abs(m - m1)) < 1e-12
+
+
+def _aligned_rows(n_reps, d, row_bytes):
+    """Start rows of the aligned layout (include/ftlm.h): S rows per
+    representative, S the smallest power of two >= d, when the row size is a
+    power of two, S > d and S * row_bytes <= 128; plain padded rows otherwise."""
+    S = 1
+    while S < d:
+        S *= 2
+    if row_bytes & (row_bytes - 1) == 0 and S > d and S * row_bytes <= 128:
+        return np.arange(n_reps) * S, n_reps * S, True
+    return np.arange(n_reps) * d, n_reps * d, False
+
+
+@pytest.mark.parametrize("bucket", range(6))
+def test_aligned_layout_against_oracle(bucket):
+    """The aligned row layout (each representative's rows in one power-of-two
+    block of at most 128 bytes) for every dimension bucket and row sizes of 2
+    to 32 bytes, the two-vector launches included (paired-row gather): every
+    output row equals the oracle's, and the padding rows are not written."""
+    name, two_s, two_M, gi = BUCKETS[bucket]
+    B, H, LB, keep = _blocks(name, two_s, two_M, gi)
+    rng = np.random.default_rng(400 + bucket)
+    d = B.irrep.dim
+    n_reps = len(B.sec.reps)
+    seen = False
+    for nvec, dt in ((1, P.F32), (2, P.F32), (4, P.F32), (8, P.F32), (1, P.F64), (2, P.F64), (2, P.F16),
+                     (3, P.F32)):
+        elem = {P.F64: 8, P.F32: 4, P.F16: 2}[dt]
+        start, rows, aligned = _aligned_rows(n_reps, d, nvec * elem)
+        seen |= aligned
+        X = rng.uniform(-1, 1, (B.D, nvec)).astype(NP[dt])
+        Xp = torch.from_numpy(_to_layout(B, X, start, rows)).cuda()
+        Y, info = LB.apply_H_ex(Xp, layout=P.LAYOUT_ALIGNED)
+        Yh = Y.cpu().numpy()
+        ref = hv.apply(B, H, X.astype(np.float64))
+        got = np.concatenate([Yh[start[i]:start[i] + int(B.n_rep[i])] for i in np.nonzero(B.n_rep)[0]])
+        assert rel_err_cols(got.astype(np.float64), ref) <= TOL[dt], (nvec, dt)
+        written = np.zeros(rows, dtype=bool)
+        for i in np.nonzero(B.n_rep)[0]:
+            written[start[i]:start[i] + int(B.n_rep[i])] = True
+        assert not np.any(Yh[~written]), (nvec, dt)
+    # d = 1, 2, 4 are powers of two already: aligned rows are the padded rows
+    assert seen or d in (1, 2, 4)
+
+
+def test_aligned_lanczos_and_kpm_match_block_rows():
+    """Lanczos chains and KPM moments in the aligned layout (d = 5: 8 rows per
+    representative) equal those in block rows up to the order of the FP64
+    reductions (one FP64 chain, four FP32 chains) or FP32 rounding (two FP32
+    chains: the paired-row gather); rows that would pass 128 bytes fall back
+    to padded rows."""
+    name, two_s, two_M, gi = "dodecahedron", 1, 0, 8
+    _, _, irs = oracle_group(name)
+    B, H, LB, keep = _blocks(name, two_s, two_M, gi)
+    S = LB.sector
+    LA = P.Block(S, gi, 0, user_rho=irs[gi].rho, layout=P.LAYOUT_ALIGNED)
+    LBl = P.Block(S, gi, 0, user_rho=irs[gi].rho, layout=P.LAYOUT_BLOCK)
+    n_reps = len(B.sec.reps)
+    a, b, n, info = LA.ftlm(1, 40, 5, storage=P.F64, info=True)
+    assert info["layout"] == P.LAYOUT_ALIGNED and info["rows"] == n_reps * 8
+    a1, b1, n1 = LBl.ftlm(1, 40, 5, storage=P.F64)
+    assert np.max(np.abs(a[:, :15] - a1[:, :15])) < 1e-12 * np.max(np.abs(a1))
+    assert np.max(np.abs(b[:, :15] - b1[:, :15])) < 1e-12 * np.max(np.abs(b1))
+    for R in (2, 4):
+        a, b, n, info = LA.ftlm(R, 30, 6, storage=P.F32, info=True)
+        assert info["layout"] == P.LAYOUT_ALIGNED and info["rows"] == n_reps * 8
+        a1, b1, n1 = LBl.ftlm(R, 30, 6, storage=P.F32)
+        assert np.max(np.abs(a[:, :15] - a1[:, :15])) < 1e-6 * np.max(np.abs(a1)), R
+        assert np.max(np.abs(b[:, :15] - b1[:, :15])) < 1e-6 * np.max(np.abs(b1)), R
+    # 4 FP64 vectors: 32-byte rows, 8 of them pass 128 bytes: plain padded rows
+    _, _, _, info = LA.ftlm(4, 10, 6, storage=P.F64, info=True)
+    assert info["layout"] == P.LAYOUT_PADDED
+    m = LA.kpm(1, 41, 9, 0.5, 20.0)
+    m1 = LBl.kpm(1, 41, 9, 0.5, 20.0)
+    assert np.max(np.abs(m - m1)) < 1e-12
