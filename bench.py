@@ -630,6 +630,7 @@ def main():
     lz_hv_ms = sum(r["hv_ms"] for r in recs) / max(lz_launches, 1)
     balg = algorithmic_bytes(stats, B.D, S.n_reps, wl["R"], elem, pad=pad, epilogue=True)
     achieved = balg / (lz_hv_ms * 1e-3) / 1e9
+    bmin = 3 * B.D * wl["R"] * elem + 32 * stats["n_active"] + 8 * (S.n_reps - stats["n_active"])
     balg_apply = algorithmic_bytes(stats, B.D, S.n_reps, wl["R"], elem)
     # plain single-vector FP64 H.V for the speedup figure
     del X, Y
@@ -744,8 +745,13 @@ def main():
                      "kernel": f"k_hv inside ftlm_run on the irrep-{rirrep} block (entry-table mode, Lanczos epilogue, "
                                + LAYOUT_NAMES[recs[0]["layout"]] + " rows)",
                      "algorithmic_bytes_per_launch": balg, "avg_launch_ms": lz_hv_ms, "launches": lz_launches,
-                     "nvec": wl["R"]},
+                     "nvec": wl["R"],
+                     # X read once (every row), Y written, the previous vector read by the
+                     # epilogue, per-representative data streamed once: no gather re-reads
+                     "compulsory_bytes_per_launch": bmin,
+                     "compulsory_frac": bmin / (lz_hv_ms * 1e-3) / 1e9 / PEAK_HBM_GBS},
         "cpu_baseline": cpu,
+        "speedup_vs_oracle": value / cpu["value"] if cpu else None,
         "context": dict(wl["context"], this_job_s=float(np.mean([r["total"] for r in recs]))) if "context" in wl else None,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "of": "whole jobs of this workload (the timed steps)"},
@@ -753,6 +759,7 @@ def main():
         "hv": {"apply_H_ms": hv_ms, "apply_H_GBs": balg_apply / (hv_ms * 1e-3) / 1e9,
                "batched_elem_vec_per_s": hv_D * wl["R"] / (hv_ms * 1e-3),
                "single_fp64_elem_vec_per_s": hv_D / (hv1_ms * 1e-3), "single_fp64_ms": hv1_ms,
+               "speedup_batched_over_single_fp64": (hv_D * wl["R"] / (hv_ms * 1e-3)) / (hv_D / (hv1_ms * 1e-3)),
                "connections": stats["connections"], "active_connections": stats["active_connections"],
                "on_the_fly": otf},
         "observables_vs_fp64": obs_err,

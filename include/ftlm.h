@@ -404,7 +404,9 @@ int ftlm_run_ex(ftlm_block* b, int32_t R, int32_t steps, uint64_t seed, int32_t 
  * Lanczos steps on the run's stream (asynchronous; *done = steps enqueued so
  * far, at most min(steps, D)); ftlm_run_save waits for the stream and writes
  * the run's device state (per-chain state, alpha and beta so far, both
- * stored vectors: 2 x rows x R elements) to a file; ftlm_run_load rebuilds a
+ * stored vectors: 2 x rows x R elements) to a file (written as path.part
+ * and renamed to path when complete, so an interrupted save leaves an
+ * earlier checkpoint at path intact); ftlm_run_load rebuilds a
  * saved run on a block built the same way (same cluster, group, sector,
  * irrep, row and row layout; INVALID_ARG otherwise), ready to advance;
  * ftlm_run_finish runs the remaining steps and returns alpha, beta and

@@ -581,14 +581,26 @@ void LanczosRun::save(const char* path, hipStream_t st, int next_step) const {
   h.seed = seed;
   h.sigma = sigma;
   h.vec_bytes = q0.bytes();
-  File f(path, "wb");
-  if (std::fwrite(&h, sizeof(h), 1, f.f) != 1) fail(FTLM_ERR_INVALID_ARG, "checkpoint write failed");
-  Pinned stage(kStageBytes);
-  dev_to_file(f.f, chain.p, chain.bytes(), st, stage);
-  dev_to_file(f.f, d_alpha.p, d_alpha.bytes(), st, stage);
-  dev_to_file(f.f, d_beta.p, d_beta.bytes(), st, stage);
-  dev_to_file(f.f, q0.p, q0.bytes(), st, stage);
-  dev_to_file(f.f, q1.p, q1.bytes(), st, stage);
+  // written next to the target and renamed into place once complete, so an
+  // interrupted save leaves an earlier checkpoint at path intact
+  const std::string part = std::string(path) + ".part";
+  try {
+    File f(part.c_str(), "wb");
+    if (std::fwrite(&h, sizeof(h), 1, f.f) != 1) fail(FTLM_ERR_INVALID_ARG, "checkpoint write failed");
+    Pinned stage(kStageBytes);
+    dev_to_file(f.f, chain.p, chain.bytes(), st, stage);
+    dev_to_file(f.f, d_alpha.p, d_alpha.bytes(), st, stage);
+    dev_to_file(f.f, d_beta.p, d_beta.bytes(), st, stage);
+    dev_to_file(f.f, q0.p, q0.bytes(), st, stage);
+    dev_to_file(f.f, q1.p, q1.bytes(), st, stage);
+    const int rc = std::fclose(f.f);
+    f.f = nullptr;
+    if (rc != 0) fail(FTLM_ERR_INVALID_ARG, "checkpoint write failed");
+    if (std::rename(part.c_str(), path) != 0) fail(FTLM_ERR_INVALID_ARG, std::string("cannot replace ") + path);
+  } catch (...) {
+    std::remove(part.c_str());
+    throw;
+  }
 }
 
 std::unique_ptr<LanczosRun> LanczosRun::load(const Block& b, const char* path, hipStream_t st, int& next_step) {

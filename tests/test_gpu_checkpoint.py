@@ -34,7 +34,9 @@ def test_interrupted_run_resumes_bitwise(tmp_path, case):
     run = P.LanczosRunState.begin(B, R, steps, 77, storage=stor, stream=s)
     assert run.advance(cut) == cut
     path = tmp_path / "run.ckpt"
+    path.write_bytes(b"an earlier file")   # replaced as a whole
     run.save(path)
+    assert not (tmp_path / "run.ckpt.part").exists()
     run.close()
     torch.cuda.synchronize()
     X = torch.randn((B.D, 2), dtype=torch.float64, device="cuda")
