@@ -464,8 +464,12 @@ def main():
     ap.add_argument("--serve-active", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--serve-log", default=None, help="write one JSON record per job to this file")
-    ap.add_argument("--hw-queues", type=int, default=0,
-                    help="hardware queues per process (GPU_MAX_HW_QUEUES, read when HIP starts); 0 keeps the default")
+    # 16 hardware queues give each server stream a queue of its own, so a short
+    # job's kernels do not wait behind a long job's queued steps (serving mix:
+    # short-job run p90 56 ms against 330-390 ms with the default 4 queues)
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="hardware queues per process (GPU_MAX_HW_QUEUES, read when HIP starts, at most 32); "
+                         "0 keeps the runtime's default")
     args = ap.parse_args()
     if args.hw_queues:
         os.environ["GPU_MAX_HW_QUEUES"] = str(min(args.hw_queues, 32))

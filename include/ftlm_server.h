@@ -9,7 +9,10 @@
  * unless already resident) fits in hbm_budget_bytes; a later job that fits may
  * overtake one that does not, until that one has been overtaken 64 times and
  * then holds back the queue behind it (nothing behind it is admitted until it
- * is).  Small jobs (sectors of a few hundred representatives, R <= 32, FP64
+ * is).  Jobs with long steps (about 1 ms or more of estimated device time
+ * per Lanczos step) take at most max_active - 2 slots when max_active > 2, so
+ * short jobs always find a slot; such a job waiting only for that reason is
+ * counted as overtaken by later long-step jobs, not by the short ones.  Small jobs (sectors of a few hundred representatives, R <= 32, FP64
  * or FP32 storage) admitted in the same pass over the queue, while no job
  * with long steps (about 1 ms or more of estimated device time) is running,
  * run together as one batch of the fused small-block kernel
@@ -27,7 +30,9 @@
  * work of different jobs overlaps on the device; its Lanczos steps are
  * enqueued in chunks of about 10 ms of estimated device time, so a long job
  * holds a hardware queue shared with other streams for at most one chunk
- * ahead of their work.  A job may ask for the fused small-block kernel
+ * ahead of their work; with at least max_active + 2 hardware queues per
+ * process (the HIP runtime's GPU_MAX_HW_QUEUES, read when it starts) no
+ * stream shares one, and short jobs do not wait behind long ones at all.  A job may ask for the fused small-block kernel
  * (ftlm_run_fused); it then joins the batch of its pass.  A job's result does
  * not depend on the other jobs (no shared reductions, deterministic kernels,
  * and a job's result in a fused batch does not depend on the batch).  The two server threads own

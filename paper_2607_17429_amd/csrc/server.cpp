@@ -74,6 +74,7 @@ struct Job {
   int32_t* h_n = nullptr;
   int overtaken = 0;
   bool heavy = false;  // a per-step job with an estimated step of at least kHeavyStepSeconds
+  bool capped = false; // refused in this walk because the long-step jobs had their slots
   // incremental enqueue: steps [0, next_step) are on the stream, at most two
   // chunks of `chunk` steps are in flight, each followed by an event
   int next_step = 0, chunk = 1;
@@ -94,6 +95,20 @@ constexpr double kHbmBytesPerSecond = 4.0e12;  // sustained gather rate assumed 
 // serving mix: median latency 110 ms batched against 23 ms with per-step
 // kernels, at the same throughput), while short per-step kernels interleave.
 constexpr double kHeavyStepSeconds = 1e-3;
+// Slots that jobs with long steps leave to the others (when max_active > 2):
+// with every slot taken by runs of seconds, a short job waited for one of
+// them to finish (measured on the serving mix: queue waits of 1.3-1.6 s with
+// 7-8 slots held by 6x6-torus runs).
+constexpr int kShortSlots = 2;
+
+// HBM bytes of one Lanczos step (entries, gathered rows, the vector passes)
+// at kHbmBytesPerSecond; rows per representative = D / n_reps.
+double step_seconds(const Sector& S, double D, int R, int storage) {
+  const double elem = storage == FTLM_F64 ? 8.0 : storage == FTLM_F32 ? 4.0 : 2.0;
+  const double rows = S.n_reps ? D / (double)S.n_reps : 0.0;
+  const double step_bytes = (double)S.n_entries * (rows * R * elem + 8.0) + 6.0 * D * R * elem;
+  return step_bytes / kHbmBytesPerSecond;
+}
 
 std::string key_of(const void* p, size_t n) { return std::string((const char*)p, n); }
 
@@ -354,6 +369,7 @@ void Server::take_builds() {
 }
 
 int Server::try_admit(const std::shared_ptr<Job>& j) {
+  j->capped = false;
   auto gf = group_failed.find(j->group_key);
   if (gf != group_failed.end()) {
     j->msg = gf->second.second;
@@ -391,6 +407,15 @@ int Server::try_admit(const std::shared_ptr<Job>& j) {
   const bool room = forming.size() < kMaxBatchJobs;
   const bool joins = small && room && !forming.empty();
   if (!joins && slots_in_use() >= max_active) return 0;
+  // a job with long steps (by an upper bound of the block: d_Gamma rows per
+  // representative) does not take the last kShortSlots slots
+  if (!small && max_active > kShortSlots && heavy_running >= max_active - kShortSlots) {
+    const int dg = (G.irreps_computed && j->irrep >= 0 && j->irrep < (int)G.irreps.size()) ? G.irreps[j->irrep].dim : 1;
+    if (step_seconds(*se.sec, (double)se.sec->n_reps * dg, j->R, j->storage) >= kHeavyStepSeconds) {
+      j->capped = true;
+      return 0;
+    }
+  }
   const int64_t est = estimate_job(*j, G, *se.sec);
   if (est > budget) {
     j->msg = "estimated job footprint of " + std::to_string(est) + " bytes exceeds the server budget";
@@ -485,11 +510,7 @@ void Server::start_steps(const std::shared_ptr<Job>& j) {
   // HBM time, so a long run never holds a shared hardware queue for more
   // than one chunk ahead of other jobs' work.
   {
-    const Sector& S = *j->block->sec;
-    const double elem = j->storage == FTLM_F64 ? 8.0 : j->storage == FTLM_F32 ? 4.0 : 2.0;
-    const double rows = S.n_reps ? (double)j->D / (double)S.n_reps : 0.0;
-    const double step_bytes = (double)S.n_entries * (rows * j->R * elem + 8.0) + 6.0 * (double)j->D * j->R * elem;
-    const double step_s = step_bytes / kHbmBytesPerSecond;
+    const double step_s = step_seconds(*j->block->sec, (double)j->D, j->R, j->storage);
     j->chunk = (int)std::max(1.0, std::min((double)std::max(j->run->target, 1), kChunkSeconds / std::max(step_s, 1e-9)));
     j->heavy = step_s >= kHeavyStepSeconds;
     if (j->heavy) heavy_running++;
@@ -728,8 +749,11 @@ void Server::loop() {
       if (r == 0) {
         refused.push_back(j.get());
       } else if (r == 1) {
+        // a job held back only by the long-step cap is overtaken by other
+        // long-step jobs, not by the short ones that use the slots left to them
         if (j->running)
-          for (Job* q : refused) ++q->overtaken;
+          for (Job* q : refused)
+            if (!q->capped || j->heavy) ++q->overtaken;
         dequeue(j->id);
       }
     }

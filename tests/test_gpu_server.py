@@ -259,3 +259,29 @@ def test_long_job_fed_in_chunks_matches_standalone():
         assert r["status"] == 0, (job, r)
         a0, b0, n0 = _standalone(job, r["engine"])
         assert np.array_equal(n, n0) and np.array_equal(a, a0) and np.array_equal(b, b0), job
+
+
+def test_long_step_jobs_leave_slots_to_short_ones():
+    """With max_active = 3, jobs with long steps (the icosidodecahedron H_g
+    block, about 2 ms of estimated device time per step) take at most one
+    slot: the second one starts only after the first has ended, while short
+    jobs submitted behind both run meanwhile.  Every result equals the same
+    run alone, bit for bit."""
+    _enums()
+    log("[server] slots for short jobs")
+    long_jobs = [("icosidodecahedron", 0, 8, 0, 8, 200, 41 + k, "f32", "gau") for k in range(2)]
+    short = [("icosahedron", 0, 8, 1, 4, 40, 50 + k, "f64", "rad") for k in range(30)]
+    srv = P.Server(16 << 30, max_active=3)
+    ids = [_submit(srv, j) for j in long_jobs] + [_submit(srv, j) for j in short]
+    res = [srv.wait(i) for i in ids]
+    srv.close()
+    (r0, *_), (r1, *_) = res[0], res[1]
+    assert r0["status"] == 0 and r1["status"] == 0
+    assert r1["start_s"] >= r0["end_s"], (r0, r1)
+    during = sum(r[0]["start_s"] < r0["end_s"] for r in res[2:])
+    log(f"  short jobs started while the first long job ran: {during} of {len(short)}")
+    assert during >= 1
+    for job, (r, a, b, n) in zip(long_jobs + short, res):
+        assert r["status"] == 0, (job, r)
+        a0, b0, n0 = _standalone(job, r["engine"])
+        assert np.array_equal(n, n0) and np.array_equal(a, a0) and np.array_equal(b, b0), job
