@@ -105,6 +105,11 @@ def test_campaign_with_realified_pairs_matches_oracle_ftlm(name, two_s):
         for k in range(len(info["dims"])):
             ir = irreps.Irrep(int(info["dims"][k]), LG.rho(k), None, int(info["indicators"][k]))
             ir.chars = np.trace(ir.rho, axis1=1, axis2=2).astype(complex)
+            # the library's matrices enter the oracle only as a choice of basis: checked
+            # first to be a real orthogonal representation of the oracle's group (with the
+            # character of one of the oracle's real forms, inside oracle_weight below)
+            assert np.max(np.abs(np.einsum("gij,hjk->ghik", ir.rho, ir.rho) - ir.rho[G.mul])) < 1e-12
+            assert np.max(np.abs(np.einsum("gji,gjk->gik", ir.rho, ir.rho) - np.eye(ir.dim))) < 1e-12
             B = basis.build_block(G, ir, sec)
             if B.D == 0:
                 continue
