@@ -370,14 +370,14 @@ __device__ __forceinline__ void hv_pass(const HvArgs<T>& a, const HvTabs& tb,
           }
         }
       };
-      // With several vectors per lane and a flip's rows in few registers
-      // (DG x VPL <= 12) the gathers of two flips are in flight together,
-      // which doubles the random requests a lane group keeps outstanding;
-      // the terms are still added in flip order, so the result is the same
-      // bit for bit.  (Measured: the ten-block icosidodecahedron job 1.49 s
-      // against 1.53 s; with one vector per lane no gain, and the
-      // single-vector FP64 H.V 14% slower.)
-      constexpr bool kTwo = VPL > 1 && DG * VPL <= 12;
+      // With several vectors per lane and a flip's rows in at most 12
+      // registers (48 bytes) the gathers of two flips are in flight
+      // together, which doubles the random requests a lane group keeps
+      // outstanding; the terms are still added in flip order, so the result
+      // is the same bit for bit.  (Measured: the ten-block icosidodecahedron
+      // job 1.48 s against 1.53 s; with more registers per flip, one vector
+      // per lane or FP64 rows of 3 x 3 doubles it was slower.)
+      constexpr bool kTwo = VPL > 1 && DG * VPL * sizeof(T) <= 48;
 #pragma unroll 1
       for (int jj = 0; jj < cnt; jj += (kTwo ? 2 : 1)) {
         const uint64_t ent0 = shfl64(my, gbase + jj);
