@@ -288,8 +288,6 @@ void hv_setup(const Block& b, int nvec, int64_t ld, int gl, const VecLayout& vl,
   uint64_t o = base;
   const uint32_t o_rho = (uint32_t)o;
   o = align16(o + (uint64_t)s.G->order * DG * DG * 8);
-  const uint32_t o_V = (uint32_t)o;
-  o = align16(o + ns * DG * DG * 8);
   const uint32_t o_stab = (uint32_t)o;
   o = align16(o + ns * 4 * 8);
   const uint32_t o_J = (uint32_t)o;
@@ -298,8 +296,14 @@ void hv_setup(const Block& b, int nvec, int64_t ld, int gl, const VecLayout& vl,
   o = align16(o + (uint64_t)(2 * s.d * s.d) * 8);
   const uint32_t o_bonds = (uint32_t)o;
   o = align16(o + (uint64_t)s.nbonds * 2 * 4);
+  // V_S last: with many stabilizer types it may not fit next to rho; it is
+  // then read through the caches (it serves only targets and outputs with a
+  // non-trivial stabilizer) while rho and the rest stay in LDS
+  const uint32_t o_V = (uint32_t)o;
+  const uint64_t o_end = align16(o + ns * DG * DG * 8);
   c.slds = (o - base) <= kSmallLdsBudget && o <= kLdsLimit;
-  c.shm = c.slds ? o : base;
+  const bool v_lds = c.slds && (o_end - base) <= kSmallLdsBudget && o_end <= kLdsLimit;
+  c.shm = c.slds ? (v_lds ? o_end : o) : base;
   {
     a.reps = s.d_reps.p;
     a.row_ptr = s.d_row_ptr.p;
@@ -341,6 +345,7 @@ void hv_setup(const Block& b, int nvec, int64_t ld, int gl, const VecLayout& vl,
     a.zero = 0;
     a.o_rho = o_rho;
     a.o_V = o_V;
+    a.v_lds = v_lds ? 1 : 0;
     a.o_stab = o_stab;
     a.o_J = o_J;
     a.o_fac = o_fac;

@@ -90,6 +90,7 @@ struct HvArgs {
   int zero;  // always 0 (see the non-trivial stabilizer branch)
   // dynamic LDS layout (byte offsets): [perm table][rho^T][V][stab][J][fac][bonds]
   uint32_t o_rho, o_V, o_stab, o_J, o_fac, o_bonds;
+  int v_lds;  // V_S staged in LDS too (else read from V)
   // on-the-fly search
   const void* tab;
   const uint64_t* cnt;
@@ -464,7 +465,7 @@ k_hv(HvArgs<T> a) {
   const int32_t* bonds = a.bonds;
   if constexpr (SLDS) {
     rhoT = stage<double>(a.rhoT, (uint32_t)a.G * DG * DG, sm + a.o_rho);
-    Vt = stage<double>(a.V, (uint32_t)a.n_stab * DG * DG, sm + a.o_V);
+    Vt = a.v_lds ? stage<double>(a.V, (uint32_t)a.n_stab * DG * DG, sm + a.o_V) : a.V;
     stabf = stage<double>(a.stabf, (uint32_t)a.n_stab * 4, sm + a.o_stab);
     Jb = stage<double>(a.J, (uint32_t)a.nbonds, sm + a.o_J);
     fac = stage<double>(a.fac, (uint32_t)(2 * a.dloc * a.dloc), sm + a.o_fac);

@@ -200,3 +200,42 @@ def test_block_errors():
     with pytest.raises(P.FtlmError) as e:
         P.Sector(clusters.Cluster("x", 12, broken, cl.gens), G, 0, two_s=1)
     assert e.value.name == "BONDS_NOT_INVARIANT"
+
+
+def test_torus_block_with_stabilizer_matrices_outside_lds():
+    """The 6x6 torus at 2M = 24 has 133 stabilizer types.  With a
+    4-dimensional irrep of its order-288 group, rho^T (37 KiB) and the small
+    tables are staged in LDS while the V_S matrices (17 KiB more) are read
+    through the caches.  Sampled output rows, half of them of representatives
+    with a non-trivial stabilizer, against the oracle's row-by-row evaluation
+    (FP64, 3 vectors, label-keyed input)."""
+    from synth.vectors import label_keyed_values
+    name, two_M, nvec, seed = "square6x6", 24, 3, 0x5EED0031
+    cl, G, irs = oracle_group(name)
+    gi = next(k for k, ir in enumerate(irs) if ir.dim == 4)
+    S = lib_sector(name, 1, two_M)
+    log(f"[parity] {name} 2M={two_M} irrep {gi} (d=4): {S.n_reps} reps, {S.n_stab} stabilizer types")
+    assert S.n_stab * 16 * 8 + 288 * 16 * 8 > 48 * 1024          # V_S does not fit next to rho^T
+    B = P.Block(S, gi, 0, user_rho=irs[gi].rho)
+    ex = B.export()
+    reps, counts, offs = ex["reps"], ex["n_gamma"].astype(np.int64), ex["offsets"].astype(np.int64)
+    _, sid, ssz = S.export()
+    X = np.zeros((B.D, nvec))
+    vv = np.arange(nvec, dtype=np.uint64)[None, :]
+    for i in np.nonzero(counts)[0]:
+        X[offs[i]:offs[i] + counts[i]] = label_keyed_values(seed, reps[i], np.arange(counts[i], dtype=np.uint64)[:, None], vv)
+    Y = B.apply_H(torch.from_numpy(X).cuda()).cpu().numpy()
+    rng = np.random.default_rng(31)
+    active = np.nonzero(counts)[0]
+    nontriv = active[ssz[sid[active]] > 1]
+    assert len(nontriv) >= 6
+    pick = np.concatenate([rng.choice(active, 6, replace=False), rng.choice(nontriv, 6, replace=False)])
+
+    def xfun(rlab, n):
+        return label_keyed_values(seed, np.uint64(rlab), np.arange(n, dtype=np.uint64)[:, None], vv)
+
+    rows = hv.sampled_rows(G, irs[gi], 0, cl.N, 1, cl.bonds, cl.J, reps[pick].astype(np.int64), xfun, nvec)
+    scale = max(np.abs(y).max() for y in rows)
+    for i, yref in zip(pick, rows):
+        got = Y[offs[i]:offs[i] + counts[i]]
+        assert np.max(np.abs(got - yref)) <= 1e-12 * scale, (i, np.max(np.abs(got - yref)) / scale)
