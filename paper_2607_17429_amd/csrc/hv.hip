@@ -288,6 +288,8 @@ void hv_setup(const Block& b, int nvec, int64_t ld, int gl, const VecLayout& vl,
   uint64_t o = base;
   const uint32_t o_rho = (uint32_t)o;
   o = align16(o + (uint64_t)s.G->order * DG * DG * 8);
+  const uint32_t o_V = (uint32_t)o;
+  o = align16(o + ns * DG * DG * 8);
   const uint32_t o_stab = (uint32_t)o;
   o = align16(o + ns * 4 * 8);
   const uint32_t o_J = (uint32_t)o;
@@ -296,14 +298,28 @@ void hv_setup(const Block& b, int nvec, int64_t ld, int gl, const VecLayout& vl,
   o = align16(o + (uint64_t)(2 * s.d * s.d) * 8);
   const uint32_t o_bonds = (uint32_t)o;
   o = align16(o + (uint64_t)s.nbonds * 2 * 4);
-  // V_S last: with many stabilizer types it may not fit next to rho; it is
-  // then read through the caches (it serves only targets and outputs with a
-  // non-trivial stabilizer) while rho and the rest stay in LDS
-  const uint32_t o_V = (uint32_t)o;
-  const uint64_t o_end = align16(o + ns * DG * DG * 8);
   c.slds = (o - base) <= kSmallLdsBudget && o <= kLdsLimit;
-  const bool v_lds = c.slds && (o_end - base) <= kSmallLdsBudget && o_end <= kLdsLimit;
-  c.shm = c.slds ? (v_lds ? o_end : o) : base;
+  c.shm = c.slds ? o : base;
+  c.vg = false;
+  uint32_t vg_stab = 0, vg_J = 0, vg_fac = 0, vg_bonds = 0;
+  if (!c.slds && !otf) {
+    // the kernels without V_S in LDS (VG): rho^T and the small tables only;
+    // V_S, used only for non-trivial stabilizers, is read through the caches
+    // (a 6x6-torus sector has up to 324 stabilizer types)
+    uint64_t v = align16(base + (uint64_t)s.G->order * DG * DG * 8);
+    vg_stab = (uint32_t)v;
+    v = align16(v + ns * 4 * 8);
+    vg_J = (uint32_t)v;
+    v = align16(v + (uint64_t)s.nbonds * 8);
+    vg_fac = (uint32_t)v;
+    v = align16(v + (uint64_t)(2 * s.d * s.d) * 8);
+    vg_bonds = (uint32_t)v;
+    v = align16(v + (uint64_t)s.nbonds * 2 * 4);
+    if ((v - base) <= kSmallLdsBudget && v <= kLdsLimit) {
+      c.slds = c.vg = true;
+      c.shm = v;
+    }
+  }
   {
     a.reps = s.d_reps.p;
     a.row_ptr = s.d_row_ptr.p;
@@ -344,12 +360,11 @@ void hv_setup(const Block& b, int nvec, int64_t ld, int gl, const VecLayout& vl,
     a.tile_w = L.tile_w;
     a.zero = 0;
     a.o_rho = o_rho;
-    a.o_V = o_V;
-    a.v_lds = v_lds ? 1 : 0;
-    a.o_stab = o_stab;
-    a.o_J = o_J;
-    a.o_fac = o_fac;
-    a.o_bonds = o_bonds;
+    a.o_V = c.vg ? 0 : o_V;
+    a.o_stab = c.vg ? vg_stab : o_stab;
+    a.o_J = c.vg ? vg_J : o_J;
+    a.o_fac = c.vg ? vg_fac : o_fac;
+    a.o_bonds = c.vg ? vg_bonds : o_bonds;
     a.tab = s.d_tab.p;
     a.cnt = s.d_cnt.p;
     a.rank_bits = s.d_rank_bits.p;

@@ -21,7 +21,10 @@
 // dependent loads (flip -> target metadata -> X rows): a chunk of GL flips is
 // fetched with one load per lane and exchanged by lane shuffles, then each
 // flip's n_r rows of X[r] are gathered for all VPL vectors.  rho^T, V_S, the
-// stabilizer data and the bond coefficients sit in LDS when they fit.
+// stabilizer data and the bond coefficients sit in LDS when they fit; when
+// only V_S does not (many stabilizer types), the dense-gather kernels keep
+// the others in LDS and read V_S, needed only for non-trivial stabilizers,
+// through the caches (VG; table-driven H.V only).
 // Arithmetic is FP64; FP32 and FP16 storage round once on the store.
 //
 // Flips come from the sector's entry table (target index, h, flip id; built
@@ -90,7 +93,6 @@ struct HvArgs {
   int zero;  // always 0 (see the non-trivial stabilizer branch)
   // dynamic LDS layout (byte offsets): [perm table][rho^T][V][stab][J][fac][bonds]
   uint32_t o_rho, o_V, o_stab, o_J, o_fac, o_bonds;
-  int v_lds;  // V_S staged in LDS too (else read from V)
   // on-the-fly search
   const void* tab;
   const uint64_t* cnt;
@@ -113,6 +115,7 @@ struct LaunchCfg {
   size_t shm;
   bool otf, lds_tab, slds, wide;
   bool contig;  // the dense gather holds: adjacent columns per lane
+  bool vg;      // all small tables but V_S in LDS (table-driven H.V)
   int nch, vpl;
 };
 
@@ -446,7 +449,8 @@ __device__ __forceinline__ void hv_pass(const HvArgs<T>& a, const HvTabs& tb,
   }
 }
 
-template <typename T, int DG, int VPL, bool OTF, int NCH, bool LDS_TAB, bool SLDS, bool CONTIG = false>
+template <typename T, int DG, int VPL, bool OTF, int NCH, bool LDS_TAB, bool SLDS, bool CONTIG = false,
+          bool VG = false>
 __global__ void __launch_bounds__(kThreads)
 __attribute__((amdgpu_waves_per_eu(DG * VPL <= FTLM_HV_FLOOR_WIDTH ? FTLM_HV_WAVES_PER_EU : 1)))
 k_hv(HvArgs<T> a) {
@@ -465,7 +469,7 @@ k_hv(HvArgs<T> a) {
   const int32_t* bonds = a.bonds;
   if constexpr (SLDS) {
     rhoT = stage<double>(a.rhoT, (uint32_t)a.G * DG * DG, sm + a.o_rho);
-    Vt = a.v_lds ? stage<double>(a.V, (uint32_t)a.n_stab * DG * DG, sm + a.o_V) : a.V;
+    if constexpr (!VG) Vt = stage<double>(a.V, (uint32_t)a.n_stab * DG * DG, sm + a.o_V);
     stabf = stage<double>(a.stabf, (uint32_t)a.n_stab * 4, sm + a.o_stab);
     Jb = stage<double>(a.J, (uint32_t)a.nbonds, sm + a.o_J);
     fac = stage<double>(a.fac, (uint32_t)(2 * a.dloc * a.dloc), sm + a.o_fac);
@@ -507,7 +511,16 @@ void launch_k(const HvArgs<T>& a, const LaunchCfg& c, hipStream_t st) {
   // bucket 8 or 12 needs d_Gamma exactly 8 or 12; it takes the default layout)
   if constexpr (!OTF && DG <= 6) {
     if (c.slds && c.contig) {
-      hipLaunchKernelGGL((k_hv<T, DG, VPL, OTF, NCH, LDS_TAB, true, true>), c.grid, dim3(kThreads), c.shm, st, a);
+      if (c.vg)
+        hipLaunchKernelGGL((k_hv<T, DG, VPL, OTF, NCH, LDS_TAB, true, true, true>), c.grid, dim3(kThreads), c.shm, st, a);
+      else
+        hipLaunchKernelGGL((k_hv<T, DG, VPL, OTF, NCH, LDS_TAB, true, true>), c.grid, dim3(kThreads), c.shm, st, a);
+      return;
+    }
+  }
+  if constexpr (!OTF) {
+    if (c.slds && c.vg) {
+      hipLaunchKernelGGL((k_hv<T, DG, VPL, OTF, NCH, LDS_TAB, true, false, true>), c.grid, dim3(kThreads), c.shm, st, a);
       return;
     }
   }

@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(kWgThreads<DG>) k_lanczos_wg(const WgJob<T>* _
   const int t = threadIdx.x;
 
   const HvTabs tb{stage<double>(a.rhoT, (uint32_t)a.G * DG * DG, sm + a.o_rho),
-                  a.v_lds ? stage<double>(a.V, (uint32_t)a.n_stab * DG * DG, sm + a.o_V) : a.V,
+                  stage<double>(a.V, (uint32_t)a.n_stab * DG * DG, sm + a.o_V),
                   stage<double>(a.stabf, (uint32_t)a.n_stab * 4, sm + a.o_stab),
                   stage<double>(a.J, (uint32_t)a.nbonds, sm + a.o_J),
                   stage<double>(a.fac, (uint32_t)(2 * a.dloc * a.dloc), sm + a.o_fac),

@@ -60,7 +60,7 @@ bool wg_supported(const Block& b, int R, int storage) {
   LaunchCfg c{};
   HvArgs<double> a{};
   hv_setup(b, R, R, wg_lanes(R), VecLayout{}, nullptr, c, a);
-  return c.slds && a.tile_w >= R && c.vpl <= 4;
+  return c.slds && !c.vg && a.tile_w >= R && c.vpl <= 4;
 }
 
 uint64_t wg_rounds(uint64_t n_reps, int R) {

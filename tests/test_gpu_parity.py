@@ -206,11 +206,13 @@ def test_torus_block_with_stabilizer_matrices_outside_lds():
     """The 6x6 torus at 2M = 24 has 133 stabilizer types.  With a
     4-dimensional irrep of its order-288 group, rho^T (37 KiB) and the small
     tables are staged in LDS while the V_S matrices (17 KiB more) are read
-    through the caches.  Sampled output rows, half of them of representatives
-    with a non-trivial stabilizer, against the oracle's row-by-row evaluation
-    (FP64, 3 vectors, label-keyed input)."""
+    through the caches, in the block-row kernel and in the dense-gather
+    kernel of padded rows alike.  Sampled output rows, half of them of
+    representatives with a non-trivial stabilizer, against the oracle's
+    row-by-row evaluation (FP64, 24 vectors, label-keyed input); the padded
+    launch against the block-row one."""
     from synth.vectors import label_keyed_values
-    name, two_M, nvec, seed = "square6x6", 24, 3, 0x5EED0031
+    name, two_M, nvec, seed = "square6x6", 24, 24, 0x5EED0031
     cl, G, irs = oracle_group(name)
     gi = next(k for k, ir in enumerate(irs) if ir.dim == 4)
     S = lib_sector(name, 1, two_M)
@@ -221,10 +223,18 @@ def test_torus_block_with_stabilizer_matrices_outside_lds():
     reps, counts, offs = ex["reps"], ex["n_gamma"].astype(np.int64), ex["offsets"].astype(np.int64)
     _, sid, ssz = S.export()
     X = np.zeros((B.D, nvec))
+    Xp = np.zeros((len(reps) * 4, nvec))
     vv = np.arange(nvec, dtype=np.uint64)[None, :]
     for i in np.nonzero(counts)[0]:
-        X[offs[i]:offs[i] + counts[i]] = label_keyed_values(seed, reps[i], np.arange(counts[i], dtype=np.uint64)[:, None], vv)
+        vals = label_keyed_values(seed, reps[i], np.arange(counts[i], dtype=np.uint64)[:, None], vv)
+        X[offs[i]:offs[i] + counts[i]] = vals
+        Xp[4 * i:4 * i + counts[i]] = vals
     Y = B.apply_H(torch.from_numpy(X).cuda()).cpu().numpy()
+    Yp, info = B.apply_H_ex(torch.from_numpy(Xp).cuda(), layout=P.LAYOUT_PADDED)
+    assert info["adjacent_columns"] == 1
+    Yp = Yp.cpu().numpy()
+    Yu = np.concatenate([Yp[4 * i:4 * i + counts[i]] for i in np.nonzero(counts)[0]])
+    assert rel_err_cols(Yu, Y) <= 1e-12
     rng = np.random.default_rng(31)
     active = np.nonzero(counts)[0]
     nontriv = active[ssz[sid[active]] > 1]
