@@ -1,0 +1,37 @@
+"""The C ABI used from plain C (no Python binding, no GPU): a program built
+with gcc against include/ftlm.h and libftlm.so calls the host-side entry
+points (group and irreps, Ritz data, thermal sums, errors); its results are
+checked against closed forms."""
+import math
+import os
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PKG = os.path.join(ROOT, "paper_2607_17429_amd")
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="gcc not installed")
+def test_host_entry_points_from_c(tmp_path):
+    if not os.path.exists(os.path.join(PKG, "libftlm.so")):
+        pytest.fail("libftlm.so is not built (run the package build first)")
+    exe = str(tmp_path / "abi_host")
+    subprocess.run(["gcc", "-O1", "-std=c99", "-I" + os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "c", "abi_host.c"), "-o", exe, "-L" + PKG, "-lftlm", "-lm",
+                    "-Wl,-rpath," + PKG, "-Wl,-rpath,/opt/rocm/lib"], check=True, timeout=120)
+    out = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stdout + out.stderr
+    v = dict(line.split(" ", 1) for line in out.stdout.strip().splitlines())
+    assert int(v["order"]) == 12 and int(v["irreps"]) == 6 and int(v["classes"]) == 6
+    assert int(v["sum_dim_sq"]) == 12 and int(v["residual_small"]) == 1
+    assert abs(float(v["theta0"]) - (3 - math.sqrt(5)) / 2) < 1e-14
+    assert abs(float(v["theta1"]) - (3 + math.sqrt(5)) / 2) < 1e-14
+    assert abs(float(v["weight_sum"]) - 1.0) < 1e-14
+    z = 1 + math.exp(-1.0)
+    e = math.exp(-1.0) / z
+    assert abs(float(v["E"]) - e) < 1e-14
+    assert abs(float(v["C"]) - (e - e * e)) < 1e-14          # <H^2> - <H>^2 at T = 1
+    assert abs(float(v["logZ"]) - math.log(z)) < 1e-14
+    assert int(v["bad_rc_nonzero"]) == 1 and int(v["bad_msg_nonempty"]) == 1
