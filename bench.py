@@ -554,13 +554,16 @@ def main():
         workload (cached process-wide; untimed)."""
         G0 = P.Group(cl.N, cl.gens)
         S0 = P.Sector(cl, G0, wl["two_M"], two_s=wl["two_s"], spin_flip=wl.get("flip", False))
-        dims = G0.irreps()["dims"]
         irreps = list(range(G0.n_irreps)) if wl["irrep"] == "all" else [wl["irrep"]]
+        # with spin flip the irrep index counts the irreps of G x Z2, so the
+        # dimension buckets of G do not apply: tune every listed block
+        dims = None if wl.get("flip") else G0.irreps()["dims"]
         seen, out = set(), None
         for gi in irreps:
-            if dims[gi] in seen and gi != rirrep:
-                continue
-            seen.add(dims[gi])
+            if dims is not None:
+                if dims[gi] in seen and gi != rirrep:
+                    continue
+                seen.add(dims[gi])
             B0 = P.Block(S0, gi, 0, layout=layout)
             if B0.D == 0:
                 continue
