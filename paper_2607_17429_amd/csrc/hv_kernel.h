@@ -375,13 +375,15 @@ __device__ __forceinline__ void hv_pass(const HvArgs<T>& a, const HvTabs& tb,
         }
       };
       // With several vectors per lane and a flip's rows in at most 12
-      // registers (48 bytes) the gathers of two flips are in flight
+      // elements and 48 bytes the gathers of two flips are in flight
       // together, which doubles the random requests a lane group keeps
       // outstanding; the terms are still added in flip order, so the result
       // is the same bit for bit.  (Measured: the ten-block icosidodecahedron
       // job 1.48 s against 1.53 s; with more registers per flip, one vector
-      // per lane or FP64 rows of 3 x 3 doubles it was slower.)
-      constexpr bool kTwo = VPL > 1 && DG * VPL * sizeof(T) <= 48;
+      // per lane or FP64 rows of 3 x 3 doubles it was slower, and FP16 rows
+      // of 15 elements took 4.0 ms per icosidodecahedron H_g launch against
+      // 3.5 ms with one flip at a time.)
+      constexpr bool kTwo = VPL > 1 && DG * VPL <= 12 && DG * VPL * sizeof(T) <= 48;
 #pragma unroll 1
       for (int jj = 0; jj < cnt; jj += (kTwo ? 2 : 1)) {
         const uint64_t ent0 = shfl64(my, gbase + jj);
