@@ -35,3 +35,29 @@ def test_byte_model_block_and_padded_rows():
     # instead of the 8-byte metadata word; the epilogue reads q_{j-1} too
     padded = gathered + entries + 2 * (3 + 2) + 3 * D * nvec * b + per_rep
     assert bench.algorithmic_bytes(st, D, n_reps, nvec, b, pad=True, epilogue=True) == padded
+
+
+def test_workload_irreps_exist_and_match_their_descriptions():
+    # every single-sector workload names an irrep of G (or of G x Z2 when it
+    # resolves the spin flip, index 2i + q for irrep i of G and parity q) and
+    # its roofline irrep; H blocks of I_h have dimension 5
+    from oracle import group as ogroup
+    from oracle import irreps as oirreps
+    from oracle import spinflip
+    from synth import clusters
+
+    for name, wl in bench.WORKLOADS.items():
+        if wl.get("campaign"):
+            continue
+        cl = clusters.get(wl["cluster"])
+        irs = oirreps.compute_irreps(ogroup.close(cl.gens, cl.N))
+        n = 2 * len(irs) if wl.get("flip") else len(irs)
+        gi = bench.roofline_irrep(wl)
+        assert 0 <= gi < n, name
+        if wl["irrep"] != "all":
+            assert wl["irrep"] == gi, name
+        base = irs[gi // 2] if wl.get("flip") else irs[gi]
+        if wl.get("flip"):
+            assert spinflip.flip_irreps(irs)[gi].dim == base.dim, name
+        if "H_g" in wl["desc"] or gi == 8:
+            assert base.dim == 5, name
