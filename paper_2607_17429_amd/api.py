@@ -411,10 +411,6 @@ def observables(blocks, T, g=1.0):
     return E, Cv, chi, lz
 
 
-__all__ = ["Group", "Sector", "Block", "tridiag_ritz", "ritz_from_run", "observables", "FtlmError",
-           "F32", "F64", "RADEMACHER", "GAUSSIAN", "HV_AUTO", "HV_ENTRIES", "HV_ONTHEFLY"]
-
-
 def campaign(cluster, gens, two_s, R, steps, seed, T, storage=F64, dist=RADEMACHER, all_M=True, two_M=0,
              spin_flip=False, chains_per_run=0, g=1.0, engine=0, fused_max_rounds=0):
     """Whole-cluster FTLM (ftlm_campaign): E, C, chi, logZ on T and the run statistics.
@@ -434,3 +430,8 @@ def campaign(cluster, gens, two_s, R, steps, seed, T, storage=F64, dist=RADEMACH
                               C.byref(st)))
     E, Cv, chi, logZ = out
     return dict(E=E, C=Cv, chi=chi, logZ=logZ, stats={f: getattr(st, f) for f, _ in L.CampaignStats._fields_})
+
+
+__all__ = ["Group", "Sector", "Block", "LanczosRunState", "run_fused", "campaign", "tridiag_ritz", "ritz_from_run",
+           "observables", "kpm_observables", "device_arch", "autotune_save", "autotune_load", "autotune_clear",
+           "FtlmError", "F32", "F64", "RADEMACHER", "GAUSSIAN", "HV_AUTO", "HV_ENTRIES", "HV_ONTHEFLY"]
