@@ -449,6 +449,9 @@ def main():
                     help="campaign workloads: Lanczos engine (fused small-block kernel, per-step kernels, or automatic)")
     ap.add_argument("--profile-hv", action="store_true",
                     help="counter run: one 1 GiB copy (calibration) and 5 H.V launches, then exit")
+    ap.add_argument("--hv-blocks", action="store_true",
+                    help="in-run H.V of every block of the workload (20 Lanczos steps each, HIP events, byte model): "
+                         "one JSON line per block, then exit")
     ap.add_argument("--serve", action="store_true", help="run the job-server benchmark (serving mix) instead")
     ap.add_argument("--serve-jobs", type=int, default=100, help="jobs of the closed burst (capacity)")
     ap.add_argument("--serve-warm", type=int, default=40)
@@ -593,6 +596,30 @@ def main():
                           "algorithmic_bytes_per_launch": algorithmic_bytes(st, B0.D, S0.n_reps, wl["R"], elem,
                                                                             pad=pad, epilogue=True),
                           "stats": st}), flush=True)
+        return
+
+    if args.hv_blocks:
+        # every block of the workload: lanes from the autotuner, then the
+        # H.V launches of a 20-step run timed on the run's stream
+        G1 = P.Group(cl.N, cl.gens)
+        S1 = P.Sector(cl, G1, wl["two_M"], two_s=wl["two_s"], spin_flip=wl.get("flip", False))
+        n_ir = 2 * G1.n_irreps if wl.get("flip") else G1.n_irreps
+        elem = {P.F64: 8, P.F32: 4, P.F16: 2}[storage]
+        for gi in (range(n_ir) if wl["irrep"] == "all" else [wl["irrep"]]):
+            B1 = P.Block(S1, gi, 0, layout=layout)
+            if B1.D == 0:
+                continue
+            t = B1.autotune(wl["R"], storage, stream=stream)
+            _, _, _, info = B1.ftlm(wl["R"], 20, 0x5EED0003, storage=storage, dist=dist, stream=stream, info=True)
+            torch.cuda.synchronize()
+            ms = info["hv_ms"] / max(info["hv_launches"], 1)
+            ab = algorithmic_bytes(B1.hv_stats(), B1.D, S1.n_reps, wl["R"], elem,
+                                   pad=info["layout"] != P.LAYOUT_BLOCK, epilogue=True)
+            print(json.dumps({"irrep": gi, "d_gamma": B1.d_gamma, "D": B1.D, "lanes_per_rep": t[0],
+                              "layout": LAYOUT_NAMES[info["layout"]], "avg_launch_ms": ms,
+                              "algorithmic_bytes_per_launch": ab, "achieved_GBs": ab / ms / 1e6,
+                              "frac": ab / ms / 1e6 / PEAK_HBM_GBS}), flush=True)
+            del B1
         return
 
     tuned, S0, G0 = tune_all()
