@@ -165,10 +165,12 @@ typedef struct ftlm_block ftlm_block;
  * d / 2 = dim / 4.  This replaces the paper's complex-arithmetic path.
  * Irreps are computed for |G| <= 1024. */
 int ftlm_group_create(int32_t N, const int32_t* gens, int32_t ngens, ftlm_group** out);
-/* |G|, number of irreps, number of conjugacy classes, number of sites. */
+/* |G|, number of irreps, number of conjugacy classes, number of sites (the
+ * group and its irreps generated and verified as Section 3 describes). */
 int ftlm_group_info(const ftlm_group* g, int32_t* order, int32_t* n_irreps, int32_t* n_classes,
                     int32_t* N);
-/* Permutation table, |G| x N int32 (host array owned by the caller). */
+/* Permutation table, |G| x N int32 (host array owned by the caller): the
+ * site-permutation table through which the group enters (Section 3). */
 int ftlm_group_elements(const ftlm_group* g, int32_t* perms);
 /* Per irrep: dimension, Frobenius-Schur indicator (0 marks a realified
  * complex pair, -1 a realified quaternionic irrep, +1 a real-type irrep),
@@ -180,13 +182,14 @@ int ftlm_group_elements(const ftlm_group* g, int32_t* perms);
  * largest verification residual. */
 int ftlm_group_irreps(const ftlm_group* g, int32_t* dims, int32_t* indicators, int32_t* weights,
                       double* chars, int32_t* class_of, double* max_residual);
-/* Irrep matrices rho(g), |G| x d x d row-major. */
+/* Irrep matrices rho(g), |G| x d x d row-major (host array owned by the
+ * caller): the rho_Gamma(g) of Eqs. (10) and (15), in real orthogonal form. */
 int ftlm_group_rho(const ftlm_group* g, int32_t irrep, double* rho);
 void ftlm_group_free(ftlm_group* g);
 
 /* --------------------------------------------------------------- sector ---
  * Irreducible-representation-independent part of one magnetization sector
- * (Section 3, "performed only once per magnetization sector"): all orbit
+ * (Section 3: built once per magnetization sector, shared by its irreps): all orbit
  * representatives of the M = two_M/2 sector (ascending), their stabilizers,
  * the rank lookup (sector rank of Ref. [36] + a bitmap over ranks), the
  * diagonal energies of Eq. (16) and, in entry mode, the table of one entry
@@ -230,8 +233,8 @@ void ftlm_sector_free(ftlm_sector* s);
  * not a unitary homomorphism), OUT_OF_MEMORY, HIP.  D = 0 is legal. */
 int ftlm_block_create(ftlm_sector* s, int32_t irrep, int32_t row, const ftlm_opts* opts,
                       ftlm_block** out);
-/* One call: group + sector + block (the block owns the private group and
- * sector).  gens: ngens x N int32. */
+/* One call: group + sector + block of Eqs. (8)-(13) (the block owns the
+ * private group and sector).  gens: ngens x N int32. */
 int ftlm_build_block(const ftlm_cluster* cl, const int32_t* gens, int32_t ngens, int32_t two_M,
                      int32_t irrep, int32_t row, const ftlm_opts* opts, ftlm_block** out);
 
@@ -275,7 +278,8 @@ typedef struct ftlm_hv_stats {
 } ftlm_hv_stats;
 int ftlm_block_hv_stats(const ftlm_block* b, ftlm_hv_stats* stats);
 
-/* Y = H X for nvec columns of D x ld device arrays of dtype (F64 or F32;
+/* Y = H X (the block matrix of Eq. 15 in gather form, diagonal of Eq. 16)
+ * for nvec columns of D x ld device arrays of dtype (F64 or F32;
  * F32 is storage only: products and sums are formed in FP64 and rounded once
  * when Y is stored).  X and Y must not overlap.  Enqueued on stream
  * (asynchronous).  Errors: INVALID_ARG, HIP. */
@@ -317,7 +321,9 @@ typedef struct ftlm_hv_opts {
   int64_t reserved[4];
 } ftlm_hv_opts;
 
-/* ftlm_apply_H with the options above (opts == NULL: exactly ftlm_apply_H).
+/* ftlm_apply_H (Eqs. 15-16) with the options above (opts == NULL: exactly
+ * ftlm_apply_H); the scale/dots epilogue is one three-term Lanczos update
+ * (Section 3) fused into the product.
  * dtype F64, F32 or F16 (storage; FP64 arithmetic).  X and Y must not
  * overlap.  With scale, device scratch of one FP64 partial sum per workgroup
  * and vector is allocated (stream-ordered) for the call.  Enqueued on stream
@@ -392,7 +398,8 @@ typedef struct ftlm_run_info {
   double hv_ms;
 } ftlm_run_info;
 
-/* ftlm_run that also fills *info (may be NULL; then it is ftlm_run).
+/* ftlm_run (Sections 2.2 and 3) that also fills *info (may be NULL; then it
+ * is ftlm_run).
  * Timing adds two event records per step. */
 int ftlm_run_ex(ftlm_block* b, int32_t R, int32_t steps, uint64_t seed, int32_t storage, int32_t dist,
                 double* alpha, double* beta, int32_t* nsteps, void* stream, ftlm_run_info* info);
