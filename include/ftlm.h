@@ -463,8 +463,8 @@ typedef struct ftlm_fused_job {
 int ftlm_run_fused(const ftlm_fused_job* jobs, int32_t n, void* stream);
 
 /* ----------------------------------------------------------------- KPM ---
- * Kernel polynomial method (the spectral-density route to thermodynamic
- * averages that the paper names next to FTLM, its Ref. [6]) on the same
+ * Kernel polynomial method (thermodynamics from a Chebyshev expansion of the
+ * density of states, the alternative to FTLM the paper cites as Ref. [6]) on the same
  * symmetry-adapted H.V: Chebyshev moments mu_n = <r|T_n(H~)|r> / <r|r> of
  * H~ = (H - center) / half_width for R start vectors r (the vectors of
  * ftlm_run's chains 0..R-1: same keys, generator and normalisation), from

@@ -1,8 +1,8 @@
 """Irreducible representations from the regular representation (paper Section 3).
 
-The paper computes every irrep numerically as explicit unitary matrices from
-the regular representation and brings irreps with Frobenius-Schur indicator +1
-to real orthogonal form.  The construction here:
+In the paper each irrep is obtained numerically, as matrices, by decomposing
+the regular representation, and an irrep whose Frobenius-Schur indicator is +1
+is then changed to a real orthogonal basis.  The construction here:
 
 1. Left and right regular representations L(g), R(g) (|G| x |G| permutation
    matrices); every R(g) commutes with every L(h).

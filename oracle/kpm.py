@@ -3,9 +3,9 @@
 TEST INFRASTRUCTURE: part of the CPU oracle; only tests, the smoke check and
 the benchmark's CPU baseline use it.
 
-The paper names the kernel polynomial method (its Ref. [6]) as the
-spectral-density route to thermodynamic averages next to FTLM; the library
-runs it on the same symmetry-adapted H.V.  Definitions used here:
+The kernel polynomial method (the paper's Ref. [6]) obtains thermodynamics
+from a Chebyshev expansion of the density of states, an alternative to FTLM;
+the library runs it on the same symmetry-adapted H.V.  Definitions used here:
 
 * Scaled block Hamiltonian H~ = (H - c) / w, with a centre c and half width w
   that put the block spectrum inside (-1, 1).

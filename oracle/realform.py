@@ -3,8 +3,8 @@
 TEST INFRASTRUCTURE: part of the FP64 CPU oracle; only tests, the smoke
 check and the benchmark's CPU baseline use it.
 
-The paper computes irreps of complex or quaternionic type as unitary matrices
-and keeps a complex-arithmetic path for them (Section 3).  The library keeps
+In the paper, irreps whose indicator is 0 or -1 stay complex unitary
+matrices and run on a path in complex arithmetic (Section 3).  The library keeps
 real arithmetic instead, and this module states what it computes:
 
 * An irrep Gamma of complex type (indicator 0, dimension d) and its conjugate
@@ -58,7 +58,7 @@ def realify(ir: Irrep) -> Irrep:
     """rho_R = [[Re rho, -Im rho], [Im rho, Re rho]] of a complex- or
     quaternionic-type irrep (the indicator is kept: 0 or -1)."""
     if ir.indicator not in (0, -1):
-        raise ValueError("realification is for irreps of complex or quaternionic type")
+        raise ValueError("realification applies to irreps with indicator 0 or -1")
     re, im = ir.rho.real, ir.rho.imag
     rho = np.block([[re, -im], [im, re]])
     chars = np.trace(rho, axis1=1, axis2=2).astype(complex)   # = 2 Re chi

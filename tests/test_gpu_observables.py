@@ -134,14 +134,14 @@ def test_icosidodecahedron_m0_fp32_against_fp64():
 def test_fp16_storage_on_the_papers_validation_case():
     """Section 4.2's validation of half-precision storage: the s=3/2
     icosahedron, every M >= 0 sector and irrep, R = 100 chains of N_L = 100
-    steps, once with FP32 and once with FP16 vector storage from the same
-    start vectors.  What the paper states and this test checks, for T >= 0.1:
+    steps, run twice from the same start vectors: vectors stored in FP32, then
+    in FP16.  What the paper states and this test checks, for T >= 0.1:
     the deviation lies inside the backward-error envelope of rounding the
     stored iterates, an operator perturbation of norm u W (u = 2^-11, W the
     spectral width: |dE| <= u W, |dC| <= u W C / T, |dchi| <= u W chi / T),
-    and it is far below the statistical uncertainty of the trace estimator
+    and it is much smaller than the random-vector error of the trace estimate
     (here at most 1% of the spread between two independent FP32 runs; the
-    paper reports three orders of magnitude).  The paper's own run printed
+    paper gives a ratio of about a thousand).  The paper's own run printed
     |dC| = 8e-5 and |dchi| = 1e-4, one realization; ours are logged next to
     it."""
     log("[observables] s=3/2 icosahedron, FP16 against FP32 storage")
