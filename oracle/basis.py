@@ -1,5 +1,8 @@
 """Symmetry-adapted basis of one (M, Gamma, alpha) block (paper Section 2.3).
 
+TEST INFRASTRUCTURE: part of the FP64 CPU oracle; only tests, the smoke
+check and the benchmark's CPU baseline use it.
+
 Plain-definition steps:
 
 * orbit of n: {U(g) n : g in G}; representative r = the smallest label

@@ -1,5 +1,8 @@
 """Sector and block dimensions by counting (paper Section 2.1, Eq. 13).
 
+TEST INFRASTRUCTURE: part of the FP64 CPU oracle; only tests, the smoke
+check and the benchmark's CPU baseline use it.
+
 * ``sector_dim``: number of labels whose N base-d digits sum to A = Ns + M,
   i.e. the coefficient of x^A in (1 + x + ... + x^(d-1))^N, by the digit-by-
   digit counting recursion.

@@ -1,5 +1,8 @@
 """FTLM stage in FP64 (paper Section 2.2, Eqs. 4-7 and 14; Section 3).
 
+TEST INFRASTRUCTURE: part of the FP64 CPU oracle; only tests, the smoke
+check and the benchmark's CPU baseline use it.
+
 * Start vectors: a counter-based SplitMix64 stream (Steele, Lea and Flood,
   OOPSLA 2014) per chain, keyed by (seed, 2M, irrep, row, chain); Rademacher
   (sign of the top bit) or Gaussian (Box-Muller on two 53-bit uniforms);

@@ -1,5 +1,8 @@
 """Permutation group from site-permutation generators (paper Section 3).
 
+TEST INFRASTRUCTURE: part of the FP64 CPU oracle; only tests, the smoke
+check and the benchmark's CPU baseline use it.
+
 The paper closes user generators into the full group; here the closure is a
 plain breadth-first search over products (not Dimino's algorithm).  Elements
 are sorted lexicographically by their image arrays, so the identity is element

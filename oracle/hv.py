@@ -1,5 +1,8 @@
 """Hamiltonian action in the symmetry-adapted basis, by plain definition.
 
+TEST INFRASTRUCTURE: part of the FP64 CPU oracle; only tests, the smoke
+check and the benchmark's CPU baseline use it.
+
 Y = Psi^H H_M Psi X, with Psi the explicit Eq. (12) basis and H_M the sector
 Hamiltonian of Eqs. (1)-(3).  This never uses the closed-form matrix element
 of Eq. (15); it therefore checks that formula as well as any kernel built on

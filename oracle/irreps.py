@@ -1,5 +1,8 @@
 """Irreducible representations from the regular representation (paper Section 3).
 
+TEST INFRASTRUCTURE: part of the FP64 CPU oracle; only tests, the smoke
+check and the benchmark's CPU baseline use it.
+
 In the paper each irrep is obtained numerically, as matrices, by decomposing
 the regular representation, and an irrep whose Frobenius-Schur indicator is +1
 is then changed to a real orthogonal basis.  The construction here:

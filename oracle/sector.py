@@ -1,5 +1,8 @@
 """M-sector basis and the Heisenberg Hamiltonian (paper Section 2.1, Eqs. 1-3).
 
+TEST INFRASTRUCTURE: part of the FP64 CPU oracle; only tests, the smoke
+check and the benchmark's CPU baseline use it.
+
 Labels follow Eq. (2): n = sum_k a_k d^k with a_k = m_k + s the k-th base-d
 digit (d = 2s + 1).  A sector holds the labels whose digits sum to Ns + M;
 they are returned in ascending label order.  H_M is built entry by entry from

@@ -1,5 +1,8 @@
 """G x Z2 for the M = 0 sector: the global spin flip.
 
+TEST INFRASTRUCTURE: part of the FP64 CPU oracle; only tests, the smoke
+check and the benchmark's CPU baseline use it.
+
 The paper resolves its M = 0 production blocks further by the global spin
 flip (Section 2.3 and the note to Table 2; the 5x8 block of Section 4.3 is one
 flip-parity half).  The flip F sends the digit a_k of every site to
